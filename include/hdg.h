@@ -1,0 +1,273 @@
+/*
+ * hdg.h -- C ABI of libhdg: the element-local hot path of the hybridizable
+ * discontinuous Galerkin (HDG) method for variable-coefficient reaction-diffusion
+ *
+ *     kappa^{-1} q + grad u = 0,   div q + c u = f   in Omega,
+ *     u = u_D on Gamma_D,          -q . nu = g_N . nu on Gamma_N          (eq 1.1)
+ *
+ * on conforming tetrahedral meshes with polynomial degree k (Fu, Gatica, Sayas,
+ * "Matlab tools for HDG in three dimensions").  The hybrid unknown uhat lives on
+ * faces; q and u are eliminated element by element (Section 5) and recovered after
+ * the global solve (Section 6).
+ *
+ * Conventions shared by every call
+ *   - Every call returns hdg_status (HDG_OK = 0).  hdg_last_error() returns a
+ *     thread-local message for the last failing call.  No C++ exception crosses
+ *     the ABI.  Arguments are validated on the host before any launch, so a call
+ *     that fails validation writes nothing.
+ *   - Pointers named d_* are device pointers (HIP device memory of the current
+ *     device), owned by the caller, who keeps them alive for as long as any handle
+ *     refers to them.  Host pointers are named h_*.  Compute calls are
+ *     asynchronous on the caller's stream and allocate no device memory; they are
+ *     safe to capture into a HIP graph unless stated otherwise.  Scratch memory is
+ *     passed in as a workspace whose size the matching *_workspace_size call gives.
+ *   - Indices are 0-based int32 (the paper's are 1-based).  Dense per-element
+ *     arrays are element-major ("[Nelt][...]", the element's entries contiguous).
+ *   - A device fault raised by an earlier asynchronous launch surfaces at the next
+ *     call that synchronises, as HDG_ERR_DEVICE.
+ *   - Handles are not thread-safe; use one per thread.
+ *
+ * Dimensions: d3 = C(k+3,3) (dim P_k(K)), d2 = C(k+2,2) (dim P_k(e)), m = 4 d2,
+ * d3p = C(k+4,3) (dim P_{k+1}(K)); the volume rule has nqd = n^3 points and the
+ * face rule nqd2 = n^2 points, n = k+2 unless chosen otherwise.
+ */
+#ifndef HDG_H
+#define HDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int hdg_status;
+enum {
+  HDG_OK = 0,
+  HDG_ERR_INVALID_ARG = 1,
+  HDG_ERR_UNSUPPORTED_DEGREE = 2,
+  HDG_ERR_MESH_ORIENTATION = 3,   /* element with det B_K <= 0, or inward boundary triangle */
+  HDG_ERR_MESH_NONCONFORMING = 4, /* a face shared by more than two elements               */
+  HDG_ERR_BOUNDARY_UNLISTED = 5,  /* a boundary face in neither list                        */
+  HDG_ERR_BOUNDARY_INVALID = 6,   /* a listed triangle that is not a boundary face, or listed twice */
+  HDG_ERR_TAU_ZERO = 7,           /* tau vanishes on all four faces of an element, or tau < 0 */
+  HDG_ERR_WORKSPACE = 8,          /* workspace pointer null or too small                   */
+  HDG_ERR_DEVICE = 9,             /* a HIP runtime error                                   */
+  HDG_ERR_NOT_CONVERGED = 10,     /* iterative solve stopped before the tolerance          */
+  HDG_ERR_SINGULAR = 11           /* no Dirichlet face and c == 0: constants in the kernel  */
+};
+
+/* Thread-local message describing the last failing call (never NULL). */
+const char* hdg_last_error(void);
+
+/* Largest supported polynomial degree. */
+int hdg_max_degree(void);
+
+/* ------------------------------------------------------------------------------
+ * Mesh (Section 2, "Data structure").
+ *
+ * Basic form (input of hdg_mesh_expand):
+ *   d_coords    double [nver][3]        vertex coordinates
+ *   d_elements  int32  [nelt][4]        vertex numbers, positively oriented
+ *   d_dirichlet int32  [ndir][3]        Dirichlet triangles, outward orientation
+ *   d_neumann   int32  [nneu][3]        Neumann triangles, outward orientation
+ * Expanded form (outputs of hdg_mesh_expand, sized by hdg_mesh_sizes):
+ *   d_faces     int32  [nfc][3]  vertex numbers; the order fixes the face's own
+ *                                parametrisation phi_e (Section 2).  Faces are
+ *                                numbered by ascending sorted vertex triple; a
+ *                                boundary face keeps the order of its row in the
+ *                                Dirichlet/Neumann list, an interior face the local
+ *                                order (eq 2.1) of its lower-numbered element.
+ *   d_ftype     int32  [nfc]     0 interior, 1 Dirichlet, 2 Neumann
+ *   d_dirfaces  int32  [ndir]    face number of each Dirichlet row
+ *   d_neufaces  int32  [nneu]    face number of each Neumann row
+ *   d_facebyele int32  [nelt][4] faces of each element in the order of eq 2.1
+ *   d_perm      int32  [nelt][4] perm(K, l) in 1..6 (eq 2.2-2.3)
+ *   d_volume    double [nelt]    |K|
+ *   d_area      double [nfc]     |e|
+ *   d_normals   double [nelt][4][3] outward normals with |n_l| = |e_l|
+ *   d_face_elem int32  [nfc][2]  4K+l of the (one or two) elements holding the face,
+ *                                ascending; -1 in the second slot on the boundary
+ *   global trace system H (eq 6.5) in block-sparse-row form with d2 x d2 blocks:
+ *   d_row_ptr   int32  [nfc+1]   block-row pointers
+ *   d_col_idx   int32  [nnzb]    block columns, ascending within a row
+ *   d_diag      int32  [nfc]     block index of the diagonal block of each row
+ *   d_slot      int32  [nelt][16] block index of (facebyele[K][l], facebyele[K][m])
+ *                                at entry 4l+m: where the (l,m) block of C^K goes
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  int64_t nver, nelt, ndir, nneu;
+  int64_t nfc;   /* = (4 nelt + ndir + nneu) / 2 for a valid mesh  */
+  int64_t nnzb;  /* = nfc + 12 nelt                                 */
+  const double* d_coords;
+  const int32_t* d_elements;
+  const int32_t* d_dirichlet;
+  const int32_t* d_neumann;
+  int32_t* d_faces;
+  int32_t* d_ftype;
+  int32_t* d_dirfaces;
+  int32_t* d_neufaces;
+  int32_t* d_facebyele;
+  int32_t* d_perm;
+  double* d_volume;
+  double* d_area;
+  double* d_normals;
+  int32_t* d_face_elem;
+  int32_t* d_row_ptr;
+  int32_t* d_col_idx;
+  int32_t* d_diag;
+  int32_t* d_slot;
+} hdg_mesh;
+
+/* Fills nfc and nnzb of *mesh from nver/nelt/ndir/nneu (which the caller sets) and
+ * returns the workspace size of hdg_mesh_expand in *ws_bytes.
+ * Errors: HDG_ERR_INVALID_ARG (negative sizes, odd 4 nelt + ndir + nneu, or more
+ * than 2^21 vertices). */
+hdg_status hdg_mesh_sizes(hdg_mesh* mesh, size_t* ws_bytes);
+
+/* Expanded mesh from the basic one (Section 2): face list by a stable radix sort of
+ * sorted-vertex-triple keys and a segmented unique, facebyele, perm, volumes,
+ * areas, outward normals, and the block pattern of H with the per-element slot map.
+ * All integer outputs are deterministic.  Synchronises the stream once at the end
+ * to read the validation flag (setup call, not graph-capturable).
+ * Errors: HDG_ERR_MESH_ORIENTATION, HDG_ERR_MESH_NONCONFORMING,
+ * HDG_ERR_BOUNDARY_UNLISTED, HDG_ERR_BOUNDARY_INVALID, HDG_ERR_WORKSPACE,
+ * HDG_ERR_INVALID_ARG, HDG_ERR_DEVICE.  On error the outputs are unspecified. */
+hdg_status hdg_mesh_expand(hdg_mesh* mesh, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Discretisation: reference-element tables for degree k (Sections 3-4).
+ * Stroud conical-product Gauss-Jacobi rules with nq points per collapsed direction
+ * (nq = 0 selects k + 2, exact to degree 2k + 3), orthonormal hierarchical Dubiner
+ * bases, and the reference matrices C^x,y,z (eq 3.7), PP_l (eq 4.5), DP_{mu,l}
+ * (eq 4.10), and the stiffness tables of P_{k+1} used by the postprocess.
+ * Tables are built on the host in long double and uploaded once to a device
+ * buffer that the handle owns (setup-time allocation; freed by destroy).
+ * ------------------------------------------------------------------------------ */
+typedef struct hdg_disc hdg_disc;
+
+typedef struct {
+  int k, nq, d3, d2, m, d3p, nqd, nqd2;
+  int factor_len;   /* doubles per element in the factor store (see hdg_assemble_condense) */
+} hdg_disc_info;
+
+/* Errors: HDG_ERR_UNSUPPORTED_DEGREE (k < 0 or k > hdg_max_degree()),
+ * HDG_ERR_INVALID_ARG (nq < k+1 or nq > 8), HDG_ERR_DEVICE. */
+hdg_status hdg_disc_create(int k, int nq, hdg_disc** out);
+hdg_status hdg_disc_destroy(hdg_disc* disc);
+hdg_status hdg_disc_get_info(const hdg_disc* disc, hdg_disc_info* info);
+/* Copies host copies of the tables (for tests): name is one of "vol_pts" [nqd][3],
+ * "vol_w" [nqd], "tri_pts" [nqd2][2], "tri_w" [nqd2], "P" [nqd][d3], "Pgrad"
+ * [3][nqd][d3], "D" [nqd2][d2], "Pface" [4][nqd2][d3], "Chat" [3][d3][d3],
+ * "PP" [4][d3][d3], "DP" [6][4][d2][d3], "P1grad" [3][nqd][d3p], "Shat"
+ * [6][d3p][d3p] (xx, yy, zz, xy+yx, xz+zx, yz+zy).  *count receives the number of
+ * doubles; pass h_out = NULL to query it. */
+hdg_status hdg_disc_table(const hdg_disc* disc, const char* name, double* h_out, int64_t* count);
+
+/* Host-only variant of hdg_disc_table that needs no device: builds the tables of
+ * degree k with nq points per direction (0: k+2) on the host and copies the named one.
+ * Errors: HDG_ERR_UNSUPPORTED_DEGREE, HDG_ERR_INVALID_ARG. */
+hdg_status hdg_reference_table(int k, int nq, const char* name, double* h_out, int64_t* count);
+
+/* Physical volume quadrature points x_q = F_K(p_q) (eq 3.2, 3.4):
+ * d_xyz double [nelt][nqd][3].  The caller evaluates kappa, c and f there. */
+hdg_status hdg_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, double* d_xyz, void* stream);
+
+/* Face quadrature points y_r = phi_e(qhat_r) in each listed face's own
+ * parametrisation (Section 4, eq 6.2): d_faces_list int32 [n] face numbers,
+ * d_xyz double [n][nqd2][3]. */
+hdg_status hdg_face_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, const int32_t* d_faces_list,
+                              int64_t n, double* d_xyz, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Assembly + static condensation + scatter (Sections 3-6, eq 5.1-5.6, eq 6.5).
+ *   d_kappa, d_c, d_f  double [nelt][nqd]  kappa > 0, c >= 0 and f at the points of
+ *                                          hdg_qp_coords
+ *   d_tau              double [nelt][4]    tau_K on the faces of K in facebyele order
+ *                                          (>= 0, not all zero on an element)
+ * Outputs:
+ *   d_H       double [nnzb][d2][d2]  the block-sparse trace matrix of eq 6.5
+ *                                    (row-major blocks); exactly symmetric
+ *   d_F       double [nfc][d2]       the assembled Cf (eq 6.5's F)
+ *   d_factors double [nelt][factor_len]  per-element factors kept for hdg_recover:
+ *                                    packed lower Cholesky factors of M_{1/kappa}
+ *                                    and of the u-Schur complement, and f^K
+ * Every block of H and every entry of F is written; off-diagonal blocks have one
+ * contributing element, diagonal blocks and F entries at most two, summed in an
+ * order-independent way, so results are bitwise reproducible.
+ * Errors: HDG_ERR_INVALID_ARG.  Tau validity is the caller's contract (not checked
+ * on the device; hdg_check_tau checks it). */
+hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                 const double* d_c, const double* d_f, const double* d_tau, double* d_H,
+                                 double* d_F, double* d_factors, void* stream);
+
+/* Host check of tau (copies d_tau to the host; synchronises). HDG_ERR_TAU_ZERO. */
+hdg_status hdg_check_tau(const hdg_mesh* mesh, const double* d_tau, void* stream);
+
+/* Debug / parity export: C^K (m x m, row-major) and Cf^K for the listed elements,
+ * computed by the same device code as hdg_assemble_condense.
+ *   d_elems int32 [n], d_C double [n][m][m], d_Cf double [n][m]. */
+hdg_status hdg_export_local(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_c,
+                            const double* d_f, const double* d_tau, const int32_t* d_elems, int64_t n,
+                            double* d_C, double* d_Cf, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Boundary conditions (eq 6.1-6.4 and the elimination at the end of Section 6).
+ *   d_uD   double [ndir][nqd2]     u_D at the face points of the Dirichlet faces
+ *                                  (hdg_face_qp_coords of d_dirfaces)
+ *   d_gN   double [nneu][nqd2][3]  the Neumann vector field g_N at the points of the
+ *                                  Neumann faces (only g_N . n_e is used)
+ * In place on the output of hdg_assemble_condense:
+ *   d_F    becomes the right-hand side b of the reduced system: F + G_N on free
+ *          faces minus H_ID uD, uD on Dirichlet faces
+ *   d_H    Dirichlet rows/columns are replaced by identity/zero blocks, so that the
+ *          system stays symmetric positive definite
+ *   d_uhat double [nfc][d2] is set to uD on Dirichlet faces and 0 elsewhere
+ * Errors: HDG_ERR_INVALID_ARG. */
+hdg_status hdg_boundary(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_uD, const double* d_gN,
+                        double* d_H, double* d_F, double* d_uhat, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Global solve of the trace system H uhat = b (eq 6.5; the paper leaves the solver
+ * open): preconditioned conjugate gradients with a block-Jacobi preconditioner
+ * (Cholesky of the d2 x d2 diagonal blocks), FP64, deterministic reductions,
+ * stopping when the recomputed FP64 residual satisfies ||b - H x|| <= rtol ||b||.
+ * d_uhat is the initial guess on entry (Dirichlet values included) and the
+ * solution on exit.  The host reads one scalar every check_every iterations.
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  double rtol;        /* relative residual target, e.g. 1e-10 */
+  int max_iter;
+  int check_every;    /* iterations between host convergence checks (>= 1) */
+  int precision;      /* 0: FP64 throughout; 1: FP32 matrix and preconditioner inside
+                         an FP64 iterative-refinement loop */
+} hdg_solve_opts;
+
+typedef struct {
+  int iterations;     /* total inner iterations */
+  int outer;          /* refinement sweeps (precision 1) */
+  double rel_residual;/* true relative residual ||b - H x|| / ||b|| in FP64 */
+} hdg_solve_info;
+
+hdg_status hdg_solve_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, int precision, size_t* ws_bytes);
+hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H, const double* d_b,
+                     double* d_uhat, const hdg_solve_opts* opts, hdg_solve_info* info, void* d_ws,
+                     size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Reconstruction and postprocess (Section 6 "Reconstruction", eq 5.3, eq 9.11).
+ *   d_factors  from hdg_assemble_condense (same disc, mesh, coefficients, tau)
+ *   d_kappa    double [nelt][nqd] (for the postprocess right-hand side)
+ *   d_tau      double [nelt][4]
+ *   d_uhat     double [nfc][d2]
+ * Outputs: d_q double [nelt][3][d3], d_u double [nelt][d3],
+ *          d_ustar double [nelt][d3p] (may be NULL to skip the postprocess).
+ * ------------------------------------------------------------------------------ */
+hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_tau,
+                       const double* d_factors, const double* d_uhat, double* d_q, double* d_u,
+                       double* d_ustar, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H */

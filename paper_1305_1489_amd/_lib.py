@@ -1,0 +1,309 @@
+"""ctypes binding of libhdg (include/hdg.h).
+
+Argument marshalling only: every function here has the name of the C call it wraps,
+takes torch tensors (device memory) and plain Python values, allocates caller-owned
+outputs with torch where the C call expects them, and raises :class:`HdgError` on a
+non-zero status.  All arithmetic happens inside the library's HIP kernels.  The
+library must have been built (``python -m paper_1305_1489_amd.build``); there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhdg.so")
+
+STATUS = {0: "HDG_OK", 1: "HDG_ERR_INVALID_ARG", 2: "HDG_ERR_UNSUPPORTED_DEGREE", 3: "HDG_ERR_MESH_ORIENTATION",
+          4: "HDG_ERR_MESH_NONCONFORMING", 5: "HDG_ERR_BOUNDARY_UNLISTED", 6: "HDG_ERR_BOUNDARY_INVALID",
+          7: "HDG_ERR_TAU_ZERO", 8: "HDG_ERR_WORKSPACE", 9: "HDG_ERR_DEVICE", 10: "HDG_ERR_NOT_CONVERGED",
+          11: "HDG_ERR_SINGULAR"}
+
+EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expand", "hdg_disc_create",
+           "hdg_disc_destroy", "hdg_disc_get_info", "hdg_disc_table", "hdg_reference_table", "hdg_qp_coords", "hdg_face_qp_coords",
+           "hdg_assemble_condense", "hdg_check_tau", "hdg_export_local", "hdg_boundary",
+           "hdg_solve_workspace_size", "hdg_solve", "hdg_recover"]
+
+
+class HdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class hdg_mesh(C.Structure):
+    _fields_ = [("nver", C.c_int64), ("nelt", C.c_int64), ("ndir", C.c_int64), ("nneu", C.c_int64),
+                ("nfc", C.c_int64), ("nnzb", C.c_int64)] + [(n, C.c_void_p) for n in (
+                    "d_coords", "d_elements", "d_dirichlet", "d_neumann", "d_faces", "d_ftype", "d_dirfaces",
+                    "d_neufaces", "d_facebyele", "d_perm", "d_volume", "d_area", "d_normals", "d_face_elem",
+                    "d_row_ptr", "d_col_idx", "d_diag", "d_slot")]
+
+
+class hdg_disc_info(C.Structure):
+    _fields_ = [(n, C.c_int) for n in ("k", "nq", "d3", "d2", "m", "d3p", "nqd", "nqd2", "factor_len")]
+
+
+class hdg_solve_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("precision", C.c_int)]
+
+
+class hdg_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("rel_residual", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libhdg is not built ({LIB_PATH} missing): run python -m paper_1305_1489_amd.build")
+        L = C.CDLL(LIB_PATH)
+        L.hdg_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("hdg_last_error",):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise HdgError(code, lib().hdg_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(x, dtype, device):
+    return torch.as_tensor(x, dtype=dtype).to(device).contiguous()
+
+
+# ----------------------------------------------------------------------------- mesh
+class Mesh:
+    """Owns the device arrays of an expanded mesh and the hdg_mesh struct that points at them."""
+
+    def __init__(self, coords, elements, dirichlet, neumann, device="cuda"):
+        self.device = torch.device(device)
+        self.coords = _dev(coords, torch.float64, self.device).reshape(-1, 3)
+        self.elements = _dev(elements, torch.int32, self.device).reshape(-1, 4)
+        self.dirichlet = _dev(dirichlet, torch.int32, self.device).reshape(-1, 3)
+        self.neumann = _dev(neumann, torch.int32, self.device).reshape(-1, 3)
+        m = hdg_mesh()
+        m.nver, m.nelt = self.coords.shape[0], self.elements.shape[0]
+        m.ndir, m.nneu = self.dirichlet.shape[0], self.neumann.shape[0]
+        self.struct = m
+        self.ws_bytes = hdg_mesh_sizes(self)
+        nfc, nelt, nnzb = m.nfc, m.nelt, m.nnzb
+        i32 = dict(dtype=torch.int32, device=self.device)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.faces = torch.zeros((nfc, 3), **i32)
+        self.ftype = torch.zeros(nfc, **i32)
+        self.dirfaces = torch.zeros(max(m.ndir, 1), **i32)
+        self.neufaces = torch.zeros(max(m.nneu, 1), **i32)
+        self.facebyele = torch.zeros((nelt, 4), **i32)
+        self.perm = torch.zeros((nelt, 4), **i32)
+        self.volume = torch.zeros(nelt, **f64)
+        self.area = torch.zeros(nfc, **f64)
+        self.normals = torch.zeros((nelt, 4, 3), **f64)
+        self.face_elem = torch.zeros((nfc, 2), **i32)
+        self.row_ptr = torch.zeros(nfc + 1, **i32)
+        self.col_idx = torch.zeros(nnzb, **i32)
+        self.diag = torch.zeros(nfc, **i32)
+        self.slot = torch.zeros((nelt, 16), **i32)
+        for name in ("coords", "elements", "dirichlet", "neumann", "faces", "ftype", "dirfaces", "neufaces",
+                     "facebyele", "perm", "volume", "area", "normals", "face_elem", "row_ptr", "col_idx", "diag",
+                     "slot"):
+            setattr(m, "d_" + name, _ptr(getattr(self, name)).value)
+
+    @property
+    def nelt(self):
+        return self.struct.nelt
+
+    @property
+    def nfc(self):
+        return self.struct.nfc
+
+    @property
+    def nnzb(self):
+        return self.struct.nnzb
+
+    @property
+    def ndir(self):
+        return self.struct.ndir
+
+    @property
+    def nneu(self):
+        return self.struct.nneu
+
+
+def hdg_mesh_sizes(mesh: Mesh) -> int:
+    ws = C.c_size_t(0)
+    _check(lib().hdg_mesh_sizes(C.byref(mesh.struct), C.byref(ws)))
+    return ws.value
+
+
+def hdg_mesh_expand(coords, elements, dirichlet, neumann, device="cuda", stream=None) -> Mesh:
+    mesh = Mesh(coords, elements, dirichlet, neumann, device)
+    ws = torch.empty(max(mesh.ws_bytes, 8), dtype=torch.uint8, device=mesh.device)
+    _check(lib().hdg_mesh_expand(C.byref(mesh.struct), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return mesh
+
+
+# ----------------------------------------------------------------------------- discretisation
+class Disc:
+    def __init__(self, handle):
+        self.handle = handle
+        info = hdg_disc_info()
+        _check(lib().hdg_disc_get_info(handle, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in hdg_disc_info._fields_}
+
+    def __getattr__(self, item):
+        info = self.__dict__.get("info")
+        if info is not None and item in info:
+            return info[item]
+        raise AttributeError(item)
+
+    def __del__(self):
+        h = self.__dict__.get("handle")
+        if h and _lib is not None:
+            _lib.hdg_disc_destroy(h)
+            self.handle = None
+
+
+def hdg_disc_create(k: int, nq: int = 0) -> Disc:
+    h = C.c_void_p()
+    _check(lib().hdg_disc_create(C.c_int(k), C.c_int(nq), C.byref(h)))
+    return Disc(h)
+
+
+def hdg_disc_get_info(disc: Disc) -> dict:
+    return dict(disc.info)
+
+
+def hdg_disc_table(disc: Disc, name: str) -> np.ndarray:
+    n = C.c_int64(0)
+    _check(lib().hdg_disc_table(disc.handle, name.encode(), None, C.byref(n)))
+    out = np.zeros(n.value)
+    _check(lib().hdg_disc_table(disc.handle, name.encode(), out.ctypes.data_as(C.c_void_p), C.byref(n)))
+    return out
+
+
+def hdg_reference_table(k: int, name: str, nq: int = 0) -> np.ndarray:
+    """Host-only table build (no device needed)."""
+    n = C.c_int64(0)
+    _check(lib().hdg_reference_table(C.c_int(k), C.c_int(nq), name.encode(), None, C.byref(n)))
+    out = np.zeros(n.value)
+    _check(lib().hdg_reference_table(C.c_int(k), C.c_int(nq), name.encode(), out.ctypes.data_as(C.c_void_p),
+                                     C.byref(n)))
+    return out
+
+
+def hdg_max_degree() -> int:
+    return lib().hdg_max_degree()
+
+
+# ----------------------------------------------------------------------------- compute calls
+def hdg_qp_coords(disc: Disc, mesh: Mesh, out=None, stream=None):
+    if out is None:
+        out = torch.empty((mesh.nelt, disc.nqd, 3), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_qp_coords(disc.handle, C.byref(mesh.struct), _ptr(out), _stream(stream)))
+    return out
+
+
+def hdg_face_qp_coords(disc: Disc, mesh: Mesh, faces, out=None, stream=None):
+    faces = _dev(faces, torch.int32, mesh.device).reshape(-1)
+    n = faces.numel()
+    if out is None:
+        out = torch.empty((n, disc.nqd2, 3), dtype=torch.float64, device=mesh.device)
+    if n:
+        _check(lib().hdg_face_qp_coords(disc.handle, C.byref(mesh.struct), _ptr(faces), C.c_int64(n), _ptr(out),
+                                        _stream(stream)))
+    return out
+
+
+def hdg_check_tau(mesh: Mesh, tau, stream=None):
+    _check(lib().hdg_check_tau(C.byref(mesh.struct), _ptr(tau), _stream(stream)))
+
+
+def hdg_assemble_condense(disc: Disc, mesh: Mesh, kappa, c, f, tau, H=None, F=None, factors=None, stream=None):
+    d2 = disc.d2
+    if H is None:
+        H = torch.empty((mesh.nnzb, d2, d2), dtype=torch.float64, device=mesh.device)
+    if F is None:
+        F = torch.empty((mesh.nfc, d2), dtype=torch.float64, device=mesh.device)
+    if factors is None:
+        factors = torch.empty((mesh.nelt, disc.factor_len), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_assemble_condense(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(tau),
+                                       _ptr(H), _ptr(F), _ptr(factors), _stream(stream)))
+    return H, F, factors
+
+
+def hdg_export_local(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, stream=None):
+    elems = _dev(elems, torch.int32, mesh.device).reshape(-1)
+    n = elems.numel()
+    m = disc.m
+    Cm = torch.empty((n, m, m), dtype=torch.float64, device=mesh.device)
+    Cf = torch.empty((n, m), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_export_local(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(tau),
+                                  _ptr(elems), C.c_int64(n), _ptr(Cm), _ptr(Cf), _stream(stream)))
+    return Cm, Cf
+
+
+def hdg_boundary(disc: Disc, mesh: Mesh, uD, gN, H, F, uhat=None, stream=None):
+    if uhat is None:
+        uhat = torch.empty((mesh.nfc, disc.d2), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_boundary(disc.handle, C.byref(mesh.struct), _ptr(uD), _ptr(gN), _ptr(H), _ptr(F), _ptr(uhat),
+                              _stream(stream)))
+    return uhat
+
+
+def hdg_solve_workspace_size(disc: Disc, mesh: Mesh, precision: int = 0) -> int:
+    ws = C.c_size_t(0)
+    _check(lib().hdg_solve_workspace_size(disc.handle, C.byref(mesh.struct), C.c_int(precision), C.byref(ws)))
+    return ws.value
+
+
+def hdg_solve(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=100000, check_every=10, precision=0,
+              ws=None, stream=None, raise_on_fail=True):
+    need = hdg_solve_workspace_size(disc, mesh, precision)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=mesh.device)
+    opts = hdg_solve_opts(rtol=rtol, max_iter=max_iter, check_every=check_every, precision=precision)
+    info = hdg_solve_info()
+    code = lib().hdg_solve(disc.handle, C.byref(mesh.struct), _ptr(H), _ptr(b), _ptr(uhat), C.byref(opts),
+                           C.byref(info), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream))
+    out = {"iterations": info.iterations, "outer": info.outer, "rel_residual": info.rel_residual, "status": code}
+    if code != 0 and raise_on_fail:
+        _check(code)
+    return out
+
+
+def hdg_recover(disc: Disc, mesh: Mesh, kappa, tau, factors, uhat, q=None, u=None, ustar=None, postprocess=True,
+                stream=None):
+    if q is None:
+        q = torch.empty((mesh.nelt, 3, disc.d3), dtype=torch.float64, device=mesh.device)
+    if u is None:
+        u = torch.empty((mesh.nelt, disc.d3), dtype=torch.float64, device=mesh.device)
+    if postprocess and ustar is None:
+        ustar = torch.empty((mesh.nelt, disc.d3p), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_recover(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(tau), _ptr(factors), _ptr(uhat),
+                             _ptr(q), _ptr(u), _ptr(ustar) if postprocess else None, _stream(stream)))
+    return q, u, (ustar if postprocess else None)

@@ -1,0 +1,115 @@
+// Device-side helpers shared by the element kernels.
+#pragma once
+
+#include "hdg_internal.h"
+
+namespace hdg {
+
+template <int K>
+struct Dims {
+  static constexpr int D3 = dim3(K);
+  static constexpr int D2 = dim2(K);
+  static constexpr int M = 4 * D2;
+  static constexpr int NQ = K + 2;
+  static constexpr int NQD = NQ * NQ * NQ;
+  static constexpr int NQD2 = NQ * NQ;
+  static constexpr int D3P = dim3(K + 1);
+};
+
+// Geometry of one element (eq 2.0, eq 3.8, Section 2): a = det(B) B^{-T} (the cofactor
+// matrix, a[s][h] = a_{s h}), |K|, outward normals n_l with |n_l| = |e_l|, T_l = tau_l |e_l|,
+// and mu_l = perm(K, l) - 1.
+struct ElemGeom {
+  double v0[3];
+  double a[3][3];
+  double det, vol;
+  double n[4][3];
+  double T[4];
+  int mu[4];
+};
+
+__device__ inline void load_geometry(int K, const hdg_mesh& mesh, const double* __restrict__ tau, ElemGeom& g) {
+  const int* el = mesh.d_elements + 4 * K;
+  double p[4][3];
+  for (int i = 0; i < 4; ++i) {
+    int v = el[i];
+    for (int d = 0; d < 3; ++d) p[i][d] = mesh.d_coords[3 * v + d];
+  }
+  double e1[3], e2[3], e3[3];
+  for (int d = 0; d < 3; ++d) {
+    g.v0[d] = p[0][d];
+    e1[d] = p[1][d] - p[0][d];
+    e2[d] = p[2][d] - p[0][d];
+    e3[d] = p[3][d] - p[0][d];
+  }
+  // columns of a: e2 x e3, e3 x e1, e1 x e2
+  double c0[3] = {e2[1] * e3[2] - e2[2] * e3[1], e2[2] * e3[0] - e2[0] * e3[2], e2[0] * e3[1] - e2[1] * e3[0]};
+  double c1[3] = {e3[1] * e1[2] - e3[2] * e1[1], e3[2] * e1[0] - e3[0] * e1[2], e3[0] * e1[1] - e3[1] * e1[0]};
+  double c2[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  for (int s = 0; s < 3; ++s) {
+    g.a[s][0] = c0[s];
+    g.a[s][1] = c1[s];
+    g.a[s][2] = c2[s];
+  }
+  g.det = c2[0] * e3[0] + c2[1] * e3[1] + c2[2] * e3[2];
+  g.vol = g.det / 6.0;
+  const double* nn = mesh.d_normals + 12 * K;
+  for (int l = 0; l < 4; ++l) {
+    double s2 = 0;
+    for (int d = 0; d < 3; ++d) {
+      g.n[l][d] = nn[3 * l + d];
+      s2 += g.n[l][d] * g.n[l][d];
+    }
+    g.T[l] = tau[4 * K + l] * sqrt(s2);
+    g.mu[l] = mesh.d_perm[4 * K + l] - 1;
+  }
+}
+
+// Cholesky factorisation in place of an n x n SPD matrix in LDS (row-major, leading
+// dimension ld); the lower triangle receives L.  All threads of the block take part.
+template <int N>
+__device__ inline void lds_cholesky(double* A, int ld) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < N; ++j) {
+    if (t == 0) {
+      double s = A[j * ld + j];
+      for (int k = 0; k < j; ++k) s -= A[j * ld + k] * A[j * ld + k];
+      A[j * ld + j] = sqrt(s);
+    }
+    __syncthreads();
+    const double inv = 1.0 / A[j * ld + j];
+    for (int i = j + 1 + t; i < N; i += nt) {
+      double s = A[i * ld + j];
+      for (int k = 0; k < j; ++k) s -= A[i * ld + k] * A[j * ld + k];
+      A[i * ld + j] = s * inv;
+    }
+    __syncthreads();
+  }
+}
+
+// X <- L^{-1} X for NC columns of an N-row matrix X (row-major, leading dimension ldx),
+// L lower triangular (ld ldl).  One thread per column.
+template <int N>
+__device__ inline void lds_forward_cols(const double* L, int ldl, double* X, int ldx, int ncols) {
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    for (int r = 0; r < N; ++r) {
+      double s = X[r * ldx + c];
+      for (int k = 0; k < r; ++k) s -= L[r * ldl + k] * X[k * ldx + c];
+      X[r * ldx + c] = s / L[r * ldl + r];
+    }
+  }
+}
+
+// X <- L^{-T} X (back substitution with the transpose), one thread per column.
+template <int N>
+__device__ inline void lds_backward_cols(const double* L, int ldl, double* X, int ldx, int ncols) {
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) {
+    for (int r = N - 1; r >= 0; --r) {
+      double s = X[r * ldx + c];
+      for (int k = r + 1; k < N; ++k) s -= L[k * ldl + r] * X[k * ldx + c];
+      X[r * ldx + c] = s / L[r * ldl + r];
+    }
+  }
+}
+
+}  // namespace hdg

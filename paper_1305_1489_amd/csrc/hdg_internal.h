@@ -1,0 +1,68 @@
+// Internal declarations shared by the host and device sources of libhdg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+
+namespace hdg {
+
+constexpr int kMaxDegree = 4;
+
+inline constexpr int dim3(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
+inline constexpr int dim2(int k) { return (k + 1) * (k + 2) / 2; }
+inline constexpr int tri(int n) { return n * (n + 1) / 2; }
+
+// Offsets (in doubles) of every reference table inside the device table buffer.
+struct TableOffsets {
+  int vol_pts, vol_w, lambda, P, Pg, tri_pts, tri_w, xi, D, Pface, Chat, PP, DP, P1g, Shat;
+  int total;
+};
+
+// Device view of the tables, passed to kernels by value.
+struct Tables {
+  const double* vol_w;   // [nqd]
+  const double* lambda;  // [nqd][4]  barycentric coordinates of the volume points (eq 3.4)
+  const double* P;       // [nqd][d3]  basis at the volume points (eq 3.5)
+  const double* Pg;      // [3][nqd][d3] reference gradients (eq 3.66)
+  const double* tri_w;   // [nqd2]
+  const double* xi;      // [nqd2][3] barycentric coordinates of the face points (Section 4)
+  const double* D;       // [nqd2][d2] face basis (eq 4.7)
+  const double* Chat;    // [3][d3][d3] (eq 3.7)
+  const double* PP;      // [4][d3][d3] (eq 4.5)
+  const double* DP;      // [6][4][d2][d3] (eq 4.10)
+  const double* P1g;     // [3][nqd][d3p] gradients of the degree k+1 basis
+  const double* Shat;    // [6][d3p][d3p]
+};
+
+struct HostTables {
+  int k, nq, d3, d2, d3p, nqd, nqd2;
+  TableOffsets off;
+  std::vector<double> data;
+};
+
+HostTables build_tables(int k, int nq);
+
+}  // namespace hdg
+
+struct hdg_disc {
+  hdg::HostTables host;
+  double* d_tables = nullptr;
+  hdg::Tables dev;
+  int factor_len = 0;
+};
+
+namespace hdg {
+hdg_status set_error(hdg_status s, const std::string& msg);
+hdg_status check_hip(hipError_t e, const char* what);
+}  // namespace hdg
+
+#define HDG_CHECK_LAUNCH(what)                                        \
+  do {                                                                \
+    hipError_t e__ = hipGetLastError();                               \
+    if (e__ != hipSuccess) return hdg::check_hip(e__, what);          \
+  } while (0)

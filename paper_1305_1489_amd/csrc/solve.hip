@@ -1,0 +1,417 @@
+// Global solve of the trace system H uhat = b (eq 6.5 after the Dirichlet elimination).
+// The paper leaves the solver open; this is preconditioned conjugate gradients with a
+// block-Jacobi preconditioner (explicit inverse of each d2 x d2 diagonal block, via its
+// Cholesky factor).  Reductions are two-stage with a fixed grid and a fixed combining
+// order, so every run gives the same bits.  alpha and beta live on the device; the host
+// reads the residual norm every check_every iterations, and accepts the iterate only when
+// the recomputed residual ||b - H x|| (FP64) meets the tolerance (otherwise the recursive
+// residual is replaced by the true one and the iteration restarts from the current x).
+//
+// precision = 1: H and the preconditioner are also kept in FP32 and the correction
+// equation H d = r is solved by an inner FP32-storage PCG inside an FP64 iterative
+// refinement x <- x + d, r = b - H x (FP64 matrix, FP64 residuals and inner products).
+#include <cmath>
+#include <vector>
+
+#include "device_common.h"
+
+namespace hdg {
+namespace {
+
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// ---- block-Jacobi setup: Minv[f] = (H_ff)^{-1}
+template <int D2, class T>
+__global__ void k_bj_setup(const double* __restrict__ H, const int* __restrict__ diag, int nfc, T* __restrict__ Minv) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfc) return;
+  double A[D2][D2], X[D2][D2];
+  const double* blk = H + (size_t)diag[f] * D2 * D2;
+  for (int i = 0; i < D2; ++i)
+    for (int j = 0; j < D2; ++j) A[i][j] = blk[i * D2 + j];
+  for (int j = 0; j < D2; ++j) {  // Cholesky, lower
+    double s = A[j][j];
+    for (int k = 0; k < j; ++k) s -= A[j][k] * A[j][k];
+    A[j][j] = sqrt(s);
+    for (int i = j + 1; i < D2; ++i) {
+      double v = A[i][j];
+      for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
+      A[i][j] = v / A[j][j];
+    }
+  }
+  for (int c = 0; c < D2; ++c) {  // columns of the inverse
+    double y[D2];
+    for (int r = 0; r < D2; ++r) {
+      double s = r == c ? 1.0 : 0.0;
+      for (int k = 0; k < r; ++k) s -= A[r][k] * y[k];
+      y[r] = s / A[r][r];
+    }
+    for (int r = D2 - 1; r >= 0; --r) {
+      double s = y[r];
+      for (int k = r + 1; k < D2; ++k) s -= A[k][r] * y[k];
+      y[r] = s / A[r][r];
+    }
+    for (int r = 0; r < D2; ++r) X[r][c] = y[r];
+  }
+  T* o = Minv + (size_t)f * D2 * D2;
+  for (int i = 0; i < D2; ++i)
+    for (int j = 0; j < D2; ++j) o[i * D2 + j] = (T)(0.5 * (X[i][j] + X[j][i]));
+}
+
+template <class T>
+__global__ void k_convert(const double* __restrict__ a, T* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (T)a[i];
+}
+
+// ---- y = alpha_y * y + H x  (alpha_y = 0: y = H x), one thread per row entry
+template <int D2, class TM, class TV>
+__global__ void k_spmv(const int* __restrict__ row_ptr, const int* __restrict__ col_idx, const TM* __restrict__ H,
+                       const TV* __restrict__ x, TV* __restrict__ y, int nfc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfc * D2) return;
+  const int f = i / D2, c = i % D2;
+  double s = 0;
+  for (int p = row_ptr[f]; p < row_ptr[f + 1]; ++p) {
+    const TM* blk = H + ((size_t)p * D2 + c) * D2;
+    const TV* xv = x + (size_t)col_idx[p] * D2;
+#pragma unroll
+    for (int j = 0; j < D2; ++j) s += (double)blk[j] * (double)xv[j];
+  }
+  y[i] = (TV)s;
+}
+
+// r = b - H x
+template <int D2>
+__global__ void k_residual(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                           const double* __restrict__ H, const double* __restrict__ x, const double* __restrict__ b,
+                           double* __restrict__ r, int nfc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfc * D2) return;
+  const int f = i / D2, c = i % D2;
+  double s = 0;
+  for (int p = row_ptr[f]; p < row_ptr[f + 1]; ++p) {
+    const double* blk = H + ((size_t)p * D2 + c) * D2;
+    const double* xv = x + (size_t)col_idx[p] * D2;
+#pragma unroll
+    for (int j = 0; j < D2; ++j) s += blk[j] * xv[j];
+  }
+  r[i] = b[i] - s;
+}
+
+// ---- deterministic dot products: partial sums per block, fixed grid; final in one block
+template <class TA, class TB>
+__global__ void k_dot_partial(const TA* __restrict__ a, const TB* __restrict__ b, size_t n, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  double s = 0;
+  for (size_t i = blockIdx.x * (size_t)kRedThreads + threadIdx.x; i < n; i += (size_t)kRedBlocks * kRedThreads)
+    s += (double)a[i] * (double)b[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_dot_final(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double s = 0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// z = Minv r (one thread per row entry)
+template <int D2, class TM, class TV>
+__global__ void k_precond(const TM* __restrict__ Minv, const TV* __restrict__ r, TV* __restrict__ z, int nfc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfc * D2) return;
+  const int f = i / D2, c = i % D2;
+  const TM* m = Minv + ((size_t)f * D2 + c) * D2;
+  const TV* rv = r + (size_t)f * D2;
+  double s = 0;
+#pragma unroll
+  for (int j = 0; j < D2; ++j) s += (double)m[j] * (double)rv[j];
+  z[i] = (TV)s;
+}
+
+// scal[0] = rz, scal[1] = pAp, scal[2] = rz_new, scal[3] = rr
+// x += alpha p, r -= alpha Ap, alpha = rz / pAp
+template <class TV>
+__global__ void k_update_xr(TV* __restrict__ x, TV* __restrict__ r, const TV* __restrict__ p,
+                            const TV* __restrict__ Ap, const double* __restrict__ scal, size_t n) {
+  const double alpha = scal[0] / scal[1];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
+    r[i] = (TV)((double)r[i] - alpha * (double)Ap[i]);
+  }
+}
+
+// p = z + beta p with beta = rz_new / rz; then rz <- rz_new
+template <class TV>
+__global__ void k_update_p(TV* __restrict__ p, const TV* __restrict__ z, const double* __restrict__ scal, size_t n) {
+  const double beta = scal[2] / scal[0];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = (TV)((double)z[i] + beta * (double)p[i]);
+}
+
+__global__ void k_shift_rz(double* scal) {
+  if (threadIdx.x == 0) scal[0] = scal[2];
+}
+
+template <class TV>
+__global__ void k_copy(const TV* __restrict__ a, TV* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+template <class TA, class TB>
+__global__ void k_axpy_cast(const TA* __restrict__ a, TB* __restrict__ b, size_t n) {  // b += a
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (TB)((double)b[i] + (double)a[i]);
+}
+
+template <class TV>
+__global__ void k_fill(TV* __restrict__ a, size_t n, double v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = (TV)v;
+}
+
+template <class TA, class TB>
+__global__ void k_scale_cast(const TA* __restrict__ a, TB* __restrict__ b, size_t n, const double* __restrict__ nrm) {
+  const double s = 1.0 / sqrt(*nrm);
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (TB)((double)a[i] * s);
+}
+
+template <class TA, class TB>
+__global__ void k_axpy_scaled(const TA* __restrict__ a, TB* __restrict__ b, size_t n, const double* __restrict__ nrm) {
+  const double s = sqrt(*nrm);  // b += s * a
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (TB)((double)b[i] + s * (double)a[i]);
+}
+
+struct Carve {
+  char* p;
+  size_t left;
+  bool ok = true;
+  template <class T>
+  T* take(size_t n) {
+    size_t bytes = (n * sizeof(T) + 255) & ~size_t(255);
+    if (bytes > left) { ok = false; return nullptr; }
+    T* r = reinterpret_cast<T*>(p);
+    p += bytes;
+    left -= bytes;
+    return r;
+  }
+};
+
+size_t ws_size(const hdg_mesh* mesh, int d2, int precision) {
+  const size_t n = (size_t)mesh->nfc * d2;
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
+  for (int i = 0; i < 4; ++i) add(n * sizeof(double));  // r z p Ap
+  add((size_t)mesh->nfc * d2 * d2 * sizeof(double));    // Minv
+  add(kRedBlocks * sizeof(double));
+  add(8 * sizeof(double));
+  if (precision == 1) {
+    for (int i = 0; i < 5; ++i) add(n * sizeof(float));  // d r z p Ap (inner)
+    add((size_t)mesh->nnzb * d2 * d2 * sizeof(float));   // H in FP32
+    add((size_t)mesh->nfc * d2 * d2 * sizeof(float));    // Minv in FP32
+  }
+  return b;
+}
+
+template <int D2>
+struct Solver {
+  const hdg_mesh* mesh;
+  hipStream_t s;
+  size_t n;
+  unsigned gv, gr;
+  double* part;
+  double* scal;
+
+  template <class TA, class TB>
+  void dot(const TA* a, const TB* b, double* out) {
+    k_dot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(a, b, n, part);
+    k_dot_final<<<1, kRedThreads, 0, s>>>(part, out);
+  }
+  double read(const double* d) {
+    double h = 0;
+    (void)hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    return h;
+  }
+};
+
+template <int D2>
+hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, double* x, const hdg_solve_opts* o,
+                     hdg_solve_info* info, void* ws, size_t ws_bytes, hipStream_t s) {
+  const size_t n = (size_t)mesh->nfc * D2;
+  Carve cv{(char*)ws, ws_bytes};
+  double* r = cv.take<double>(n);
+  double* z = cv.take<double>(n);
+  double* p = cv.take<double>(n);
+  double* Ap = cv.take<double>(n);
+  double* Minv = cv.take<double>((size_t)mesh->nfc * D2 * D2);
+  double* part = cv.take<double>(kRedBlocks);
+  double* scal = cv.take<double>(8);
+  float *d32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *H32 = nullptr,
+        *Minv32 = nullptr;
+  if (o->precision == 1) {
+    d32 = cv.take<float>(n);
+    r32 = cv.take<float>(n);
+    z32 = cv.take<float>(n);
+    p32 = cv.take<float>(n);
+    Ap32 = cv.take<float>(n);
+    H32 = cv.take<float>((size_t)mesh->nnzb * D2 * D2);
+    Minv32 = cv.take<float>((size_t)mesh->nfc * D2 * D2);
+  }
+  if (!cv.ok) return set_error(HDG_ERR_WORKSPACE, "hdg_solve: workspace too small");
+  const unsigned T = 256;
+  const unsigned gv = (unsigned)std::min<size_t>((n + T - 1) / T, 8192);
+  const unsigned gr = (unsigned)((n + T - 1) / T);
+  Solver<D2> S{mesh, s, n, gv, gr, part, scal};
+  const int nfc = (int)mesh->nfc;
+  k_bj_setup<D2, double><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv);
+  // ||b||
+  S.dot(b, b, scal + 4);
+  const double bb = S.read(scal + 4);
+  HDG_CHECK_LAUNCH("hdg_solve setup");
+  info->iterations = 0;
+  info->outer = 0;
+  info->rel_residual = 0;
+  if (bb == 0) {
+    k_fill<double><<<gv, T, 0, s>>>(x, n, 0.0);
+    return HDG_OK;
+  }
+  const double tol2 = o->rtol * o->rtol * bb;
+  const int every = std::max(1, o->check_every);
+  if (o->precision == 0) {
+    k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
+    k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, r, z, nfc);
+    k_copy<double><<<gv, T, 0, s>>>(z, p, n);
+    S.dot(r, z, scal + 0);
+    int it = 0;
+    for (;;) {
+      if (it % every == 0 || it >= o->max_iter) {
+        S.dot(r, r, scal + 3);
+        double rr = S.read(scal + 3);
+        HDG_CHECK_LAUNCH("hdg_solve");
+        if (!std::isfinite(rr)) {
+          info->iterations = it;
+          return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: breakdown (non-finite residual)");
+        }
+        if (rr <= tol2 || it >= o->max_iter) {
+          // verify with the recomputed residual
+          k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
+          S.dot(r, r, scal + 3);
+          double tr = S.read(scal + 3);
+          info->iterations = it;
+          info->rel_residual = std::sqrt(tr / bb);
+          if (tr <= tol2) return HDG_OK;
+          if (it >= o->max_iter)
+            return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: iteration limit reached");
+          // residual replacement and restart
+          k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, r, z, nfc);
+          k_copy<double><<<gv, T, 0, s>>>(z, p, n);
+          S.dot(r, z, scal + 0);
+        }
+      }
+      k_spmv<D2, double, double><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, p, Ap, nfc);
+      S.dot(p, Ap, scal + 1);
+      k_update_xr<double><<<gv, T, 0, s>>>(x, r, p, Ap, scal, n);
+      k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, r, z, nfc);
+      S.dot(r, z, scal + 2);
+      k_update_p<double><<<gv, T, 0, s>>>(p, z, scal, n);
+      k_shift_rz<<<1, 1, 0, s>>>(scal);
+      ++it;
+    }
+  }
+  // ---- precision 1: FP64 refinement around an FP32-storage PCG
+  const size_t nh = (size_t)mesh->nnzb * D2 * D2;
+  k_convert<float><<<8192, T, 0, s>>>(H, H32, nh);
+  k_bj_setup<D2, float><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv32);
+  int total = 0;
+  const double inner_rtol = 1e-4;
+  for (int outer = 0; outer < 60; ++outer) {
+    k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
+    S.dot(r, r, scal + 5);
+    const double rr = S.read(scal + 5);
+    HDG_CHECK_LAUNCH("hdg_solve refinement");
+    info->outer = outer;
+    info->iterations = total;
+    info->rel_residual = std::sqrt(rr / bb);
+    if (!std::isfinite(rr)) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: breakdown in refinement");
+    if (rr <= tol2) return HDG_OK;
+    if (total >= o->max_iter) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: iteration limit reached");
+    // inner: H d = r / ||r|| in FP32 storage, d = 0
+    k_scale_cast<double, float><<<gv, T, 0, s>>>(r, r32, n, scal + 5);
+    k_fill<float><<<gv, T, 0, s>>>(d32, n, 0.0);
+    k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, r32, z32, nfc);
+    k_copy<float><<<gv, T, 0, s>>>(z32, p32, n);
+    S.dot(r32, z32, scal + 0);
+    const double in_tol2 = inner_rtol * inner_rtol;  // relative to ||r32|| = 1
+    for (int it = 0;; ++it) {
+      if (it % every == 0) {
+        S.dot(r32, r32, scal + 3);
+        double r2 = S.read(scal + 3);
+        if (!(r2 > in_tol2) || total >= o->max_iter) break;
+      }
+      k_spmv<D2, float, float><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H32, p32, Ap32, nfc);
+      S.dot(p32, Ap32, scal + 1);
+      k_update_xr<float><<<gv, T, 0, s>>>(d32, r32, p32, Ap32, scal, n);
+      k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, r32, z32, nfc);
+      S.dot(r32, z32, scal + 2);
+      k_update_p<float><<<gv, T, 0, s>>>(p32, z32, scal, n);
+      k_shift_rz<<<1, 1, 0, s>>>(scal);
+      ++total;
+    }
+    k_axpy_scaled<float, double><<<gv, T, 0, s>>>(d32, x, n, scal + 5);
+  }
+  return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: refinement did not converge");
+}
+
+}  // namespace
+
+hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const char* who);
+
+}  // namespace hdg
+
+using namespace hdg;
+
+extern "C" hdg_status hdg_solve_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, int precision,
+                                               size_t* ws_bytes) {
+  if (!disc || !mesh || !ws_bytes) return set_error(HDG_ERR_INVALID_ARG, "hdg_solve_workspace_size: NULL argument");
+  if (precision != 0 && precision != 1) return set_error(HDG_ERR_INVALID_ARG, "hdg_solve_workspace_size: precision");
+  *ws_bytes = ws_size(mesh, disc->host.d2, precision);
+  return HDG_OK;
+}
+
+extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H, const double* d_b,
+                                double* d_uhat, const hdg_solve_opts* opts, hdg_solve_info* info, void* d_ws,
+                                size_t ws_bytes, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_solve");
+  if (st) return st;
+  if (!d_H || !d_b || !d_uhat || !opts || !info || !mesh->d_row_ptr || !mesh->d_col_idx)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: NULL argument");
+  if (!(opts->rtol > 0) || opts->max_iter < 0 || (opts->precision != 0 && opts->precision != 1))
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: bad options");
+  if (!d_ws || ws_bytes < ws_size(mesh, disc->host.d2, opts->precision))
+    return set_error(HDG_ERR_WORKSPACE, "hdg_solve: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  switch (disc->host.k) {
+    case 0: return run_solve<dim2(0)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
+    case 1: return run_solve<dim2(1)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
+    case 2: return run_solve<dim2(2)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
+    case 3: return run_solve<dim2(3)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
+    case 4: return run_solve<dim2(4)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve: unsupported degree");
+}

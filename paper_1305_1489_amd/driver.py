@@ -1,0 +1,86 @@
+"""End-to-end driver over the C-ABI: mesh expansion, tables, coefficients at the quadrature
+points, assembly + condensation + scatter, boundary conditions, global solve,
+reconstruction and postprocess.
+
+Only marshalling and orchestration happen here.  The coefficient fields are whatever
+callables the caller hands in (functions of device tensors X, Y, Z); they are evaluated
+at the physical quadrature points that the library computes.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _field(fn, X, Y, Z):
+    v = fn(X, Y, Z)
+    if not isinstance(v, torch.Tensor):
+        v = torch.as_tensor(v, dtype=torch.float64, device=X.device)
+    return (v * torch.ones_like(X)).to(torch.float64).contiguous()
+
+
+class HDGSystem:
+    """Device state of one HDG problem (mesh, degree, data)."""
+
+    def __init__(self, coords, elements, dirichlet, neumann, k, problem, device="cuda", stream=None):
+        self.device = torch.device(device)
+        self.stream = stream
+        self.mesh = L.hdg_mesh_expand(coords, elements, dirichlet, neumann, device=device, stream=stream)
+        self.disc = L.hdg_disc_create(k)
+        self.k = k
+        self.problem = problem
+        xyz = L.hdg_qp_coords(self.disc, self.mesh, stream=stream)
+        X, Y, Z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+        self.qp = xyz
+        self.kappa = _field(problem.kappa, X, Y, Z)
+        self.c = _field(problem.c, X, Y, Z)
+        self.f = _field(problem.f, X, Y, Z)
+        tau = problem.tau
+        if np.isscalar(tau):
+            self.tau = torch.full((self.mesh.nelt, 4), float(tau), dtype=torch.float64, device=self.device)
+        else:
+            self.tau = torch.as_tensor(np.asarray(tau, dtype=np.float64).reshape(-1, 4)).to(self.device).contiguous()
+        m = self.mesh
+        nqd2 = self.disc.nqd2
+        if m.ndir:
+            y = L.hdg_face_qp_coords(self.disc, m, m.dirfaces[: m.ndir], stream=stream)
+            self.uD = _field(problem.uD, y[..., 0], y[..., 1], y[..., 2])
+        else:
+            self.uD = torch.zeros((1, nqd2), dtype=torch.float64, device=self.device)
+        if m.nneu:
+            y = L.hdg_face_qp_coords(self.disc, m, m.neufaces[: m.nneu], stream=stream)
+            g = problem.gN(y[..., 0], y[..., 1], y[..., 2])
+            self.gN = torch.stack([_field(lambda a, b, c, gi=gi: gi, y[..., 0], y[..., 1], y[..., 2]) for gi in g],
+                                  dim=-1).contiguous()
+        else:
+            self.gN = torch.zeros((1, nqd2, 3), dtype=torch.float64, device=self.device)
+        d2 = self.disc.d2
+        self.H = torch.empty((m.nnzb, d2, d2), dtype=torch.float64, device=self.device)
+        self.F = torch.empty((m.nfc, d2), dtype=torch.float64, device=self.device)
+        self.factors = torch.empty((m.nelt, self.disc.factor_len), dtype=torch.float64, device=self.device)
+        self.uhat = torch.zeros((m.nfc, d2), dtype=torch.float64, device=self.device)
+
+    # ---- stages
+    def assemble(self):
+        L.hdg_assemble_condense(self.disc, self.mesh, self.kappa, self.c, self.f, self.tau, self.H, self.F,
+                                self.factors, stream=self.stream)
+
+    def boundary(self):
+        L.hdg_boundary(self.disc, self.mesh, self.uD, self.gN, self.H, self.F, self.uhat, stream=self.stream)
+
+    def solve(self, rtol=1e-10, max_iter=200000, check_every=20, precision=0):
+        return L.hdg_solve(self.disc, self.mesh, self.H, self.F, self.uhat, rtol=rtol, max_iter=max_iter,
+                           check_every=check_every, precision=precision, stream=self.stream)
+
+    def recover(self, postprocess=True):
+        return L.hdg_recover(self.disc, self.mesh, self.kappa, self.tau, self.factors, self.uhat,
+                             postprocess=postprocess, stream=self.stream)
+
+    def run(self, rtol=1e-10, precision=0):
+        self.assemble()
+        self.boundary()
+        info = self.solve(rtol=rtol, precision=precision)
+        q, u, us = self.recover()
+        return dict(info=info, q=q, u=u, ustar=us)

@@ -1,0 +1,83 @@
+"""Host-side checks of libhdg that need no GPU: the shared library loads and exports every
+call declared in include/hdg.h, and the C++ reference tables (quadrature, Dubiner bases,
+reference matrices of eq 3.7, 4.5, 4.10 and the postprocess stiffness tables) agree with
+the oracle's independently built ones."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis as OB, quadrature as OQ
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1305_1489_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_symbol(L):
+    hdr = open(os.path.join(ROOT, "include", "hdg.h")).read()
+    declared = set(re.findall(r"^\s*(?:hdg_status|const char\*|int)\s+(hdg_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 18
+    lib = L.lib()
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(L.EXPORTS) == declared
+
+
+def test_error_reporting_without_device(L):
+    with pytest.raises(L.HdgError) as e:
+        L.hdg_reference_table(9, "P")
+    assert e.value.name == "HDG_ERR_UNSUPPORTED_DEGREE"
+    with pytest.raises(L.HdgError) as e:
+        L.hdg_reference_table(2, "nope")
+    assert e.value.name == "HDG_ERR_INVALID_ARG"
+    assert L.hdg_max_degree() >= 4
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def test_tables_match_oracle(L, k):
+    n = k + 2
+    vp, vw = OQ.tet_rule(n)
+    tp, tw = OQ.tri_rule(n)
+    d3, d2, d3p = OB.dim3(k), OB.dim2(k), OB.dim3(k + 1)
+    T = lambda name: L.hdg_reference_table(k, name)
+    assert np.abs(T("vol_pts").reshape(-1, 3) - vp).max() < 1e-15
+    assert np.abs(T("vol_w") - vw).max() < 1e-15
+    assert np.abs(T("tri_pts").reshape(-1, 2) - tp).max() < 1e-15
+    assert np.abs(T("tri_w") - tw).max() < 1e-15
+    P = OB.eval3(k, vp)
+    assert np.abs(T("P").reshape(-1, d3) - P).max() < 1e-12
+    G = OB.grad3(k, vp)
+    assert np.abs(T("Pgrad").reshape(3, -1, d3) - G).max() < 1e-11
+    D = OB.eval2(k, tp)
+    assert np.abs(T("D").reshape(-1, d2) - D).max() < 1e-13
+    # face traces (eq 4.4) at the points of eq 2.5
+    s, t = tp[:, 0], tp[:, 1]
+    fpts = [np.stack([s, t, 0 * s], 1), np.stack([s, 0 * s, t], 1), np.stack([0 * s, s, t], 1),
+            np.stack([s, t, 1 - s - t], 1)]
+    Pf = np.stack([OB.eval3(k, p) for p in fpts])
+    assert np.abs(T("Pface").reshape(4, -1, d3) - Pf).max() < 1e-12
+    # eq 3.7: Chat^h = (1/6) (w . P)^T P^h
+    Ch = np.einsum("q,qi,hqj->hij", vw, P, G) / 6
+    assert np.abs(T("Chat").reshape(3, d3, d3) - Ch).max() < 1e-12
+    # eq 4.5: PP_l = (v . P^l)^T P^l
+    PP = np.einsum("r,lri,lrj->lij", tw, Pf, Pf)
+    assert np.abs(T("PP").reshape(4, d3, d3) - PP).max() < 1e-12
+    # eq 4.10: DP_{mu,l} = (v . D^mu)^T P^l with D^mu_ri = D_i(F_mu(q_r)) (eq 2.2)
+    Fm = [np.stack([s, t], 1), np.stack([t, s], 1), np.stack([t, 1 - s - t], 1), np.stack([s, 1 - s - t], 1),
+          np.stack([1 - s - t, s], 1), np.stack([1 - s - t, t], 1)]
+    Dmu = np.stack([OB.eval2(k, p) for p in Fm])
+    DP = np.einsum("r,mri,lrj->mlij", tw, Dmu, Pf)
+    assert np.abs(T("DP").reshape(6, 4, d2, d3) - DP).max() < 1e-12
+    # postprocess tables
+    G1 = OB.grad3(k + 1, vp)
+    assert np.abs(T("P1grad").reshape(3, -1, d3p) - G1).max() < 1e-10
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    Sh = np.stack([np.einsum("q,qi,qj->ij", vw, G1[a], G1[b]) / 6 + (np.einsum("q,qi,qj->ij", vw, G1[b], G1[a]) / 6 if a != b else 0)
+                   for a, b in pairs])
+    assert np.abs(T("Shat").reshape(6, d3p, d3p) - Sh).max() < 1e-10 * max(1.0, np.abs(Sh).max())
