@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of the HDG element hot path on one MI355X.
+
+A step is one pass of the element-local hot path over the whole mesh:
+  hdg_assemble_condense  (geometry, volume and face blocks, static condensation,
+                          scatter into the block-sparse trace matrix H and F)
+  hdg_boundary           (Dirichlet data, Neumann load, Dirichlet elimination)
+  hdg_recover            (reconstruction of q and u from the face traces, and the
+                          postprocessed u*)
+with the trace solution uhat computed once before the timed region (the solve is the
+second metric, reported under "solve").  Inputs are synthetic, seeded and resident in
+HBM when the timed region starts.
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def binom(n, k):
+    return math.comb(n, k)
+
+
+def algorithmic_flops(k):
+    """Algorithmic FP64 flops per element of the two element kernels (FMA = 2 flops),
+    for the block-elimination condensation implemented by the library."""
+    d3, d2, d3p = binom(k + 3, 3), binom(k + 2, 2), binom(k + 4, 3)
+    m = 4 * d2
+    nqd = (k + 2) ** 3
+    tri = lambda n: n * (n + 1) // 2
+    condense = (4 * tri(d3) * nqd          # two Gram matrices (M_{1/kappa}, M_c), symmetric
+                + 2 * d3 * nqd             # load vector
+                + 8 * tri(d3)              # tau PP
+                + 18 * d3 * d3             # C_s^T from the cofactors
+                + d3 ** 3 // 3             # Cholesky of M
+                + 3 * d3 ** 3              # W = L^{-1} C^T
+                + m * d3 * d3              # Z = L^{-1} DP^T
+                + 6 * d3 * tri(d3)         # S += sum W^T W (symmetric)
+                + d3 ** 3 // 3             # Cholesky of S
+                + 24 * d3 * d3             # U_l = sum_s n_ls W_s
+                + 2 * m * d3 * d3          # B = T DP^T + U^T Z
+                + (m + 1) * d3 * d3        # V = Ls^{-1} [B | f]
+                + 4 * d3 * tri(m)          # C^K = (n.n) Z^T Z - V^T V (symmetric)
+                + 2 * m * d3)              # Cf^K
+    recover = (2 * 4 * d2 * d3 + 24 * d3 + 3 * 2 * d3 * d3 + 18 * d3 + 2 * 3 * d3 * d3 + 8 * d3
+               + 2 * d3 * d3 + 3 * 2 * d3 * d3 + 3 * 2 * d3 * d3
+               + 6 * nqd * d3 + 20 * nqd + 12 * d3p * d3p + 6 * nqd * d3p
+               + (d3p - 1) ** 3 // 3 + 2 * (d3p - 1) ** 2)
+    return condense, recover
+
+
+def algorithmic_bytes(k, nelt, nfc, nnzb):
+    """Minimal HBM bytes of the condensation kernel per launch: coefficients at the
+    quadrature points, per-element geometry/topology, the H and F writes and the factors."""
+    d3, d2 = binom(k + 3, 3), binom(k + 2, 2)
+    nqd = (k + 2) ** 3
+    per_elt = 3 * nqd * 8 + (16 + 96 + 32 + 96 + 16 + 64 + 16) + (d3 * (d3 + 1) + d3) * 8
+    return per_elt * nelt + nnzb * d2 * d2 * 8 + nfc * d2 * 8
+
+
+def cpu_baseline(cfg, sample=4096):
+    """The oracle, untuned, on a bounded sample of elements of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from hdg_inputs import kuhn_mesh
+    from oracle import globalsys as OG, local as OL, mesh as OM
+    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
+                  neumann_sides=cfg["neumann"])
+    ex = OM.expand(m.coordinates, m.elements, m.dirichlet, m.neumann)
+    pb = cfg["problem"]()
+    R = OL.rules(cfg["k"])
+    el = np.arange(min(sample, ex.nelt))
+    rng = np.random.default_rng(0)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        b = OL.local_blocks(ex, pb, R, el)
+        OL.condense(b)
+        b = OL.local_blocks(ex, pb, R, el)
+        q, u = OL.recover(b, rng.standard_normal((el.size, 4 * binom(cfg["k"] + 2, 2))))
+        OG.postprocess(ex, pb, R, q, u, el)
+        dt = time.perf_counter() - t0
+    return {"value": el.size / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {el.size} elements of the same mesh: element blocks + dense-LU condensation "
+                      f"(eq 5.5-5.6) + blocks again + reconstruction + postprocess, NumPy/SciPy FP64, "
+                      f"BLAS limited to 1 thread; {dt:.1f} s"}
+
+
+def traffic_record(kernel_src_sha):
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except Exception:
+        return None
+    if rec.get("source_sha") != kernel_src_sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def solve_metric(args):
+    import torch
+    from hdg_inputs import config, kuhn_mesh
+    from paper_1305_1489_amd.driver import HDGSystem
+    cfg = config("lognormal")
+    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
+                  neumann_sides=cfg["neumann"])
+    S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, cfg["k"], cfg["problem"]())
+    out = {"workload": "lognormal: Kuhn 32^3 cube, 196608 tets, k=2, kappa=exp(1.5 g) (corr. length 0.1), c=0.1",
+           "metric": "solve time to rel.res 1e-10", "unit": "s", "unknowns": int(S.mesh.nfc * S.disc.d2)}
+    for prec, name in ((0, "fp64_block_jacobi"), (1, "fp32_refined")):
+        S.assemble()
+        S.uhat.zero_()
+        S.boundary()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = S.solve(rtol=1e-10, precision=prec, check_every=50)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": dt, "iterations": info["iterations"], "outer": info["outer"],
+                     "true_rel_residual": info["rel_residual"]}
+        log(f"solve {name}: {dt:.3f} s, {info['iterations']} it, relres {info['rel_residual']:.2e}")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="jitter_k3")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is documented "
+              f"in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from hdg_inputs import config, kuhn_mesh
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem
+
+    cfg = config(args.workload)
+    k = cfg["k"]
+    log(f"workload {args.workload}: n={cfg['n']} k={k}")
+    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
+                  neumann_sides=cfg["neumann"])
+    S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, cfg["problem"]())
+    nelt, nfc, nnzb = S.mesh.nelt, S.mesh.nfc, S.mesh.nnzb
+    log(f"nelt={nelt} nfc={nfc} nnzb={nnzb}")
+    # trace solution computed once, outside the timed region
+    S.assemble()
+    S.boundary()
+    info = S.solve(rtol=1e-10, check_every=50)
+    uhat = S.uhat.clone()
+    log(f"precomputed uhat: {info['iterations']} PCG iterations, relres {info['rel_residual']:.2e}")
+    uhat_bc = torch.empty_like(uhat)
+    q = torch.empty((nelt, 3, S.disc.d3), dtype=torch.float64, device="cuda")
+    u = torch.empty((nelt, S.disc.d3), dtype=torch.float64, device="cuda")
+    us = torch.empty((nelt, S.disc.d3p), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        L.hdg_assemble_condense(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors)
+        if ev is not None:
+            ev[1].record(stream)
+        L.hdg_boundary(S.disc, S.mesh, S.uD, S.gN, S.H, S.F, uhat_bc)
+        if ev is not None:
+            ev[2].record(stream)
+        L.hdg_recover(S.disc, S.mesh, S.kappa, S.tau, S.factors, uhat, q, u, us)
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for i in range(args.steps):
+        step(evs[i])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms = total_ms / args.steps
+    cond_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    bc_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    rec_ms = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    log(f"step {ms:.3f} ms: condense {cond_ms:.3f}, boundary {bc_ms:.3f}, recover {rec_ms:.3f}")
+    fl_c, fl_r = algorithmic_flops(k)
+    ach_c = fl_c * nelt / (cond_ms * 1e-3) / 1e12
+    ach_r = fl_r * nelt / (rec_ms * 1e-3) / 1e12
+    src = open(os.path.join(ROOT, "paper_1305_1489_amd", "csrc", "condense.hip"), "rb").read()
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    peak = 78.6
+    roofline = {"kernel": "k_condense (hdg_assemble_condense)", "bound": "alu", "achieved": round(ach_c, 3),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach_c / peak, 4),
+                "traffic": traffic_record(sha),
+                "algorithmic_flops_per_element": fl_c, "elements_per_launch": nelt,
+                "avg_launch_ms": round(cond_ms, 4),
+                "algorithmic_bytes_per_launch": algorithmic_bytes(k, nelt, nfc, nnzb),
+                "recover": {"achieved": round(ach_r, 3), "unit": "TFLOP/s", "avg_launch_ms": round(rec_ms, 4),
+                            "algorithmic_flops_per_element": fl_r}}
+    result = {
+        "metric": "elements/s for assemble+condense+recover at k=3",
+        "value": nelt / (ms * 1e-3),
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: Kuhn {cfg['n']}^3 unit cube, {nelt} tets, k={k}, "
+                               f"interior jitter {cfg['jitter']}h, kappa=1+0.5 sin(2pi x)cos(2pi y), c=1+|x|^2, "
+                               f"tau=1, Dirichlet x=0,1, Neumann elsewhere",
+                   "nelt": nelt, "k": k, "nfc": nfc, "nnzb": nnzb,
+                   "stage_ms": {"assemble_condense": cond_ms, "boundary": bc_ms, "recover_postprocess": rec_ms}},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(cfg)
+    if not args.no_solve:
+        log("solve metric ...")
+        result["solve"] = solve_metric(args)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
