@@ -59,8 +59,9 @@ hdg_status hdg_disc_create(int k, int nq, hdg_disc** out) {
   const auto& o = h.off;
   const double* b = d->d_tables;
   d->dev = Tables{b + o.vol_w, b + o.lambda, b + o.P, b + o.Pg, b + o.tri_w, b + o.xi, b + o.D,
-                  b + o.Chat, b + o.PP, b + o.DP, b + o.P1g, b + o.Shat};
-  d->factor_len = h.d3 * (h.d3 + 1) + h.d3;
+                  b + o.Chat, b + o.PP, b + o.DP, b + o.P1g, b + o.Shat, b + o.Pt, b + o.ChatT,
+                  b + o.PPt, b + o.DPT};
+  d->factor_len = tile_factor_len(k) ? tile_factor_len(k) : h.d3 * (h.d3 + 1) + h.d3;
   *out = d;
   return HDG_OK;
 }

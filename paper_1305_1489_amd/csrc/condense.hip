@@ -216,9 +216,19 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
   return HDG_OK;
 }
 
+}  // namespace
+
+hdg_status dispatch_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                                  const double* f, const double* tau, double* H, double* F, double* factors,
+                                  const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s);
+
+namespace {
+
 hdg_status dispatch_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
                              const double* f, const double* tau, double* H, double* F, double* factors,
                              const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s) {
+  if (disc->host.k >= 1 && disc->host.k <= 3)
+    return dispatch_condense_tile(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
   switch (disc->host.k) {
     case 0: return run_condense<0>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
     case 1: return run_condense<1>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);

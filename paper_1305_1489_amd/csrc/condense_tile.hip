@@ -1,0 +1,365 @@
+// Assembly + static condensation + scatter on the FP64 matrix cores (degrees 1..3).
+//
+// Same mathematics as k_condense (Sections 3-6; eq 3.55, 3.56, 4.5, 4.8, 4.10, 5.1-5.6,
+// 6.5), organised as chains of 4x4x4 MFMA tile products with four elements per wavefront
+// (one per matrix-core block).  The element dimension d3 is zero-padded to a multiple of
+// 4 (padded diagonal entries of the SPD blocks set to 1); the trace dimension m = 4 d2 is
+// always a multiple of 4 and is tiled without padding (a tile may straddle two faces, so
+// face-dependent factors are applied per lane).
+//   Gram      M  = P^T diag(|K| w / kappa) P,  Mc = P^T diag(|K| w c) P,  f = P^T (|K| w f)
+//             (the quadrature index is the contraction dimension), + tauPP = sum_l T_l PP_l
+//   Cholesky  M = U^T U (blocked, upper tiles in registers)
+//   Z         = U^{-T} DP^T                   (block forward substitution, all faces)
+//   for s in x, y, z:
+//     W_s     = U^{-T} C_s^T,  C_s^T = sum_h a_{sh} Chat^{h T}
+//     S      += W_s^T W_s
+//     B      += n_{l s} W_s^T Z_l             (face l's columns)
+//   B        += T_l DP_l^T
+//   Cholesky  Mc + tauPP + sum W^T W = Us^T Us;   V = Us^{-T} [B | f]
+//   C^K       = tauDD + (n_l . n_m) Z_l^T Z_m - V^T V,   Cf^K = V^T (Us^{-T} f)
+// Each finished 4x4 tile of C^K is scattered straight into H (upper triangle mirrored,
+// so H stays exactly symmetric); diagonal face blocks and F take atomic adds onto zeros.
+// The factor store keeps U, Us (packed upper tiles) and f (tiles, column 0) per element.
+#include "tile.h"
+
+namespace hdg {
+namespace {
+
+template <int K>
+struct TD {
+  static constexpr int D3 = dim3(K), D2 = dim2(K), M = 4 * D2, NQD = (K + 2) * (K + 2) * (K + 2);
+  static constexpr int T = (D3 + 3) / 4, MT = D2, QT = (NQD + 3) / 4;
+  static constexpr int D3P4 = 4 * T, D2P4 = (D2 + 3) / 4 * 4, NQP = 4 * QT, NU = T * (T + 1) / 2;
+  static constexpr int FACTOR_LEN = (2 * NU + T) * 16;
+};
+
+enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_LEN = 43 };
+
+template <int K>
+__global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+                                                      const double* __restrict__ cco, const double* __restrict__ fco,
+                                                      const double* __restrict__ tau, double* __restrict__ H,
+                                                      double* __restrict__ F, double* __restrict__ factors,
+                                                      const int* __restrict__ elems, int nwork,
+                                                      double* __restrict__ Cout, double* __restrict__ Cfout) {
+  using D = TD<K>;
+  constexpr int T = D::T, MT = D::MT, QT = D::QT, D3 = D::D3, D2 = D::D2, M = D::M;
+  constexpr int NQD = D::NQD, NQP = D::NQP, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
+  __shared__ double s_w[3][4][NQP];
+  __shared__ double s_geo[4][G_LEN];
+  __shared__ int s_mu[4][4];
+  __shared__ int s_slot[4][16];
+  __shared__ int s_fbe[4][4];
+  __shared__ int s_E[4];
+  __shared__ double s_x[64];
+  __shared__ double s_Z[T * MT][64];  // Z tiles, lane-contiguous
+  const int lane = threadIdx.x;
+  const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
+
+  for (int w0 = blockIdx.x * 4; w0 < nwork; w0 += gridDim.x * 4) {
+    __syncthreads();
+    if (lane < 4) {
+      const int wi = w0 + lane;
+      int E = -1;
+      if (wi < nwork) {
+        E = elems ? elems[wi] : wi;
+        if (E < 0 || E >= mesh.nelt) E = -1;
+      }
+      s_E[lane] = E;
+      ElemGeom g;
+      if (E >= 0) {
+        load_geometry(E, mesh, tau, g);
+      } else {
+        g = ElemGeom{};
+        g.vol = 1.0;
+        g.det = 6.0;
+      }
+      for (int i = 0; i < 9; ++i) s_geo[lane][G_A + i] = g.a[i / 3][i % 3];
+      s_geo[lane][G_DET] = g.det;
+      s_geo[lane][G_VOL] = g.vol;
+      for (int i = 0; i < 12; ++i) s_geo[lane][G_N + i] = g.n[i / 3][i % 3];
+      for (int l = 0; l < 4; ++l) {
+        s_geo[lane][G_T + l] = g.T[l];
+        s_mu[lane][l] = g.mu[l];
+        s_fbe[lane][l] = E >= 0 ? mesh.d_facebyele[4 * E + l] : 0;
+        for (int m = 0; m < 4; ++m) {
+          s_geo[lane][G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
+          s_slot[lane][4 * l + m] = (E >= 0 && !Cout) ? mesh.d_slot[16 * E + 4 * l + m] : 0;
+        }
+      }
+    }
+    __syncthreads();
+    for (int idx = lane; idx < 4 * NQP; idx += 64) {
+      const int e = idx / NQP, q = idx % NQP;
+      const int E = s_E[e];
+      double wk = 0, wc = 0, wf = 0;
+      if (E >= 0 && q < NQD) {
+        const double wq = s_geo[e][G_VOL] * tb.vol_w[q];
+        const size_t o = (size_t)E * NQD + q;
+        wk = wq / kappa[o];
+        wc = wq * cco[o];
+        wf = wq * fco[o];
+      }
+      s_w[0][e][q] = wk;
+      s_w[1][e][q] = wc;
+      s_w[2][e][q] = wf;
+    }
+    __syncthreads();
+    const int E = s_E[blk];
+    const double* geo = s_geo[blk];
+
+    // ---- Gram matrices and the load vector (contraction over the quadrature points)
+    double Ma[NU], Sa[NU], fa[T];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) Ma[i] = Sa[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < T; ++i) fa[i] = 0.0;
+    for (int kq = 0; kq < QT; ++kq) {
+      const int q = 4 * kq + r;
+      double pv[T];
+#pragma unroll
+      for (int J = 0; J < T; ++J) pv[J] = tb.Pt[q * D3P4 + 4 * J + c];
+      const double wk = s_w[0][blk][q], wc = s_w[1][blk][q], wf = s_w[2][blk][q];
+#pragma unroll
+      for (int N = 0; N < T; ++N) {
+        const double yk = wk * pv[N], yc = wc * pv[N];
+#pragma unroll
+        for (int I = 0; I <= N; ++I) {
+          Ma[utile(I, N, T)] = mfma4(pv[I], yk, Ma[utile(I, N, T)]);
+          Sa[utile(I, N, T)] = mfma4(pv[I], yc, Sa[utile(I, N, T)]);
+        }
+      }
+      const double yf = c == 0 ? wf : 0.0;
+#pragma unroll
+      for (int I = 0; I < T; ++I) fa[I] = mfma4(pv[I], yf, fa[I]);
+    }
+    // tau PP (eq 4.5) and identity on the padded / unused part
+    {
+      const double T0 = geo[G_T], T1 = geo[G_T + 1], T2 = geo[G_T + 2], T3 = geo[G_T + 3];
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int N = I; N < T; ++N) {
+          const int o = (4 * I + r) * D3P4 + 4 * N + c;
+          constexpr int L4 = D3P4 * D3P4;
+          Sa[utile(I, N, T)] += T0 * tb.PPt[o] + T1 * tb.PPt[L4 + o] + T2 * tb.PPt[2 * L4 + o] + T3 * tb.PPt[3 * L4 + o];
+          if (I == N && r == c && (4 * I + r >= D3 || E < 0)) {
+            Ma[utile(I, N, T)] = 1.0;
+            Sa[utile(I, N, T)] = 1.0;
+          } else if (E < 0) {
+            Ma[utile(I, N, T)] = 0.0;
+            Sa[utile(I, N, T)] = 0.0;
+          }
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double Vd[T];
+    tile_cholesky<T>(Ma, Vd, s_x);  // Ma <- U, M = U^T U
+    double Ui[NU];
+    tile_upper_inverse<T>(Ma, Vd, Ui);  // Ui = U^{-1}; L^{-1} = Ui^T
+    __builtin_amdgcn_sched_barrier(0);
+
+    // the trace-dimension column of lane c in tile N is j = 4N + c (face j / d2)
+    // ---- Z = L^{-1} DP^T: Z(K,N) = sum_{J<=K} L^{-1}(K,J) DP^T(J,N)
+#pragma unroll
+    for (int N = 0; N < MT; ++N) {
+      const int j = 4 * N + c, l = j / D2, i = j % D2;
+      const double* dpt = tb.DPT + (size_t)(s_mu[blk][l] * 4 + l) * D3P4 * D2P4 + i;
+      double rhs[T];
+#pragma unroll
+      for (int J = 0; J < T; ++J) rhs[J] = dpt[(4 * J + r) * D2P4];
+#pragma unroll
+      for (int Kk = 0; Kk < T; ++Kk) {
+        double acc = 0.0;
+#pragma unroll
+        for (int J = 0; J <= Kk; ++J) acc = mfma4(Ui[utile(J, Kk, T)], rhs[J], acc);
+        s_Z[Kk * MT + N][lane] = acc;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- W_s = L^{-1} C_s^T streamed by tile rows: S += W_s^T W_s, B += n_{ls} W_s^T Z_l
+    double B[T][MT];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+      for (int N = 0; N < MT; ++N) B[I][N] = 0.0;
+    constexpr int L3 = D3P4 * D3P4;
+    for (int s = 0; s < 3; ++s) {
+      const double a0 = geo[G_A + 3 * s], a1 = geo[G_A + 3 * s + 1], a2 = geo[G_A + 3 * s + 2];
+      double nls[MT];
+#pragma unroll
+      for (int N = 0; N < MT; ++N) nls[N] = geo[G_N + 3 * ((4 * N + c) / D2) + s];
+#pragma unroll
+      for (int Kk = 0; Kk < T; ++Kk) {
+        double Wr[T];
+#pragma unroll
+        for (int N = 0; N < T; ++N) {
+          double acc = 0.0;
+#pragma unroll
+          for (int J = 0; J <= Kk; ++J) {
+            const int o = (4 * J + r) * D3P4 + 4 * N + c;
+            const double ct = a0 * tb.ChatT[o] + a1 * tb.ChatT[L3 + o] + a2 * tb.ChatT[2 * L3 + o];
+            acc = mfma4(Ui[utile(J, Kk, T)], ct, acc);
+          }
+          Wr[N] = acc;
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+          for (int N = I; N < T; ++N) Sa[utile(I, N, T)] = mfma4(Wr[I], Wr[N], Sa[utile(I, N, T)]);
+#pragma unroll
+        for (int N = 0; N < MT; ++N) {
+          const double zs = nls[N] * s_Z[Kk * MT + N][lane];
+#pragma unroll
+          for (int I = 0; I < T; ++I) B[I][N] = mfma4(Wr[I], zs, B[I][N]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // B += T_l DP_l^T
+#pragma unroll
+    for (int N = 0; N < MT; ++N) {
+      const int j = 4 * N + c, l = j / D2, i = j % D2;
+      const double Tl = geo[G_T + l];
+      const double* dpt = tb.DPT + (size_t)(s_mu[blk][l] * 4 + l) * D3P4 * D2P4 + i;
+#pragma unroll
+      for (int I = 0; I < T; ++I) B[I][N] += Tl * dpt[(4 * I + r) * D2P4];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    // ---- factors kept for the reconstruction: U^{-1}, Us^{-1} (packed upper tiles), f
+    double* fac = (factors && E >= 0) ? factors + (size_t)E * D::FACTOR_LEN : nullptr;
+    const int ent = r * 4 + c;
+    if (fac) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) fac[i * 16 + ent] = Ui[i];
+#pragma unroll
+      for (int i = 0; i < T; ++i) fac[(2 * NU + i) * 16 + ent] = fa[i];
+    }
+
+    // ---- Cholesky of S, Us^{-1}, and V = Ls^{-1} [B | f] (rows from the bottom, in place)
+    double Vs[T];
+    tile_cholesky<T>(Sa, Vs, s_x);
+    tile_upper_inverse<T>(Sa, Vs, Ui);  // Ui now holds Us^{-1}
+    if (fac) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) fac[(NU + i) * 16 + ent] = Ui[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int Kk = T - 1; Kk >= 0; --Kk) {
+#pragma unroll
+      for (int N = 0; N < MT; ++N) {
+        double acc = 0.0;
+#pragma unroll
+        for (int J = 0; J <= Kk; ++J) acc = mfma4(Ui[utile(J, Kk, T)], B[J][N], acc);
+        B[Kk][N] = acc;
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int J = 0; J <= Kk; ++J) acc = mfma4(Ui[utile(J, Kk, T)], fa[J], acc);
+      fa[Kk] = acc;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- C^K tiles and Cf^K, straight to H and F (or to the export arrays)
+#pragma unroll
+    for (int I = 0; I < MT; ++I) {
+      const int a = 4 * I + r, la = a / D2, ia = a % D2;
+      double zi[T];
+#pragma unroll
+      for (int Kk = 0; Kk < T; ++Kk) zi[Kk] = s_Z[Kk * MT + I][lane];
+#pragma unroll
+      for (int N = I; N < MT; ++N) {
+        __builtin_amdgcn_sched_barrier(0);
+        double g1 = 0.0, g2 = 0.0;
+#pragma unroll
+        for (int Kk = 0; Kk < T; ++Kk) {
+          g1 = mfma4(zi[Kk], s_Z[Kk * MT + N][lane], g1);
+          g2 = mfma4(B[Kk][I], B[Kk][N], g2);
+        }
+        const int b = 4 * N + c, lb = b / D2, ib = b % D2;
+        double val = geo[G_NN + 4 * la + lb] * g1 - g2;
+        if (a == b) val += geo[G_T + la];
+        if (E >= 0 && (I != N || r <= c)) {
+          if (Cout) {
+            const size_t base = (size_t)(w0 + blk) * M * M;
+            Cout[base + (size_t)a * M + b] = val;
+            Cout[base + (size_t)b * M + a] = val;
+          } else {
+            const size_t s1 = s_slot[blk][4 * la + lb];
+            if (la == lb) {
+              unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
+              if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
+            } else {
+              const size_t s2 = s_slot[blk][4 * lb + la];
+              H[(s1 * D2 + ia) * D2 + ib] = val;
+              H[(s2 * D2 + ib) * D2 + ia] = val;
+            }
+          }
+        }
+      }
+      double h = 0.0;
+#pragma unroll
+      for (int Kk = 0; Kk < T; ++Kk) h = mfma4(B[Kk][I], fa[Kk], h);
+      if (E >= 0 && c == 0) {
+        if (Cfout)
+          Cfout[(size_t)(w0 + blk) * M + a] = h;
+        else
+          unsafeAtomicAdd(&F[(size_t)s_fbe[blk][la] * D2 + ia], h);
+      }
+    }
+  }
+}
+
+template <int D2>
+__global__ void k_zero_diag_t(const int* __restrict__ diag, int nfc, double* __restrict__ H, double* __restrict__ F) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= (size_t)nfc * D2 * D2) return;
+  const size_t f = i / (D2 * D2), e = i % (D2 * D2);
+  H[(size_t)diag[f] * D2 * D2 + e] = 0.0;
+  if (e < D2) F[f * D2 + e] = 0.0;
+}
+
+template <int K>
+hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                             const double* f, const double* tau, double* H, double* F, double* factors,
+                             const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s) {
+  using D = TD<K>;
+  if (!Cout) {
+    const size_t tot = (size_t)mesh->nfc * D::D2 * D::D2;
+    k_zero_diag_t<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, (int)mesh->nfc, H, F);
+    HDG_CHECK_LAUNCH("k_zero_diag");
+  }
+  if (n == 0) return HDG_OK;
+  const int64_t groups = (n + 3) / 4;
+  const int grid = (int)std::min<int64_t>(groups, 1 << 20);
+  k_condense_tile<K><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout);
+  HDG_CHECK_LAUNCH("k_condense_tile");
+  return HDG_OK;
+}
+
+}  // namespace
+
+int tile_factor_len(int k) {
+  switch (k) {
+    case 1: return TD<1>::FACTOR_LEN;
+    case 2: return TD<2>::FACTOR_LEN;
+    case 3: return TD<3>::FACTOR_LEN;
+  }
+  return 0;
+}
+
+hdg_status dispatch_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                                  const double* f, const double* tau, double* H, double* F, double* factors,
+                                  const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s) {
+  switch (disc->host.k) {
+    case 1: return run_condense_tile<1>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
+    case 2: return run_condense_tile<2>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
+    case 3: return run_condense_tile<3>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "tile condensation: unsupported degree");
+}
+
+}  // namespace hdg

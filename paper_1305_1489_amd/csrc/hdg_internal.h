@@ -20,6 +20,8 @@ inline constexpr int tri(int n) { return n * (n + 1) / 2; }
 // Offsets (in doubles) of every reference table inside the device table buffer.
 struct TableOffsets {
   int vol_pts, vol_w, lambda, P, Pg, tri_pts, tri_w, xi, D, Pface, Chat, PP, DP, P1g, Shat;
+  // zero-padded copies for the 4x4-tile kernels (dimensions rounded up to multiples of 4)
+  int Pt, ChatT, PPt, DPT;
   int total;
 };
 
@@ -37,15 +39,24 @@ struct Tables {
   const double* DP;      // [6][4][d2][d3] (eq 4.10)
   const double* P1g;     // [3][nqd][d3p] gradients of the degree k+1 basis
   const double* Shat;    // [6][d3p][d3p]
+  const double* Pt;      // [nqp][d3p4]   P padded (nqp = nqd rounded up to 4, d3p4 = d3 rounded up)
+  const double* ChatT;   // [3][d3p4][d3p4] transposes of Chat^h, padded
+  const double* PPt;     // [4][d3p4][d3p4] PP_l padded
+  const double* DPT;     // [6][4][d3p4][d2p4] transposes of DP_{mu,l}, padded
 };
 
 struct HostTables {
   int k, nq, d3, d2, d3p, nqd, nqd2;
+  int d3p4, d2p4, nqp;  // padded sizes
   TableOffsets off;
   std::vector<double> data;
 };
 
 HostTables build_tables(int k, int nq);
+
+// Doubles per element of the factor store of the tile kernels (0 where the degree uses
+// the packed layout of the per-element kernel).
+int tile_factor_len(int k);
 
 }  // namespace hdg
 

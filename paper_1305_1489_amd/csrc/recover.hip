@@ -10,7 +10,7 @@
 // G = det(B) B^{-1} B^{-T}; rhs_i = -sum_q |K| w_q kappa_q^{-1} (B^{-1} q_h(x_q)) . gradhat P_i;
 // the hierarchical orthonormal basis makes the mean condition fix u*_1 = u_1, and the
 // stiffness system is solved (Cholesky) on the remaining modes.
-#include "device_common.h"
+#include "tile.h"
 
 namespace hdg {
 namespace {
@@ -49,7 +49,30 @@ __device__ inline void solve_upper_t(const double* L, int ld, double* x, int str
   }
 }
 
-template <int K>
+// x <- A^{-1} x for an SPD block A, given either its lower Cholesky factor L (A = L L^T,
+// two triangular solves) or, for the tile kernels' factor store, Ui = U^{-1} with
+// A = U^T U stored as an upper matrix (two triangular products: A^{-1} = Ui Ui^T).
+template <int N, bool INVERSE>
+__device__ inline void spd_apply(const double* F, double* x) {
+  if constexpr (INVERSE) {
+    double y[N];
+    for (int i = 0; i < N; ++i) {  // y = Ui^T x
+      double s = 0;
+      for (int j = 0; j <= i; ++j) s += F[j * N + i] * x[j];
+      y[i] = s;
+    }
+    for (int i = 0; i < N; ++i) {  // x = Ui y
+      double s = 0;
+      for (int j = i; j < N; ++j) s += F[i * N + j] * y[j];
+      x[i] = s;
+    }
+  } else {
+    solve_lower<N>(F, N, x, 1);
+    solve_upper_t<N>(F, N, x, 1);
+  }
+}
+
+template <int K, bool TILE>
 __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                 const double* __restrict__ tau, const double* __restrict__ factors,
                                                 const double* __restrict__ uhat, double* __restrict__ qout,
@@ -61,12 +84,22 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
   for (int E = blockIdx.x; E < mesh.nelt; E += gridDim.x) {
     ElemGeom g;
     load_geometry(E, mesh, tau, g);
-    const double* fa = factors + (size_t)E * (D3 * (D3 + 1) + D3);
+    constexpr int TT = (D3 + 3) / 4, NU = TT * (TT + 1) / 2;
+    constexpr int FLEN = TILE ? (2 * NU + TT) * 16 : D3 * (D3 + 1) + D3;
+    const double* fa = factors + (size_t)E * FLEN;
     for (int idx = t; idx < D3 * D3; idx += nt) {
       const int i = idx / D3, j = idx % D3;
-      if (j > i) continue;
-      sm.L[idx] = fa[i * (i + 1) / 2 + j];
-      sm.LS[idx] = fa[D3 * (D3 + 1) / 2 + i * (i + 1) / 2 + j];
+      if constexpr (TILE) {
+        // upper inverses U^{-1}, Us^{-1} stored as packed upper 4x4 tiles: entry (i, j), j >= i
+        if (j < i) continue;
+        const int o = utile(i / 4, j / 4, TT) * 16 + (i % 4) * 4 + (j % 4);
+        sm.L[idx] = fa[o];
+        sm.LS[idx] = fa[NU * 16 + o];
+      } else {
+        if (j > i) continue;
+        sm.L[idx] = fa[i * (i + 1) / 2 + j];
+        sm.LS[idx] = fa[D3 * (D3 + 1) / 2 + i * (i + 1) / 2 + j];
+      }
     }
     for (int idx = t; idx < 4 * D2; idx += nt)
       sm.uh[idx] = uhat[(size_t)mesh.d_facebyele[4 * E + idx / D2] * D2 + idx % D2];
@@ -91,8 +124,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
     __syncthreads();
     // x_s <- M^{-1} r_s  (three columns)
     if (t < 3) {
-      solve_lower<D3>(sm.L, D3, sm.x + t * D3, 1);
-      solve_upper_t<D3>(sm.L, D3, sm.x + t * D3, 1);
+      spd_apply<D3, TILE>(sm.L, sm.x + t * D3);
     }
     __syncthreads();
     // v_h = sum_s a[s][h] (M^{-1} r_s)
@@ -103,7 +135,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
     __syncthreads();
     // rhs_u = f + sum_l T_l t_l + sum_h Chat^h v_h
     for (int i = t; i < D3; i += nt) {
-      double s = fa[D3 * (D3 + 1) + i];
+      double s = TILE ? fa[(2 * NU + i / 4) * 16 + (i % 4) * 4] : fa[D3 * (D3 + 1) + i];
       for (int l = 0; l < 4; ++l) s += g.T[l] * sm.tl[l * D3 + i];
       for (int h = 0; h < 3; ++h)
         for (int j = 0; j < D3; ++j) s += tb.Chat[(h * D3 + i) * D3 + j] * sm.v[h * D3 + j];
@@ -111,8 +143,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
     }
     __syncthreads();
     if (t == 0) {
-      solve_lower<D3>(sm.LS, D3, sm.u, 1);
-      solve_upper_t<D3>(sm.LS, D3, sm.u, 1);
+      spd_apply<D3, TILE>(sm.LS, sm.u);
     }
     __syncthreads();
     // x_s = C_s^T u - r_s with (C_s^T u)_i = sum_h a[s][h] sum_j Chat^h[j][i] u_j
@@ -129,8 +160,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
     }
     __syncthreads();
     if (t < 3) {
-      solve_lower<D3>(sm.L, D3, sm.x + t * D3, 1);
-      solve_upper_t<D3>(sm.L, D3, sm.x + t * D3, 1);
+      spd_apply<D3, TILE>(sm.L, sm.x + t * D3);
     }
     __syncthreads();
     for (int idx = t; idx < 3 * D3; idx += nt) qout[(size_t)E * 3 * D3 + idx] = sm.x[idx];
@@ -186,7 +216,7 @@ template <int K>
 hdg_status run_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
                        const double* factors, const double* uhat, double* q, double* u, double* us, hipStream_t s) {
   const int grid = (int)std::min<int64_t>(mesh->nelt, 1 << 20);
-  k_recover<K><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u, us);
+  k_recover<K, (K >= 1 && K <= 3)><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u, us);
   HDG_CHECK_LAUNCH("k_recover");
   return HDG_OK;
 }

@@ -273,6 +273,14 @@ HostTables build_tables(int k, int nq) {
   o.DP = take(24 * d2 * d3);
   o.P1g = take(3 * nqd * d3p);
   o.Shat = take(6 * d3p * d3p);
+  const int D3P4 = (d3 + 3) / 4 * 4, D2P4 = (d2 + 3) / 4 * 4, NQP = (nqd + 3) / 4 * 4;
+  t.d3p4 = D3P4;
+  t.d2p4 = D2P4;
+  t.nqp = NQP;
+  o.Pt = take(NQP * D3P4);
+  o.ChatT = take(3 * D3P4 * D3P4);
+  o.PPt = take(4 * D3P4 * D3P4);
+  o.DPT = take(24 * D3P4 * D2P4);
   o.total = pos;
   t.data.assign(pos, 0.0);
   auto put = [&](int off, const std::vector<ld>& v) {
@@ -304,6 +312,17 @@ HostTables build_tables(int k, int nq) {
   put(o.DP, DP);
   put(o.P1g, P1g);
   put(o.Shat, Shat);
+  for (int q = 0; q < nqd; ++q)
+    for (int j = 0; j < d3; ++j) t.data[o.Pt + q * D3P4 + j] = (double)P[q * d3 + j];
+  for (int h = 0; h < 3; ++h)
+    for (int i = 0; i < d3; ++i)
+      for (int j = 0; j < d3; ++j) t.data[o.ChatT + (h * D3P4 + i) * D3P4 + j] = (double)Chat[(h * d3 + j) * d3 + i];
+  for (int l = 0; l < 4; ++l)
+    for (int i = 0; i < d3; ++i)
+      for (int j = 0; j < d3; ++j) t.data[o.PPt + (l * D3P4 + i) * D3P4 + j] = (double)PP[(l * d3 + i) * d3 + j];
+  for (int ml = 0; ml < 24; ++ml)
+    for (int i = 0; i < d3; ++i)
+      for (int j = 0; j < d2; ++j) t.data[o.DPT + (ml * D3P4 + i) * D2P4 + j] = (double)DP[(ml * d2 + j) * d3 + i];
   return t;
 }
 

@@ -1,0 +1,135 @@
+// 4x4-tile dense linear algebra on the FP64 matrix cores of gfx950 (v_mfma_f64_4x4x4f64).
+//
+// The instruction runs four independent 4x4x4 products per wavefront, one per group of 16
+// lanes ("block").  Lane l belongs to block (l >> 2) & 3 and, inside a tile, to row
+// r = l >> 4 and column c = l & 3.  With every operand stored in this layout ("canonical
+// tile": the lane holds X[r][c]), the instruction computes
+//     D = X^T Y + C
+// for the two 4x4 source tiles X, Y and the accumulator C.  Each block carries one
+// element, so a wavefront works on four elements at once and every per-element matrix is
+// an array of tiles, one double per lane per tile.
+//
+// A product A B of tiled matrices therefore needs the tiles of A^T (A "in transposed
+// storage") and B in normal storage; Gram products X^T Y need both in normal storage.
+#pragma once
+
+#include "device_common.h"
+
+namespace hdg {
+
+__device__ __forceinline__ double mfma4(double x, double y, double acc) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(x, y, acc, 0, 0, 0);
+}
+
+// Index of tile (I, N), I <= N, in the packed upper triangle of a T x T tile matrix.
+__host__ __device__ constexpr int utile(int I, int N, int T) { return I * T - I * (I - 1) / 2 + (N - I); }
+
+// Upper Cholesky of one 4x4 SPD tile per block (A = U^T U) and the inverse V = U^{-1}.
+// Every lane of the block reads the whole tile through LDS and factors it redundantly;
+// it returns its own entries U[r][c] and V[r][c].  xch: 64 doubles of LDS.
+__device__ __forceinline__ void diag_chol4(double a_rc, double* xch, double& u_rc, double& v_rc) {
+  const int lane = threadIdx.x & 63, r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
+  __syncthreads();
+  xch[blk * 16 + r * 4 + c] = a_rc;
+  __syncthreads();
+  double a[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[i][j] = xch[blk * 16 + i * 4 + j];
+  double u[4][4] = {}, v[4][4] = {};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double s = a[i][i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= u[k][i] * u[k][i];
+    u[i][i] = sqrt(s);
+    const double inv = 1.0 / u[i][i];
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) {
+      double t = a[i][j];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= u[k][i] * u[k][j];
+      u[i][j] = t * inv;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[j][j] = 1.0 / u[j][j];
+#pragma unroll
+    for (int i = j - 1; i >= 0; --i) {
+      double t = 0;
+#pragma unroll
+      for (int k = i + 1; k <= j; ++k) t += u[i][k] * v[k][j];
+      v[i][j] = -t / u[i][i];
+    }
+  }
+  double ur = 0, vr = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (i == r && j == c) {
+        ur = u[i][j];
+        vr = v[i][j];
+      }
+  u_rc = ur;
+  v_rc = vr;
+}
+
+// Transpose of each block's 4x4 tile: the lane (r, c) receives X[c][r] (cross-lane
+// permute, no LDS storage).
+__device__ __forceinline__ double tile_transpose(double v) {
+  const int lane = threadIdx.x & 63;
+  const int src = 16 * (lane & 3) + (lane & 12) + (lane >> 4);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Inverse of the upper Cholesky factor: given U (packed upper tiles) and Vd[J] =
+// U(J,J)^{-1}, returns Ui = U^{-1} as packed upper tiles.  Computed as L^{-1} = U^{-T} by
+// block forward substitution on the identity (natural operand forms for the matrix
+// cores), then each tile transposed into place.
+template <int T>
+__device__ __forceinline__ void tile_upper_inverse(const double (&U)[T * (T + 1) / 2], const double (&Vd)[T],
+                                                   double (&Ui)[T * (T + 1) / 2]) {
+  const int lane = threadIdx.x & 63;
+  const double eye = ((lane >> 4) == (lane & 3)) ? 1.0 : 0.0;
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    double X[T];
+#pragma unroll
+    for (int I = J; I < T; ++I) {
+      double acc = 0.0;
+#pragma unroll
+      for (int K = J; K < I; ++K) acc = mfma4(U[utile(K, I, T)], X[K], acc);
+      X[I] = mfma4(Vd[I], (I == J ? eye : 0.0) - acc, 0.0);  // X = L^{-1}(:, J)
+    }
+#pragma unroll
+    for (int I = J; I < T; ++I) Ui[utile(J, I, T)] = tile_transpose(X[I]);  // U^{-1}(J,I) = L^{-1}(I,J)^T
+  }
+}
+
+// Blocked upper Cholesky in place on the packed upper tiles A (T x T tiles, symmetric
+// matrix): afterwards A holds U (A = U^T U) and Vd[J] = U(J,J)^{-1}.
+template <int T>
+__device__ __forceinline__ void tile_cholesky(double (&A)[T * (T + 1) / 2], double (&Vd)[T], double* xch) {
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    double u, v;
+    diag_chol4(A[utile(J, J, T)], xch, u, v);
+    A[utile(J, J, T)] = u;
+    Vd[J] = v;
+    // panel: U(J,I) = U(J,J)^{-T} A(J,I)
+#pragma unroll
+    for (int I = J + 1; I < T; ++I) A[utile(J, I, T)] = mfma4(v, A[utile(J, I, T)], 0.0);
+    // trailing update: A(I',I) -= U(J,I')^T U(J,I)
+#pragma unroll
+    for (int Ip = J + 1; Ip < T; ++Ip)
+#pragma unroll
+      for (int I = Ip; I < T; ++I) A[utile(Ip, I, T)] -= mfma4(A[utile(J, Ip, T)], A[utile(J, I, T)], 0.0);
+  }
+}
+
+}  // namespace hdg
