@@ -99,15 +99,17 @@ def cpu_baseline(cfg, sample=4096):
                       f"BLAS limited to 1 thread; {dt:.1f} s"}
 
 
-def traffic_record(kernel_src_sha):
+def traffic_record(kernel, kernel_src_sha):
+    """HBM bytes per launch from the committed counter summary (profiles/traffic.json), or
+    None when the kernel's source has changed since the counters were taken."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     try:
-        rec = json.load(open(p))
+        rec = json.load(open(p)).get(kernel)
     except Exception:
         return None
-    if rec.get("source_sha") != kernel_src_sha:
+    if not rec or rec.get("source_sha") != kernel_src_sha:
         return None
     return rec.get("bytes_per_launch")
 
@@ -145,6 +147,8 @@ def main():
     ap.add_argument("--workload", default="jitter_k3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is documented "
@@ -209,17 +213,33 @@ def main():
     fl_c, fl_r = algorithmic_flops(k)
     ach_c = fl_c * nelt / (cond_ms * 1e-3) / 1e12
     ach_r = fl_r * nelt / (rec_ms * 1e-3) / 1e12
-    src = open(os.path.join(ROOT, "paper_1305_1489_amd", "csrc", "condense.hip"), "rb").read()
-    sha = hashlib.sha256(src).hexdigest()[:16]
-    peak = 78.6
-    roofline = {"kernel": "k_condense (hdg_assemble_condense)", "bound": "alu", "achieved": round(ach_c, 3),
-                "peak": peak, "unit": "TFLOP/s", "frac": round(ach_c / peak, 4),
-                "traffic": traffic_record(sha),
-                "algorithmic_flops_per_element": fl_c, "elements_per_launch": nelt,
-                "avg_launch_ms": round(cond_ms, 4),
-                "algorithmic_bytes_per_launch": algorithmic_bytes(k, nelt, nfc, nnzb),
-                "recover": {"achieved": round(ach_r, 3), "unit": "TFLOP/s", "avg_launch_ms": round(rec_ms, 4),
-                            "algorithmic_flops_per_element": fl_r}}
+    peak = 78.6  # MI355X FP64: dense matrix and vector rate are both 78.6 TFLOP/s
+    tile = 1 <= k <= 3
+    kernels = {
+        "condense": {"kernel": "k_condense_tile" if tile else "k_condense", "call": "hdg_assemble_condense",
+                     "source": "condense_tile.hip" if tile else "condense.hip",
+                     "bound": "mfma" if tile else "alu", "achieved": round(ach_c, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(ach_c / peak, 4), "avg_launch_ms": round(cond_ms, 4),
+                     "algorithmic_flops_per_element": fl_c, "elements_per_launch": nelt,
+                     "algorithmic_bytes_per_launch": algorithmic_bytes(k, nelt, nfc, nnzb)},
+        "recover": {"kernel": "k_recover", "call": "hdg_recover", "source": "recover.hip", "bound": "alu",
+                    "achieved": round(ach_r, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach_r / peak, 4),
+                    "avg_launch_ms": round(rec_ms, 4), "algorithmic_flops_per_element": fl_r,
+                    "elements_per_launch": nelt},
+    }
+    for kk in kernels.values():
+        src = open(os.path.join(ROOT, "paper_1305_1489_amd", "csrc", kk["source"]), "rb").read()
+        kk["traffic"] = traffic_record(kk["kernel"], hashlib.sha256(src).hexdigest()[:16])
+    dom = "condense" if cond_ms >= rec_ms else "recover"
+    roofline = dict(kernels[dom])
+    roofline["other_kernels"] = {n: v for n, v in kernels.items() if n != dom}
+    if args.calibrate_copy:
+        x = torch.empty(args.calibrate_copy // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {x.numel() * 8} bytes read and written")
     result = {
         "metric": "elements/s for assemble+condense+recover at k=3",
         "value": nelt / (ms * 1e-3),

@@ -1,11 +1,15 @@
 // Reconstruction of (q, u) from the face traces (eq 5.3, Section 6 "Reconstruction") and
-// the local postprocess u* (eq 9.11), one wavefront per element.
+// the local postprocess u* (eq 9.11), one wavefront per element, every step spread over
+// the wavefront's lanes.
 //
-// With the factors kept by the condensation (L L^T = M_{1/kappa}, Ls Ls^T = S, and f):
+// With the factors kept by the condensation (M = M_{1/kappa}, S the u-Schur complement,
+// and f):
 //   t_l = DP_l^T uhat_l,   r_s = sum_l n_{l s} t_l,          (r_s = (n_sDP)^T u_dK)
 //   u   = S^{-1} ( f + sum_l T_l t_l + sum_s C_s M^{-1} r_s ),
 //   q_s = M^{-1} ( C_s^T u - r_s ),
-// which is the block elimination of A1 [q; u] = Af - A2 u_dK.
+// which is the block elimination of A1 [q; u] = Af - A2 u_dK.  The tile kernels (k = 1..3)
+// store the inverse upper Cholesky factors U^{-1}, Us^{-1} (A^{-1} = U^{-1} U^{-T}, two
+// triangular products); the per-element kernel (k = 0, 4) stores the lower factors.
 // Postprocess: S*_{ij} = int_K grad P_i . grad P_j = sum G_{hg} Shat^{hg} with
 // G = det(B) B^{-1} B^{-T}; rhs_i = -sum_q |K| w_q kappa_q^{-1} (B^{-1} q_h(x_q)) . gradhat P_i;
 // the hierarchical orthonormal basis makes the mean condition fix u*_1 = u_1, and the
@@ -22,8 +26,9 @@ struct RecoverSmem {
   double LS[Dm::D3 * Dm::D3];
   double uh[4 * Dm::D2];
   double tl[4 * Dm::D3];
-  double r[3 * Dm::D3];       // r_s, then M^{-1} r_s
-  double x[3 * Dm::D3];       // right-hand sides of the q solves, then q
+  double r[3 * Dm::D3];    // r_s
+  double x[3 * Dm::D3];    // right-hand sides of the M solves, then their solutions
+  double tmp[3 * Dm::D3];
   double u[Dm::D3];
   double v[3 * Dm::D3];
   double y[3 * Dm::NQD];
@@ -31,45 +36,78 @@ struct RecoverSmem {
   double rs[Dm::D3P];
 };
 
+// ---- wavefront-parallel dense kernels on LDS data (all lanes of the block take part)
+
+// Right-looking Cholesky of an N x N SPD matrix (leading dimension ld), lower factor.
 template <int N>
-__device__ inline void solve_lower(const double* L, int ld, double* x, int stride) {
-  for (int r = 0; r < N; ++r) {
-    double s = x[r * stride];
-    for (int k = 0; k < r; ++k) s -= L[r * ld + k] * x[k * stride];
-    x[r * stride] = s / L[r * ld + r];
+__device__ inline void par_cholesky(double* A, int ld) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < N; ++j) {
+    if (t == 0) A[j * ld + j] = sqrt(A[j * ld + j]);
+    __syncthreads();
+    const double inv = 1.0 / A[j * ld + j];
+    for (int i = j + 1 + t; i < N; i += nt) A[i * ld + j] *= inv;
+    __syncthreads();
+    const int w = N - j - 1;
+    for (int p = t; p < w * w; p += nt) {
+      const int i = j + 1 + p / w, k = j + 1 + p % w;
+      if (k <= i) A[i * ld + k] -= A[i * ld + j] * A[k * ld + j];
+    }
+    __syncthreads();
   }
 }
 
+// X <- L^{-1} X then X <- L^{-T} X for ncols columns of length N (column stride N).
 template <int N>
-__device__ inline void solve_upper_t(const double* L, int ld, double* x, int stride) {
-  for (int r = N - 1; r >= 0; --r) {
-    double s = x[r * stride];
-    for (int k = r + 1; k < N; ++k) s -= L[k * ld + r] * x[k * stride];
-    x[r * stride] = s / L[r * ld + r];
+__device__ inline void par_chol_solve(const double* L, int ld, double* X, int ncols) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < N; ++j) {
+    for (int c = t; c < ncols; c += nt) X[c * N + j] /= L[j * ld + j];
+    __syncthreads();
+    const int w = N - j - 1;
+    for (int p = t; p < w * ncols; p += nt) {
+      const int c = p / w, i = j + 1 + p % w;
+      X[c * N + i] -= L[i * ld + j] * X[c * N + j];
+    }
+    __syncthreads();
+  }
+  for (int j = N - 1; j >= 0; --j) {
+    for (int c = t; c < ncols; c += nt) X[c * N + j] /= L[j * ld + j];
+    __syncthreads();
+    for (int p = t; p < j * ncols; p += nt) {
+      const int c = p / j, i = p % j;
+      X[c * N + i] -= L[j * ld + i] * X[c * N + j];
+    }
+    __syncthreads();
   }
 }
 
-// x <- A^{-1} x for an SPD block A, given either its lower Cholesky factor L (A = L L^T,
-// two triangular solves) or, for the tile kernels' factor store, Ui = U^{-1} with
-// A = U^T U stored as an upper matrix (two triangular products: A^{-1} = Ui Ui^T).
-template <int N, bool INVERSE>
-__device__ inline void spd_apply(const double* F, double* x) {
-  if constexpr (INVERSE) {
-    double y[N];
-    for (int i = 0; i < N; ++i) {  // y = Ui^T x
-      double s = 0;
-      for (int j = 0; j <= i; ++j) s += F[j * N + i] * x[j];
-      y[i] = s;
-    }
-    for (int i = 0; i < N; ++i) {  // x = Ui y
-      double s = 0;
-      for (int j = i; j < N; ++j) s += F[i * N + j] * y[j];
-      x[i] = s;
-    }
-  } else {
-    solve_lower<N>(F, N, x, 1);
-    solve_upper_t<N>(F, N, x, 1);
+// X <- Ui (Ui^T X) for ncols columns; Ui upper (row-major N x N), tmp as large as X.
+template <int N>
+__device__ inline void par_inverse_apply(const double* Ui, double* X, double* tmp, int ncols) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int p = t; p < N * ncols; p += nt) {
+    const int c = p / N, i = p % N;
+    double s = 0;
+    for (int j = 0; j <= i; ++j) s += Ui[j * N + i] * X[c * N + j];
+    tmp[p] = s;
   }
+  __syncthreads();
+  for (int p = t; p < N * ncols; p += nt) {
+    const int c = p / N, i = p % N;
+    double s = 0;
+    for (int j = i; j < N; ++j) s += Ui[i * N + j] * tmp[c * N + j];
+    X[p] = s;
+  }
+  __syncthreads();
+}
+
+template <int N, bool TILE>
+__device__ inline void spd_apply(const double* F, double* X, double* tmp, int ncols) {
+  if constexpr (TILE)
+    par_inverse_apply<N>(F, X, tmp, ncols);
+  else
+    par_chol_solve<N>(F, N, X, ncols);
 }
 
 template <int K, bool TILE>
@@ -79,18 +117,18 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
                                                 double* __restrict__ uout, double* __restrict__ usout) {
   using Dm = Dims<K>;
   constexpr int D3 = Dm::D3, D2 = Dm::D2, NQD = Dm::NQD, D3P = Dm::D3P;
+  constexpr int TT = (D3 + 3) / 4, NU = TT * (TT + 1) / 2;
+  constexpr int FLEN = TILE ? (2 * NU + TT) * 16 : D3 * (D3 + 1) + D3;
   __shared__ RecoverSmem<K> sm;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int E = blockIdx.x; E < mesh.nelt; E += gridDim.x) {
     ElemGeom g;
     load_geometry(E, mesh, tau, g);
-    constexpr int TT = (D3 + 3) / 4, NU = TT * (TT + 1) / 2;
-    constexpr int FLEN = TILE ? (2 * NU + TT) * 16 : D3 * (D3 + 1) + D3;
     const double* fa = factors + (size_t)E * FLEN;
     for (int idx = t; idx < D3 * D3; idx += nt) {
       const int i = idx / D3, j = idx % D3;
       if constexpr (TILE) {
-        // upper inverses U^{-1}, Us^{-1} stored as packed upper 4x4 tiles: entry (i, j), j >= i
+        // U^{-1}, Us^{-1}: packed upper 4x4 tiles, entry (i, j) with j >= i
         if (j < i) continue;
         const int o = utile(i / 4, j / 4, TT) * 16 + (i % 4) * 4 + (j % 4);
         sm.L[idx] = fa[o];
@@ -113,7 +151,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
       sm.tl[idx] = s;
     }
     __syncthreads();
-    // r_s and the right-hand side pieces
+    // r_s
     for (int idx = t; idx < 3 * D3; idx += nt) {
       const int s = idx / D3, j = idx % D3;
       double v = 0;
@@ -122,11 +160,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
       sm.x[idx] = v;
     }
     __syncthreads();
-    // x_s <- M^{-1} r_s  (three columns)
-    if (t < 3) {
-      spd_apply<D3, TILE>(sm.L, sm.x + t * D3);
-    }
-    __syncthreads();
+    spd_apply<D3, TILE>(sm.L, sm.x, sm.tmp, 3);  // x_s = M^{-1} r_s
     // v_h = sum_s a[s][h] (M^{-1} r_s)
     for (int idx = t; idx < 3 * D3; idx += nt) {
       const int h = idx / D3, j = idx % D3;
@@ -142,10 +176,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
       sm.u[i] = s;
     }
     __syncthreads();
-    if (t == 0) {
-      spd_apply<D3, TILE>(sm.LS, sm.u);
-    }
-    __syncthreads();
+    spd_apply<D3, TILE>(sm.LS, sm.u, sm.tmp, 1);  // u = S^{-1} rhs_u
     // x_s = C_s^T u - r_s with (C_s^T u)_i = sum_h a[s][h] sum_j Chat^h[j][i] u_j
     for (int idx = t; idx < 3 * D3; idx += nt) {
       const int h = idx / D3, i = idx % D3;
@@ -159,10 +190,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
       sm.x[idx] = g.a[s][0] * sm.v[i] + g.a[s][1] * sm.v[D3 + i] + g.a[s][2] * sm.v[2 * D3 + i] - sm.r[idx];
     }
     __syncthreads();
-    if (t < 3) {
-      spd_apply<D3, TILE>(sm.L, sm.x + t * D3);
-    }
-    __syncthreads();
+    spd_apply<D3, TILE>(sm.L, sm.x, sm.tmp, 3);  // q_s = M^{-1} x_s
     for (int idx = t; idx < 3 * D3; idx += nt) qout[(size_t)E * 3 * D3 + idx] = sm.x[idx];
     for (int i = t; i < D3; i += nt) uout[(size_t)E * D3 + i] = sm.u[i];
     if (usout) {
@@ -199,12 +227,9 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
       }
       __syncthreads();
       // Cholesky of S* restricted to modes 2..d3p, then the solve
-      lds_cholesky<D3P - 1>(sm.Ss + D3P + 1, D3P);
-      if (t == 0) {
-        solve_lower<D3P - 1>(sm.Ss + D3P + 1, D3P, sm.rs + 1, 1);
-        solve_upper_t<D3P - 1>(sm.Ss + D3P + 1, D3P, sm.rs + 1, 1);
-        sm.rs[0] = sm.u[0];
-      }
+      par_cholesky<D3P - 1>(sm.Ss + D3P + 1, D3P);
+      par_chol_solve<D3P - 1>(sm.Ss + D3P + 1, D3P, sm.rs + 1, 1);
+      if (t == 0) sm.rs[0] = sm.u[0];
       __syncthreads();
       for (int i = t; i < D3P; i += nt) usout[(size_t)E * D3P + i] = sm.rs[i];
     }
