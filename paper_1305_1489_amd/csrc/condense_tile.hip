@@ -53,10 +53,13 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
   __shared__ int s_E[4];
   __shared__ double s_x[64];
   __shared__ double s_Z[T * MT][64];  // Z tiles, lane-contiguous
-  const int lane = threadIdx.x;
-  const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
-
   for (int w0 = blockIdx.x * 4; w0 < nwork; w0 += gridDim.x * 4) {
+    // lane-derived indices are recomputed per group and kept opaque to the compiler, so
+    // that the many table addresses derived from them are not hoisted out of this loop
+    // (hoisted, they outlive the register file and spill)
+    int lane = threadIdx.x;
+    asm volatile("" : "+v"(lane));
+    const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
     __syncthreads();
     if (lane < 4) {
       const int wi = w0 + lane;
@@ -282,6 +285,9 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
         const int b = 4 * N + c, lb = b / D2, ib = b % D2;
         double val = geo[G_NN + 4 * la + lb] * g1 - g2;
         if (a == b) val += geo[G_T + la];
+        // only entries of the upper triangle (a <= b) are ever written; their mirror images
+        // are written from the transposed tile, so each 4-lane row of a store is contiguous
+        const double tv = tile_transpose(val);  // lane (r, c) now holds C[4I + c][4N + r]
         if (E >= 0 && (I != N || r <= c)) {
           if (Cout) {
             const size_t base = (size_t)(w0 + blk) * M * M;
@@ -293,10 +299,16 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
               unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
               if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
             } else {
-              const size_t s2 = s_slot[blk][4 * lb + la];
               H[(s1 * D2 + ia) * D2 + ib] = val;
-              H[(s2 * D2 + ib) * D2 + ia] = val;
             }
+          }
+        }
+        {
+          const int a2 = 4 * I + c, b2 = 4 * N + r;  // the upper entry now held by this lane
+          const int la2 = a2 / D2, lb2 = b2 / D2;
+          if (!Cout && E >= 0 && (I != N || c <= r) && la2 != lb2) {
+            const size_t s2 = s_slot[blk][4 * lb2 + la2];
+            H[(s2 * D2 + b2 % D2) * D2 + a2 % D2] = tv;
           }
         }
       }

@@ -122,8 +122,11 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
   __shared__ RecoverSmem<K> sm;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int E = blockIdx.x; E < mesh.nelt; E += gridDim.x) {
-    ElemGeom g;
-    load_geometry(E, mesh, tau, g);
+    // element geometry in LDS (indexed at run time below; registers would spill)
+    __shared__ ElemGeom sg;
+    if (t == 0) load_geometry(E, mesh, tau, sg);
+    __syncthreads();
+    const ElemGeom& g = sg;
     const double* fa = factors + (size_t)E * FLEN;
     for (int idx = t; idx < D3 * D3; idx += nt) {
       const int i = idx / D3, j = idx % D3;
