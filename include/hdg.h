@@ -160,7 +160,10 @@ hdg_status hdg_disc_get_info(const hdg_disc* disc, hdg_disc_info* info);
  * "vol_w" [nqd], "tri_pts" [nqd2][2], "tri_w" [nqd2], "P" [nqd][d3], "Pgrad"
  * [3][nqd][d3], "D" [nqd2][d2], "Pface" [4][nqd2][d3], "Chat" [3][d3][d3],
  * "PP" [4][d3][d3], "DP" [6][4][d2][d3], "P1grad" [3][nqd][d3p], "Shat"
- * [6][d3p][d3p] (xx, yy, zz, xy+yx, xz+zx, yz+zy).  *count receives the number of
+ * [6][d3p][d3p] (xx, yy, zz, xy+yx, xz+zx, yz+zy), and the zero-padded layouts of the
+ * postprocess kernel: "P1grad_pad" [3][nqp][d3pp4] and "Shat_tiles" [6][ts(ts+1)/2][4][4]
+ * (upper 4x4 tiles (I, N), I <= N, row by row), where nqp and d3pp4 are nqd and d3p
+ * rounded up to multiples of 4 and ts = d3pp4 / 4.  *count receives the number of
  * doubles; pass h_out = NULL to query it. */
 hdg_status hdg_disc_table(const hdg_disc* disc, const char* name, double* h_out, int64_t* count);
 

@@ -22,6 +22,8 @@ struct TableOffsets {
   int vol_pts, vol_w, lambda, P, Pg, tri_pts, tri_w, xi, D, Pface, Chat, PP, DP, P1g, Shat;
   // zero-padded copies for the 4x4-tile kernels (dimensions rounded up to multiples of 4)
   int Pt, ChatT, PPt, DPT;
+  // for the postprocess kernel: degree k+1 gradients padded, stiffness tables as upper tiles
+  int P1gt, Shatt;
   int total;
 };
 
@@ -43,11 +45,13 @@ struct Tables {
   const double* ChatT;   // [3][d3p4][d3p4] transposes of Chat^h, padded
   const double* PPt;     // [4][d3p4][d3p4] PP_l padded
   const double* DPT;     // [6][4][d3p4][d2p4] transposes of DP_{mu,l}, padded
+  const double* P1gt;    // [3][nqp][d3pp4]  P1g padded (d3pp4 = d3p rounded up to 4)
+  const double* Shatt;   // [6][nus][16]  Shat as packed upper 4x4 tiles (nus = ts(ts+1)/2, ts = d3pp4/4)
 };
 
 struct HostTables {
   int k, nq, d3, d2, d3p, nqd, nqd2;
-  int d3p4, d2p4, nqp;  // padded sizes
+  int d3p4, d2p4, nqp, d3pp4;  // padded sizes
   TableOffsets off;
   std::vector<double> data;
 };

@@ -1,6 +1,6 @@
-// Reconstruction of (q, u) from the face traces (eq 5.3, Section 6 "Reconstruction") and
-// the local postprocess u* (eq 9.11), one wavefront per element, every step spread over
-// the wavefront's lanes.
+// Reconstruction of (q, u) from the face traces (eq 5.3, Section 6 "Reconstruction"),
+// one wavefront per element, every step spread over the wavefront's lanes.  The local
+// postprocess u* (eq 9.11) runs afterwards in its own kernel (postprocess.hip).
 //
 // With the factors kept by the condensation (M = M_{1/kappa}, S the u-Schur complement,
 // and f):
@@ -17,6 +17,10 @@
 #include "tile.h"
 
 namespace hdg {
+
+hdg_status launch_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
+                              const double* q, const double* u, double* us, hipStream_t s);
+
 namespace {
 
 template <int K>
@@ -31,31 +35,9 @@ struct RecoverSmem {
   double tmp[3 * Dm::D3];
   double u[Dm::D3];
   double v[3 * Dm::D3];
-  double y[3 * Dm::NQD];
-  double Ss[Dm::D3P * Dm::D3P];
-  double rs[Dm::D3P];
 };
 
 // ---- wavefront-parallel dense kernels on LDS data (all lanes of the block take part)
-
-// Right-looking Cholesky of an N x N SPD matrix (leading dimension ld), lower factor.
-template <int N>
-__device__ inline void par_cholesky(double* A, int ld) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int j = 0; j < N; ++j) {
-    if (t == 0) A[j * ld + j] = sqrt(A[j * ld + j]);
-    __syncthreads();
-    const double inv = 1.0 / A[j * ld + j];
-    for (int i = j + 1 + t; i < N; i += nt) A[i * ld + j] *= inv;
-    __syncthreads();
-    const int w = N - j - 1;
-    for (int p = t; p < w * w; p += nt) {
-      const int i = j + 1 + p / w, k = j + 1 + p % w;
-      if (k <= i) A[i * ld + k] -= A[i * ld + j] * A[k * ld + j];
-    }
-    __syncthreads();
-  }
-}
 
 // X <- L^{-1} X then X <- L^{-T} X for ncols columns of length N (column stride N).
 template <int N>
@@ -114,7 +96,7 @@ template <int K, bool TILE>
 __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                 const double* __restrict__ tau, const double* __restrict__ factors,
                                                 const double* __restrict__ uhat, double* __restrict__ qout,
-                                                double* __restrict__ uout, double* __restrict__ usout) {
+                                                double* __restrict__ uout) {
   using Dm = Dims<K>;
   constexpr int D3 = Dm::D3, D2 = Dm::D2, NQD = Dm::NQD, D3P = Dm::D3P;
   constexpr int TT = (D3 + 3) / 4, NU = TT * (TT + 1) / 2;
@@ -196,46 +178,6 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
     spd_apply<D3, TILE>(sm.L, sm.x, sm.tmp, 3);  // q_s = M^{-1} x_s
     for (int idx = t; idx < 3 * D3; idx += nt) qout[(size_t)E * 3 * D3 + idx] = sm.x[idx];
     for (int i = t; i < D3; i += nt) uout[(size_t)E * D3 + i] = sm.u[i];
-    if (usout) {
-      // y_h(q) = |K| w_q kappa_q^{-1} (B^{-1} q_h(x_q))_h, with B^{-1} = a^T / det
-      for (int q = t; q < NQD; q += nt) {
-        double qh[3] = {0, 0, 0};
-        for (int j = 0; j < D3; ++j) {
-          const double p = tb.P[q * D3 + j];
-          qh[0] += sm.x[j] * p;
-          qh[1] += sm.x[D3 + j] * p;
-          qh[2] += sm.x[2 * D3 + j] * p;
-        }
-        const double wq = g.vol * tb.vol_w[q] / kappa[(size_t)E * NQD + q] / g.det;
-        for (int h = 0; h < 3; ++h)
-          sm.y[h * NQD + q] = wq * (g.a[0][h] * qh[0] + g.a[1][h] * qh[1] + g.a[2][h] * qh[2]);
-      }
-      // G = a^T a / det
-      double G[3][3];
-      for (int h = 0; h < 3; ++h)
-        for (int k = 0; k < 3; ++k)
-          G[h][k] = (g.a[0][h] * g.a[0][k] + g.a[1][h] * g.a[1][k] + g.a[2][h] * g.a[2][k]) / g.det;
-      const double cf[6] = {G[0][0], G[1][1], G[2][2], G[0][1], G[0][2], G[1][2]};
-      for (int idx = t; idx < D3P * D3P; idx += nt) {
-        double s = 0;
-        for (int p = 0; p < 6; ++p) s += cf[p] * tb.Shat[p * D3P * D3P + idx];
-        sm.Ss[idx] = s;
-      }
-      __syncthreads();
-      for (int i = t; i < D3P; i += nt) {
-        double s = 0;
-        for (int h = 0; h < 3; ++h)
-          for (int q = 0; q < NQD; ++q) s -= sm.y[h * NQD + q] * tb.P1g[(h * NQD + q) * D3P + i];
-        sm.rs[i] = s;
-      }
-      __syncthreads();
-      // Cholesky of S* restricted to modes 2..d3p, then the solve
-      par_cholesky<D3P - 1>(sm.Ss + D3P + 1, D3P);
-      par_chol_solve<D3P - 1>(sm.Ss + D3P + 1, D3P, sm.rs + 1, 1);
-      if (t == 0) sm.rs[0] = sm.u[0];
-      __syncthreads();
-      for (int i = t; i < D3P; i += nt) usout[(size_t)E * D3P + i] = sm.rs[i];
-    }
     __syncthreads();
   }
 }
@@ -244,9 +186,9 @@ template <int K>
 hdg_status run_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
                        const double* factors, const double* uhat, double* q, double* u, double* us, hipStream_t s) {
   const int grid = (int)std::min<int64_t>(mesh->nelt, 1 << 20);
-  k_recover<K, (K >= 1 && K <= 3)><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u, us);
+  k_recover<K, (K >= 1 && K <= 3)><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
   HDG_CHECK_LAUNCH("k_recover");
-  return HDG_OK;
+  return us ? launch_postprocess(disc, mesh, kappa, tau, q, u, us, s) : HDG_OK;
 }
 
 }  // namespace

@@ -281,6 +281,10 @@ HostTables build_tables(int k, int nq) {
   o.ChatT = take(3 * D3P4 * D3P4);
   o.PPt = take(4 * D3P4 * D3P4);
   o.DPT = take(24 * D3P4 * D2P4);
+  const int D3PP4 = (d3p + 3) / 4 * 4, TS = D3PP4 / 4, NUS = TS * (TS + 1) / 2;
+  t.d3pp4 = D3PP4;
+  o.P1gt = take(3 * NQP * D3PP4);
+  o.Shatt = take(6 * NUS * 16);
   o.total = pos;
   t.data.assign(pos, 0.0);
   auto put = [&](int off, const std::vector<ld>& v) {
@@ -323,6 +327,21 @@ HostTables build_tables(int k, int nq) {
   for (int ml = 0; ml < 24; ++ml)
     for (int i = 0; i < d3; ++i)
       for (int j = 0; j < d2; ++j) t.data[o.DPT + (ml * D3P4 + i) * D2P4 + j] = (double)DP[(ml * d2 + j) * d3 + i];
+  for (int h = 0; h < 3; ++h)
+    for (int q = 0; q < nqd; ++q)
+      for (int i = 0; i < d3p; ++i)
+        t.data[o.P1gt + (h * NQP + q) * D3PP4 + i] = (double)P1g[(h * nqd + q) * d3p + i];
+  for (int p = 0; p < 6; ++p)
+    for (int I = 0; I < TS; ++I)
+      for (int N = I; N < TS; ++N) {
+        const int u = I * TS - I * (I - 1) / 2 + (N - I);
+        for (int r = 0; r < 4; ++r)
+          for (int c = 0; c < 4; ++c) {
+            const int i = 4 * I + r, j = 4 * N + c;
+            if (i < d3p && j < d3p)
+              t.data[o.Shatt + (p * NUS + u) * 16 + 4 * r + c] = (double)Shat[(p * d3p + i) * d3p + j];
+          }
+      }
   return t;
 }
 

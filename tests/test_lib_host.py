@@ -81,3 +81,20 @@ def test_tables_match_oracle(L, k):
     Sh = np.stack([np.einsum("q,qi,qj->ij", vw, G1[a], G1[b]) / 6 + (np.einsum("q,qi,qj->ij", vw, G1[b], G1[a]) / 6 if a != b else 0)
                    for a, b in pairs])
     assert np.abs(T("Shat").reshape(6, d3p, d3p) - Sh).max() < 1e-10 * max(1.0, np.abs(Sh).max())
+    # padded layouts of the same tables: the copies are exact, the padding is zero
+    nqd = G1.shape[1]
+    nqp, d3pp4 = -(-nqd // 4) * 4, -(-d3p // 4) * 4
+    ts = d3pp4 // 4
+    Gp = T("P1grad_pad").reshape(3, nqp, d3pp4)
+    assert np.array_equal(Gp[:, :nqd, :d3p], T("P1grad").reshape(3, nqd, d3p))
+    assert not Gp[:, nqd:, :].any() and not Gp[:, :, d3p:].any()
+    St = T("Shat_tiles").reshape(6, ts * (ts + 1) // 2, 4, 4)
+    full = np.zeros((6, d3pp4, d3pp4))
+    u = 0
+    for I in range(ts):
+        for N in range(I, ts):
+            full[:, 4 * I:4 * I + 4, 4 * N:4 * N + 4] = St[:, u]
+            u += 1
+    Sref = T("Shat").reshape(6, d3p, d3p)
+    assert np.array_equal(np.triu(full[:, :d3p, :d3p]), np.triu(Sref))
+    assert not full[:, d3p:, :].any() and not full[:, :, d3p:].any()
