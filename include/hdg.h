@@ -270,6 +270,19 @@ hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
                        const double* d_factors, const double* d_uhat, double* d_q, double* d_u,
                        double* d_ustar, void* stream);
 
+/* ------------------------------------------------------------------------------
+ * Local postprocess alone (eq 9.11): u* in P_{k+1}(K) with grad u* = -kappa^{-1} q_h
+ * in the least-squares sense on K (the stiffness system tested against the gradients of
+ * P_{k+1}) and the mean of u* equal to that of u_h.  hdg_recover with a non-NULL d_ustar
+ * runs it after the reconstruction; this entry runs it on given fields.
+ *   d_kappa  double [nelt][nqd]     d_tau double [nelt][4] (geometry set-up only)
+ *   d_q      double [nelt][3][d3]   d_u   double [nelt][d3]   (layouts of hdg_recover)
+ * Output: d_ustar double [nelt][d3p].  Errors: HDG_ERR_INVALID_ARG (NULL array),
+ * HDG_ERR_UNSUPPORTED_DEGREE, HDG_ERR_DEVICE.  Nothing is allocated.
+ * ------------------------------------------------------------------------------ */
+hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_tau,
+                           const double* d_q, const double* d_u, double* d_ustar, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ STATUS = {0: "HDG_OK", 1: "HDG_ERR_INVALID_ARG", 2: "HDG_ERR_UNSUPPORTED_DEGREE"
 EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expand", "hdg_disc_create",
            "hdg_disc_destroy", "hdg_disc_get_info", "hdg_disc_table", "hdg_reference_table", "hdg_qp_coords", "hdg_face_qp_coords",
            "hdg_assemble_condense", "hdg_check_tau", "hdg_export_local", "hdg_boundary",
-           "hdg_solve_workspace_size", "hdg_solve", "hdg_recover"]
+           "hdg_solve_workspace_size", "hdg_solve", "hdg_recover", "hdg_postprocess"]
 
 
 class HdgError(RuntimeError):
@@ -307,3 +307,11 @@ def hdg_recover(disc: Disc, mesh: Mesh, kappa, tau, factors, uhat, q=None, u=Non
     _check(lib().hdg_recover(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(tau), _ptr(factors), _ptr(uhat),
                              _ptr(q), _ptr(u), _ptr(ustar) if postprocess else None, _stream(stream)))
     return q, u, (ustar if postprocess else None)
+
+
+def hdg_postprocess(disc: Disc, mesh: Mesh, kappa, tau, q, u, ustar=None, stream=None):
+    if ustar is None:
+        ustar = torch.empty((mesh.nelt, disc.d3p), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_postprocess(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(tau), _ptr(q), _ptr(u),
+                                 _ptr(ustar), _stream(stream)))
+    return ustar

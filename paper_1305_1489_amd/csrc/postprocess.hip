@@ -222,4 +222,16 @@ hdg_status launch_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const 
   return HDG_OK;
 }
 
+hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const char* who);
+
 }  // namespace hdg
+
+extern "C" hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                      const double* d_tau, const double* d_q, const double* d_u, double* d_ustar,
+                                      void* stream) {
+  hdg_status st = hdg::check_disc_mesh(disc, mesh, "hdg_postprocess");
+  if (st) return st;
+  if (!d_kappa || !d_tau || !d_q || !d_u || !d_ustar)
+    return hdg::set_error(HDG_ERR_INVALID_ARG, "hdg_postprocess: NULL array");
+  return hdg::launch_postprocess(disc, mesh, d_kappa, d_tau, d_q, d_u, d_ustar, (hipStream_t)stream);
+}

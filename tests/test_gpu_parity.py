@@ -169,6 +169,22 @@ def test_recovery_parity_same_uhat(k):
     assert rel(us.cpu().numpy(), out["ustar"]) < TOL
 
 
+@pytest.mark.parametrize("k", [0, 2, 4])
+def test_postprocess_entry_on_oracle_fields(k):
+    """hdg_postprocess alone, fed the oracle's q and u (eq 9.11), on a ragged element count."""
+    from paper_1305_1489_amd import _lib as L
+    m = make_mesh(3, jitter=0.12, seed=30 + k, **MIXED)
+    pb = _problem_random_tau(m, seed=40 + k)
+    print(f"postprocess k={k}", flush=True)
+    out = OG.solve_problem(oracle_expand(m), pb, k)
+    S = gpu_system(m, k, pb)
+    q = torch.as_tensor(out["q"], device="cuda").contiguous()
+    u = torch.as_tensor(out["u"], device="cuda").contiguous()
+    us = L.hdg_postprocess(S.disc, S.mesh, S.kappa, S.tau, q, u)
+    torch.cuda.synchronize()
+    assert rel(us.cpu().numpy(), out["ustar"]) < TOL
+
+
 # ----------------------------------------------------------------------------- whole pipeline
 @pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
 def test_polynomial_reproduction_gpu(k):
