@@ -283,6 +283,68 @@ hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
 hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_tau,
                            const double* d_q, const double* d_u, double* d_ustar, void* stream);
 
+/* ------------------------------------------------------------------------------
+ * Batched condensation of many independent meshes of mixed degree in one launch.
+ *
+ * Each mesh of the batch gets exactly what hdg_assemble_condense gives it (H, F and the
+ * factor store, bit for bit); the element work is that of Sections 3-6 (eq 5.5-5.6) and
+ * the scatter of eq 6.5, cut into work units (groups of four elements for k = 1..3,
+ * single elements for k = 0 and 4) and swept by one persistent kernel per degree.
+ *
+ * hdg_batch_create copies the item list and the mesh structs; the discs, the mesh arrays,
+ * the coefficient arrays and the outputs stay owned by the caller and must outlive the
+ * batch.  Two items must not share an output array (their writes would race).  It
+ * allocates the device work lists, one stream per degree and the capture objects
+ * (set-up, not a compute call).  Errors: HDG_ERR_INVALID_ARG (n < 1, NULL arrays, an
+ * unexpanded mesh, nq != k + 2), HDG_ERR_DEVICE.
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  const hdg_disc* disc;      /* degree and tables (nq = k + 2) */
+  const hdg_mesh* mesh;      /* expanded mesh */
+  const double* d_kappa;     /* double [nelt][nqd]  as in hdg_assemble_condense */
+  const double* d_c;         /* double [nelt][nqd] */
+  const double* d_f;         /* double [nelt][nqd] */
+  const double* d_tau;       /* double [nelt][4] */
+  double* d_H;               /* double [nnzb][d2][d2]  output */
+  double* d_F;               /* double [nfc][d2]       output */
+  double* d_factors;         /* double [nelt][factor_len] output, may be NULL */
+} hdg_batch_item;
+
+/* Launch shape of one degree's persistent kernel: the grid is workgroups_per_cu times
+ * the number of compute units (at most the number of work units); xcd_remap = 1 hands
+ * each of the eight XCDs a contiguous run of work units per sweep.  Defaults: 8 (k =
+ * 1..3) or 2 (k = 0, 4) workgroups per CU, no remap. */
+typedef struct {
+  int workgroups_per_cu;     /* 1..64 */
+  int xcd_remap;             /* 0 or 1 */
+} hdg_tile_config;
+
+typedef struct hdg_batch hdg_batch;
+
+hdg_status hdg_batch_create(int n, const hdg_batch_item* items, hdg_batch** out);
+hdg_status hdg_batch_destroy(hdg_batch* batch);
+/* Number of meshes and elements of degree k in the batch. */
+hdg_status hdg_batch_info(const hdg_batch* batch, int k, int64_t* nmesh, int64_t* nelt);
+hdg_status hdg_batch_set_config(hdg_batch* batch, int k, const hdg_tile_config* cfg);
+hdg_status hdg_batch_get_config(const hdg_batch* batch, int k, hdg_tile_config* cfg);
+/* Eager form: per degree (highest first) zero the diagonal blocks of H and F of its
+ * meshes, then run the persistent kernel; all on `stream`. */
+hdg_status hdg_batch_condense(hdg_batch* batch, void* stream);
+/* (Re)records the same work as one hipGraph whose per-degree parts are parallel branches;
+ * called by hdg_batch_launch when no graph exists or the configuration changed. */
+hdg_status hdg_batch_capture(hdg_batch* batch);
+/* One graph launch of the whole batch on `stream`. */
+hdg_status hdg_batch_launch(hdg_batch* batch, void* stream);
+
+/* Autotuner for degree k on this batch: times every candidate shape (workgroups_per_cu in
+ * {1, 2, 4, 8, 16} x xcd_remap in {0, 1}), each once to warm up and then `reps` times on
+ * `stream` (the batch's degree-k outputs are overwritten with identical values), keeps the
+ * fastest in the batch and returns it.  ncand, cands [16] and cand_ms [16] may be NULL;
+ * else they receive every candidate and its mean time (ms).  Synchronises the stream.
+ * Errors: HDG_ERR_INVALID_ARG (no mesh of degree k, reps < 1), HDG_ERR_DEVICE. */
+hdg_status hdg_autotune(hdg_batch* batch, int k, int reps, hdg_tile_config* best, double* best_ms, int* ncand,
+                        hdg_tile_config* cands, double* cand_ms, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

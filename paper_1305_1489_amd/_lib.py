@@ -26,7 +26,9 @@ STATUS = {0: "HDG_OK", 1: "HDG_ERR_INVALID_ARG", 2: "HDG_ERR_UNSUPPORTED_DEGREE"
 EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expand", "hdg_disc_create",
            "hdg_disc_destroy", "hdg_disc_get_info", "hdg_disc_table", "hdg_reference_table", "hdg_qp_coords", "hdg_face_qp_coords",
            "hdg_assemble_condense", "hdg_check_tau", "hdg_export_local", "hdg_boundary",
-           "hdg_solve_workspace_size", "hdg_solve", "hdg_recover", "hdg_postprocess"]
+           "hdg_solve_workspace_size", "hdg_solve", "hdg_recover", "hdg_postprocess", "hdg_batch_create",
+           "hdg_batch_destroy", "hdg_batch_info", "hdg_batch_set_config", "hdg_batch_get_config",
+           "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune"]
 
 
 class HdgError(RuntimeError):
@@ -315,3 +317,93 @@ def hdg_postprocess(disc: Disc, mesh: Mesh, kappa, tau, q, u, ustar=None, stream
     _check(lib().hdg_postprocess(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(tau), _ptr(q), _ptr(u),
                                  _ptr(ustar), _stream(stream)))
     return ustar
+
+
+# ----------------------------------------------------------------------------- batched condensation
+class hdg_batch_item(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("disc", "mesh", "d_kappa", "d_c", "d_f", "d_tau", "d_H", "d_F",
+                                          "d_factors")]
+
+
+class hdg_tile_config(C.Structure):
+    _fields_ = [("workgroups_per_cu", C.c_int), ("xcd_remap", C.c_int)]
+
+
+class Batch:
+    """Owns an hdg_batch handle and keeps alive everything its work list points at."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def __del__(self):
+        h = self.__dict__.get("handle")
+        if h and _lib is not None:
+            _lib.hdg_batch_destroy(h)
+            self.handle = None
+
+
+def hdg_batch_create(items) -> Batch:
+    """items: sequence of dicts with keys disc, mesh, kappa, c, f, tau, H, F and optionally
+    factors (tensors as for hdg_assemble_condense)."""
+    arr = (hdg_batch_item * len(items))()
+    keep = []
+    for i, it in enumerate(items):
+        for name in ("kappa", "c", "f", "tau", "H", "F"):
+            t = it[name]
+            if t.dtype != torch.float64 or not t.is_contiguous():
+                raise ValueError(f"batch item {i}: {name} must be a contiguous float64 tensor")
+        a = arr[i]
+        a.disc = it["disc"].handle.value if isinstance(it["disc"].handle, C.c_void_p) else it["disc"].handle
+        a.mesh = C.addressof(it["mesh"].struct)
+        for name in ("kappa", "c", "f", "tau", "H", "F"):
+            setattr(a, "d_" + name, it[name].data_ptr())
+        fac = it.get("factors")
+        a.d_factors = fac.data_ptr() if fac is not None else None
+        keep.append(it)
+    h = C.c_void_p()
+    _check(lib().hdg_batch_create(C.c_int(len(items)), arr, C.byref(h)))
+    return Batch(h, keep)
+
+
+def hdg_batch_info(batch: Batch, k: int):
+    nm, ne = C.c_int64(), C.c_int64()
+    _check(lib().hdg_batch_info(batch.handle, C.c_int(k), C.byref(nm), C.byref(ne)))
+    return nm.value, ne.value
+
+
+def hdg_batch_set_config(batch: Batch, k: int, workgroups_per_cu: int, xcd_remap: int):
+    cfg = hdg_tile_config(workgroups_per_cu, xcd_remap)
+    _check(lib().hdg_batch_set_config(batch.handle, C.c_int(k), C.byref(cfg)))
+
+
+def hdg_batch_get_config(batch: Batch, k: int):
+    cfg = hdg_tile_config()
+    _check(lib().hdg_batch_get_config(batch.handle, C.c_int(k), C.byref(cfg)))
+    return {"workgroups_per_cu": cfg.workgroups_per_cu, "xcd_remap": cfg.xcd_remap}
+
+
+def hdg_batch_condense(batch: Batch, stream=None):
+    _check(lib().hdg_batch_condense(batch.handle, _stream(stream)))
+
+
+def hdg_batch_capture(batch: Batch):
+    _check(lib().hdg_batch_capture(batch.handle))
+
+
+def hdg_batch_launch(batch: Batch, stream=None):
+    _check(lib().hdg_batch_launch(batch.handle, _stream(stream)))
+
+
+def hdg_autotune(batch: Batch, k: int, reps: int = 3, stream=None):
+    best = hdg_tile_config()
+    best_ms = C.c_double()
+    nc = C.c_int()
+    cands = (hdg_tile_config * 16)()
+    cms = (C.c_double * 16)()
+    _check(lib().hdg_autotune(batch.handle, C.c_int(k), C.c_int(reps), C.byref(best), C.byref(best_ms), C.byref(nc),
+                              cands, cms, _stream(stream)))
+    return {"best": {"workgroups_per_cu": best.workgroups_per_cu, "xcd_remap": best.xcd_remap},
+            "best_ms": best_ms.value,
+            "candidates": [{"workgroups_per_cu": cands[i].workgroups_per_cu, "xcd_remap": cands[i].xcd_remap,
+                            "ms": cms[i]} for i in range(nc.value)]}

@@ -33,20 +33,21 @@ struct CondenseSmem {
   double U[Dm::D3 * Dm::D3];
 };
 
+// Work item w (one element) on one wavefront.
 template <int K>
-__global__ void __launch_bounds__(64) k_condense(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+__device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tables& tb, const double* __restrict__ kappa,
                                                  const double* __restrict__ cco, const double* __restrict__ fco,
                                                  const double* __restrict__ tau, double* __restrict__ H,
                                                  double* __restrict__ F, double* __restrict__ factors,
                                                  const int* __restrict__ elems, int nwork, double* __restrict__ Cout,
-                                                 double* __restrict__ Cfout) {
+                                                 double* __restrict__ Cfout, int w) {
   using Dm = Dims<K>;
   constexpr int D3 = Dm::D3, D2 = Dm::D2, M = Dm::M, NQD = Dm::NQD, MV = M + 1;
   __shared__ CondenseSmem<K> sm;
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+  {
     const int E = elems ? elems[w] : w;
-    if (E < 0 || E >= mesh.nelt) continue;  // uniform across the block
+    if (E < 0 || E >= mesh.nelt) return;  // uniform across the block
     ElemGeom g;
     load_geometry(E, mesh, tau, g);
     // ---- coefficients at the quadrature points
@@ -189,6 +190,28 @@ __global__ void __launch_bounds__(64) k_condense(hdg_mesh mesh, Tables tb, const
   }
 }
 
+template <int K>
+__global__ void __launch_bounds__(64) k_condense(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+                                                 const double* __restrict__ cco, const double* __restrict__ fco,
+                                                 const double* __restrict__ tau, double* __restrict__ H,
+                                                 double* __restrict__ F, double* __restrict__ factors,
+                                                 const int* __restrict__ elems, int nwork, double* __restrict__ Cout,
+                                                 double* __restrict__ Cfout) {
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x)
+    condense_element<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, elems, nwork, Cout, Cfout, w);
+}
+
+// Persistent batched form: work unit u is element u - unit_begin of its mesh.
+template <int K>
+__global__ void __launch_bounds__(64) k_batch_condense(const BatchItem* __restrict__ items, int nitems, int total_units,
+                                                       Tables tb, int xcd_remap) {
+  for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
+    const BatchItem* it = items + batch_find(items, nitems, u);
+    condense_element<K>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
+                        (int)it->mesh.nelt, nullptr, nullptr, u - it->unit_begin);
+  }
+}
+
 // Zero the diagonal blocks of H and F before the scatter.
 template <int D2>
 __global__ void k_zero_diag(const int* __restrict__ diag, int nfc, double* __restrict__ H, double* __restrict__ F) {
@@ -240,6 +263,24 @@ hdg_status dispatch_condense(const hdg_disc* disc, const hdg_mesh* mesh, const d
 }
 
 }  // namespace
+
+hdg_status launch_batch_condense_tile(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
+                                      int grid, int xcd_remap, hipStream_t s);
+
+int condense_unit(int k) { return (k >= 1 && k <= 3) ? 4 : 1; }
+
+hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
+                                 int grid, int xcd_remap, hipStream_t s) {
+  if (nitems <= 0 || total_units <= 0) return HDG_OK;
+  if (k >= 1 && k <= 3) return launch_batch_condense_tile(k, tb, d_items, nitems, total_units, grid, xcd_remap, s);
+  switch (k) {
+    case 0: k_batch_condense<0><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    case 4: k_batch_condense<4><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "batched condensation: unsupported degree");
+  }
+  HDG_CHECK_LAUNCH("k_batch_condense");
+  return HDG_OK;
+}
 
 hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const char* who) {
   if (!disc || !mesh) return set_error(HDG_ERR_INVALID_ARG, std::string(who) + ": NULL handle");

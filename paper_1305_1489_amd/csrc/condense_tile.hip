@@ -35,13 +35,14 @@ struct TD {
 
 enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_LEN = 43 };
 
+// One group of four elements (w0 .. w0+3 of the work list) on one wavefront.
 template <int K>
-__global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+__device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const Tables& tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
                                                       const double* __restrict__ tau, double* __restrict__ H,
                                                       double* __restrict__ F, double* __restrict__ factors,
                                                       const int* __restrict__ elems, int nwork,
-                                                      double* __restrict__ Cout, double* __restrict__ Cfout) {
+                                                      double* __restrict__ Cout, double* __restrict__ Cfout, int w0) {
   using D = TD<K>;
   constexpr int T = D::T, MT = D::MT, QT = D::QT, D3 = D::D3, D2 = D::D2, M = D::M;
   constexpr int NQD = D::NQD, NQP = D::NQP, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
@@ -53,7 +54,7 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
   __shared__ int s_E[4];
   __shared__ double s_x[64];
   __shared__ double s_Z[T * MT][64];  // Z tiles, lane-contiguous
-  for (int w0 = blockIdx.x * 4; w0 < nwork; w0 += gridDim.x * 4) {
+  {
     // lane-derived indices are recomputed per group and kept opaque to the compiler, so
     // that the many table addresses derived from them are not hoisted out of this loop
     // (hoisted, they outlive the register file and spill)
@@ -325,6 +326,28 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
   }
 }
 
+template <int K>
+__global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+                                                      const double* __restrict__ cco, const double* __restrict__ fco,
+                                                      const double* __restrict__ tau, double* __restrict__ H,
+                                                      double* __restrict__ F, double* __restrict__ factors,
+                                                      const int* __restrict__ elems, int nwork,
+                                                      double* __restrict__ Cout, double* __restrict__ Cfout) {
+  for (int w0 = blockIdx.x * 4; w0 < nwork; w0 += gridDim.x * 4)
+    condense_tile_group<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, elems, nwork, Cout, Cfout, w0);
+}
+
+// Persistent batched form: work unit u is group u - unit_begin of its mesh.
+template <int K>
+__global__ void __launch_bounds__(64) k_batch_condense_tile(const BatchItem* __restrict__ items, int nitems,
+                                                            int total_units, Tables tb, int xcd_remap) {
+  for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
+    const BatchItem* it = items + batch_find(items, nitems, u);
+    condense_tile_group<K>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
+                           (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin));
+  }
+}
+
 template <int D2>
 __global__ void k_zero_diag_t(const int* __restrict__ diag, int nfc, double* __restrict__ H, double* __restrict__ F) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
@@ -361,6 +384,18 @@ int tile_factor_len(int k) {
     case 3: return TD<3>::FACTOR_LEN;
   }
   return 0;
+}
+
+hdg_status launch_batch_condense_tile(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
+                                      int grid, int xcd_remap, hipStream_t s) {
+  switch (k) {
+    case 1: k_batch_condense_tile<1><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    case 2: k_batch_condense_tile<2><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    case 3: k_batch_condense_tile<3><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "batched tile condensation: unsupported degree");
+  }
+  HDG_CHECK_LAUNCH("k_batch_condense_tile");
+  return HDG_OK;
 }
 
 hdg_status dispatch_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,

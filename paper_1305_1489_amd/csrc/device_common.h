@@ -112,4 +112,26 @@ __device__ inline void lds_backward_cols(const double* L, int ldl, double* X, in
   }
 }
 
+// ---- batched (several meshes per launch) persistent kernels
+
+// Index of the mesh owning work unit u: the last item whose unit_begin <= u.  The unit is
+// uniform over the workgroup, so the search runs on the scalar unit.
+__device__ __forceinline__ int batch_find(const BatchItem* __restrict__ items, int n, int u) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Workgroups are dealt round-robin to the eight XCDs (workgroup b runs on XCD b mod 8).
+// With remapping, the workgroups of one XCD take consecutive unit numbers, so that
+// neighbouring elements (which share vertices, faces and rows of H) meet in one L2.
+__device__ __forceinline__ int batch_block(int xcd_remap) {
+  const int b = blockIdx.x, nb = gridDim.x;
+  if (!xcd_remap || (nb & 7)) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
 }  // namespace hdg

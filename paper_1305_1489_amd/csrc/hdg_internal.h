@@ -62,6 +62,26 @@ HostTables build_tables(int k, int nq);
 // the packed layout of the per-element kernel).
 int tile_factor_len(int k);
 
+// Device-side descriptor of one mesh of a batched condensation: the mesh, its coefficient
+// arrays and its outputs, and the first work unit of the mesh in the degree's work list
+// (a unit is a group of four elements for the tile kernels, one element otherwise).
+struct BatchItem {
+  hdg_mesh mesh;
+  const double *kappa, *c, *f, *tau;
+  double *H, *F, *factors;
+  int unit_begin;
+  int pad_;
+};
+
+// Elements per work unit of the condensation kernel used for degree k.
+int condense_unit(int k);
+
+// Persistent batched condensation of every mesh of degree k listed in d_items (device
+// array, sorted by unit_begin); grid workgroups take the units round-robin, and with
+// xcd_remap each of the eight XCDs takes a contiguous run of units per sweep.
+hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
+                                 int grid, int xcd_remap, hipStream_t s);
+
 }  // namespace hdg
 
 struct hdg_disc {

@@ -24,11 +24,13 @@ def _field(fn, X, Y, Z):
 class HDGSystem:
     """Device state of one HDG problem (mesh, degree, data)."""
 
-    def __init__(self, coords, elements, dirichlet, neumann, k, problem, device="cuda", stream=None):
+    def __init__(self, coords, elements, dirichlet, neumann, k, problem, device="cuda", stream=None, disc=None):
         self.device = torch.device(device)
         self.stream = stream
         self.mesh = L.hdg_mesh_expand(coords, elements, dirichlet, neumann, device=device, stream=stream)
-        self.disc = L.hdg_disc_create(k)
+        if disc is not None and disc.k != k:
+            raise ValueError(f"disc has degree {disc.k}, expected {k}")
+        self.disc = disc if disc is not None else L.hdg_disc_create(k)
         self.k = k
         self.problem = problem
         xyz = L.hdg_qp_coords(self.disc, self.mesh, stream=stream)
@@ -84,3 +86,8 @@ class HDGSystem:
         info = self.solve(rtol=rtol, precision=precision)
         q, u, us = self.recover()
         return dict(info=info, q=q, u=u, ustar=us)
+
+    def batch_item(self):
+        """This system's arrays as an item of a batched condensation (hdg_batch_create)."""
+        return dict(disc=self.disc, mesh=self.mesh, kappa=self.kappa, c=self.c, f=self.f, tau=self.tau, H=self.H,
+                    F=self.F, factors=self.factors)

@@ -1,0 +1,121 @@
+"""Batched condensation of meshes of mixed degree: the persistent batched kernels, eager and
+graph-captured, and after autotuning, give every mesh exactly (bit for bit) what a separate
+hdg_assemble_condense gives it."""
+import numpy as np
+import pytest
+import torch
+
+from hdg_inputs import kuhn_mesh
+from hdg_inputs.fields import constant_rhs_problem
+from hdg_inputs.mesh import SIDES
+
+pytestmark = pytest.mark.gpu
+
+# (n, k, seed): every degree, ragged element counts (6 n^3 is not a multiple of 4 for odd n)
+SPECS = [(3, 4, 0), (2, 1, 1), (3, 2, 2), (1, 3, 3), (2, 0, 4), (3, 3, 5), (2, 4, 6), (3, 1, 7)]
+
+
+def _systems():
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem
+    discs, out = {}, []
+    for n, k, seed in SPECS:
+        m = kuhn_mesh(n, jitter=0.1 if n > 1 else 0.0, seed=seed, dirichlet_sides=SIDES, neumann_sides=())
+        pb = constant_rhs_problem(1.0, 0.3, 500 + seed, 0.5)
+        pb.tau = np.random.default_rng(seed).uniform(0.3, 2.0, size=(m.elements.shape[0], 4))
+        disc = discs.setdefault(k, L.hdg_disc_create(k))
+        out.append(HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, pb, disc=disc))
+    return out
+
+
+def _nan_fill(systems):
+    for S in systems:
+        S.H.fill_(float("nan"))
+        S.F.fill_(float("nan"))
+        S.factors.fill_(float("nan"))
+
+
+def _bits(t):
+    return t.view(torch.int64)
+
+
+def _references(systems):
+    _nan_fill(systems)
+    for S in systems:
+        S.assemble()
+    torch.cuda.synchronize()
+    return [(S.H.clone(), S.F.clone(), S.factors.clone()) for S in systems]
+
+
+def _assert_same(systems, refs, what):
+    for i, (S, (H, F, X)) in enumerate(zip(systems, refs)):
+        assert torch.equal(_bits(S.H), _bits(H)), f"{what}: H of mesh {i} (k={S.k})"
+        assert torch.equal(_bits(S.F), _bits(F)), f"{what}: F of mesh {i}"
+        assert torch.equal(_bits(S.factors), _bits(X)), f"{what}: factors of mesh {i}"
+        assert not torch.isnan(S.H).any() and not torch.isnan(S.F).any()
+
+
+def test_batch_equals_per_mesh_launches_bitwise():
+    from paper_1305_1489_amd import _lib as L
+    systems = _systems()
+    refs = _references(systems)
+    b = L.hdg_batch_create([S.batch_item() for S in systems])
+    for k in range(5):
+        nm, ne = L.hdg_batch_info(b, k)
+        assert nm == sum(1 for n, kk, _ in SPECS if kk == k)
+        assert ne == sum(6 * n ** 3 for n, kk, _ in SPECS if kk == k)
+    print("batch eager", flush=True)
+    _nan_fill(systems)
+    L.hdg_batch_condense(b)
+    torch.cuda.synchronize()
+    _assert_same(systems, refs, "eager")
+    # every launch shape gives the same bits
+    for wpc, remap in ((1, 0), (3, 1), (16, 1)):
+        for k in range(5):
+            L.hdg_batch_set_config(b, k, wpc, remap)
+        _nan_fill(systems)
+        L.hdg_batch_condense(b)
+        torch.cuda.synchronize()
+        _assert_same(systems, refs, f"eager wpc={wpc} remap={remap}")
+
+
+def test_batch_graph_replays_and_autotune():
+    from paper_1305_1489_amd import _lib as L
+    systems = _systems()
+    refs = _references(systems)
+    b = L.hdg_batch_create([S.batch_item() for S in systems])
+    print("batch graph", flush=True)
+    for rep in range(3):
+        _nan_fill(systems)  # eager work between the replays
+        torch.cuda.synchronize()
+        L.hdg_batch_launch(b)
+        torch.cuda.synchronize()
+        _assert_same(systems, refs, f"graph replay {rep}")
+        systems[rep].assemble()  # unrelated eager launch on the same arrays, then restore by replay
+        torch.cuda.synchronize()
+    print("autotune", flush=True)
+    for k in range(5):
+        res = L.hdg_autotune(b, k, reps=1)
+        assert len(res["candidates"]) == 10
+        assert res["best_ms"] > 0
+        assert res["best"] in [{kk: c[kk] for kk in ("workgroups_per_cu", "xcd_remap")} for c in res["candidates"]]
+        assert L.hdg_batch_get_config(b, k) == res["best"]
+    for rep in range(2):
+        _nan_fill(systems)
+        L.hdg_batch_launch(b)  # recaptured with the tuned shapes
+        torch.cuda.synchronize()
+        _assert_same(systems, refs, f"tuned graph replay {rep}")
+
+
+def test_batch_rejects_bad_items():
+    from paper_1305_1489_amd import _lib as L
+    systems = _systems()[:2]
+    items = [S.batch_item() for S in systems]
+    items[1] = dict(items[1], H=items[1]["H"][:, :1, :])  # non-contiguous
+    with pytest.raises(ValueError):
+        L.hdg_batch_create(items)
+    b = L.hdg_batch_create([S.batch_item() for S in systems])
+    with pytest.raises(L.HdgError):
+        L.hdg_batch_set_config(b, 1, 0, 0)
+    with pytest.raises(L.HdgError):
+        L.hdg_autotune(b, 2, reps=1)  # no mesh of degree 2 in this batch

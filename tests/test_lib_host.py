@@ -98,3 +98,23 @@ def test_tables_match_oracle(L, k):
     Sref = T("Shat").reshape(6, d3p, d3p)
     assert np.array_equal(np.triu(full[:, :d3p, :d3p]), np.triu(Sref))
     assert not full[:, d3p:, :].any() and not full[:, :, d3p:].any()
+
+
+def test_batch_argument_errors_without_device():
+    """Argument validation of the batch calls happens before any device work."""
+    import ctypes as C
+    from paper_1305_1489_amd import _lib as L
+    lib = L.lib()
+    out = C.c_void_p()
+    assert lib.hdg_batch_create(C.c_int(0), None, C.byref(out)) == 1
+    assert b"n >= 1" in lib.hdg_last_error()
+    assert lib.hdg_batch_create(C.c_int(1), None, None) == 1
+    assert lib.hdg_autotune(None, 1, 1, None, None, None, None, None, None) == 1
+    cfg = L.hdg_tile_config(4, 1)
+    assert lib.hdg_batch_set_config(None, 1, C.byref(cfg)) == 1
+    assert lib.hdg_batch_get_config(None, 1, C.byref(cfg)) == 1
+    assert lib.hdg_batch_condense(None, None) == 1
+    assert lib.hdg_batch_launch(None, None) == 1
+    assert lib.hdg_batch_capture(None) == 1
+    assert lib.hdg_batch_destroy(None) == 0
+
