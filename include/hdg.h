@@ -312,12 +312,22 @@ typedef struct {
 
 /* Launch shape of one degree's persistent kernel: the grid is workgroups_per_cu times
  * the number of compute units (at most the number of work units); xcd_remap = 1 hands
- * each of the eight XCDs a contiguous run of work units per sweep.  Defaults: 8 (k =
- * 1..3) or 2 (k = 0, 4) workgroups per CU, no remap. */
+ * each of the eight XCDs a contiguous run of work units per sweep; waves_per_element is
+ * the workgroup size, in wavefronts, of the per-element kernel of k = 0 and 4 (1, 2, 4
+ * or 8; must be 1 for the four-elements-per-wavefront kernels of k = 1..3).
+ * A new batch starts from the library-wide shape of hdg_get_launch_config. */
 typedef struct {
   int workgroups_per_cu;     /* 1..64 */
   int xcd_remap;             /* 0 or 1 */
+  int waves_per_element;     /* 1, 2, 4, 8 */
 } hdg_tile_config;
+
+/* Library-wide launch shape of the condensation of degree k, used by hdg_assemble_condense
+ * and hdg_export_local and as the starting shape of new batches (defaults: k = 1..3
+ * {4, 1, 1}, k = 4 {1, 1, 8}, k = 0 {2, 0, 1}).  Every shape gives the same results bit for
+ * bit.  Not synchronised with calls running in other threads.  Errors: HDG_ERR_INVALID_ARG. */
+hdg_status hdg_set_launch_config(int k, const hdg_tile_config* cfg);
+hdg_status hdg_get_launch_config(int k, hdg_tile_config* cfg);
 
 typedef struct hdg_batch hdg_batch;
 
@@ -336,8 +346,9 @@ hdg_status hdg_batch_capture(hdg_batch* batch);
 /* One graph launch of the whole batch on `stream`. */
 hdg_status hdg_batch_launch(hdg_batch* batch, void* stream);
 
-/* Autotuner for degree k on this batch: times every candidate shape (workgroups_per_cu in
- * {1, 2, 4, 8, 16} x xcd_remap in {0, 1}), each once to warm up and then `reps` times on
+/* Autotuner for degree k on this batch: times every candidate shape (k = 1..3:
+ * workgroups_per_cu in {1, 2, 4, 8, 16} x xcd_remap in {0, 1}; k = 0, 4: workgroups_per_cu
+ * in {1, 2} x xcd_remap x waves_per_element in {1, 2, 4, 8}), each once to warm up and then `reps` times on
  * `stream` (the batch's degree-k outputs are overwritten with identical values), keeps the
  * fastest in the batch and returns it.  ncand, cands [16] and cand_ms [16] may be NULL;
  * else they receive every candidate and its mean time (ms).  Synchronises the stream.

@@ -28,7 +28,8 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_assemble_condense", "hdg_check_tau", "hdg_export_local", "hdg_boundary",
            "hdg_solve_workspace_size", "hdg_solve", "hdg_recover", "hdg_postprocess", "hdg_batch_create",
            "hdg_batch_destroy", "hdg_batch_info", "hdg_batch_set_config", "hdg_batch_get_config",
-           "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune"]
+           "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune", "hdg_set_launch_config",
+           "hdg_get_launch_config"]
 
 
 class HdgError(RuntimeError):
@@ -326,7 +327,7 @@ class hdg_batch_item(C.Structure):
 
 
 class hdg_tile_config(C.Structure):
-    _fields_ = [("workgroups_per_cu", C.c_int), ("xcd_remap", C.c_int)]
+    _fields_ = [("workgroups_per_cu", C.c_int), ("xcd_remap", C.c_int), ("waves_per_element", C.c_int)]
 
 
 class Batch:
@@ -372,15 +373,16 @@ def hdg_batch_info(batch: Batch, k: int):
     return nm.value, ne.value
 
 
-def hdg_batch_set_config(batch: Batch, k: int, workgroups_per_cu: int, xcd_remap: int):
-    cfg = hdg_tile_config(workgroups_per_cu, xcd_remap)
+def hdg_batch_set_config(batch: Batch, k: int, workgroups_per_cu: int, xcd_remap: int, waves_per_element: int = 1):
+    cfg = hdg_tile_config(workgroups_per_cu, xcd_remap, waves_per_element)
     _check(lib().hdg_batch_set_config(batch.handle, C.c_int(k), C.byref(cfg)))
 
 
 def hdg_batch_get_config(batch: Batch, k: int):
     cfg = hdg_tile_config()
     _check(lib().hdg_batch_get_config(batch.handle, C.c_int(k), C.byref(cfg)))
-    return {"workgroups_per_cu": cfg.workgroups_per_cu, "xcd_remap": cfg.xcd_remap}
+    return {"workgroups_per_cu": cfg.workgroups_per_cu, "xcd_remap": cfg.xcd_remap,
+            "waves_per_element": cfg.waves_per_element}
 
 
 def hdg_batch_condense(batch: Batch, stream=None):
@@ -403,7 +405,20 @@ def hdg_autotune(batch: Batch, k: int, reps: int = 3, stream=None):
     cms = (C.c_double * 16)()
     _check(lib().hdg_autotune(batch.handle, C.c_int(k), C.c_int(reps), C.byref(best), C.byref(best_ms), C.byref(nc),
                               cands, cms, _stream(stream)))
-    return {"best": {"workgroups_per_cu": best.workgroups_per_cu, "xcd_remap": best.xcd_remap},
-            "best_ms": best_ms.value,
-            "candidates": [{"workgroups_per_cu": cands[i].workgroups_per_cu, "xcd_remap": cands[i].xcd_remap,
-                            "ms": cms[i]} for i in range(nc.value)]}
+    shape = lambda c: {"workgroups_per_cu": c.workgroups_per_cu, "xcd_remap": c.xcd_remap,
+                       "waves_per_element": c.waves_per_element}
+    return {"best": shape(best), "best_ms": best_ms.value,
+            "candidates": [dict(shape(cands[i]), ms=cms[i]) for i in range(nc.value)]}
+
+
+def hdg_set_launch_config(k: int, workgroups_per_cu: int, xcd_remap: int, waves_per_element: int = 1):
+    cfg = hdg_tile_config(workgroups_per_cu, xcd_remap, waves_per_element)
+    _check(lib().hdg_set_launch_config(C.c_int(k), C.byref(cfg)))
+
+
+def hdg_get_launch_config(k: int):
+    cfg = hdg_tile_config()
+    _check(lib().hdg_get_launch_config(C.c_int(k), C.byref(cfg)))
+    return {"workgroups_per_cu": cfg.workgroups_per_cu, "xcd_remap": cfg.xcd_remap,
+            "waves_per_element": cfg.waves_per_element}
+

@@ -55,7 +55,8 @@ def tune_batch(batch, degrees, arch: str | None = None, cache_path: str = DEFAUL
     """
     from . import _lib as L
     tuner = tuner or (lambda b, k, r, s: L.hdg_autotune(b, k, reps=r, stream=s))
-    apply = apply or (lambda b, k, cfg: L.hdg_batch_set_config(b, k, cfg["workgroups_per_cu"], cfg["xcd_remap"]))
+    apply = apply or (lambda b, k, cfg: L.hdg_batch_set_config(b, k, cfg["workgroups_per_cu"], cfg["xcd_remap"],
+                                                               cfg.get("waves_per_element", 1)))
     arch = arch or device_arch()
     cache = load_cache(cache_path)
     out, dirty = {}, False
@@ -65,7 +66,8 @@ def tune_batch(batch, degrees, arch: str | None = None, cache_path: str = DEFAUL
         if ent is None or force:
             res = tuner(batch, k, reps, stream)
             ent = {"workgroups_per_cu": int(res["best"]["workgroups_per_cu"]),
-                   "xcd_remap": int(res["best"]["xcd_remap"]), "ms": float(res["best_ms"]),
+                   "xcd_remap": int(res["best"]["xcd_remap"]),
+                   "waves_per_element": int(res["best"].get("waves_per_element", 1)), "ms": float(res["best_ms"]),
                    "candidates": res.get("candidates", [])}
             cache[key] = ent
             dirty = True

@@ -30,6 +30,27 @@ const char* hdg_last_error(void) { return g_last_error.c_str(); }
 
 int hdg_max_degree(void) { return kMaxDegree; }
 
+// Launch shapes of the single-mesh condensation, per degree (persistent grids; the tile
+// kernels of k = 1..3 run four elements per wavefront, so waves_per_element is 1).
+static hdg_tile_config g_launch[kMaxDegree + 1] = {{2, 0, 1}, {4, 1, 1}, {4, 1, 1}, {4, 1, 1}, {1, 1, 8}};
+
+hdg_status hdg_set_launch_config(int k, const hdg_tile_config* cfg) {
+  if (k < 0 || k > kMaxDegree || !cfg) return set_error(HDG_ERR_INVALID_ARG, "hdg_set_launch_config: bad argument");
+  const bool tile = k >= 1 && k <= 3;
+  const int w = cfg->waves_per_element;
+  if (cfg->workgroups_per_cu < 1 || cfg->workgroups_per_cu > 64 || (cfg->xcd_remap != 0 && cfg->xcd_remap != 1) ||
+      (tile ? w != 1 : (w != 1 && w != 2 && w != 4 && w != 8)))
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_set_launch_config: shape out of range");
+  g_launch[k] = *cfg;
+  return HDG_OK;
+}
+
+hdg_status hdg_get_launch_config(int k, hdg_tile_config* cfg) {
+  if (k < 0 || k > kMaxDegree || !cfg) return set_error(HDG_ERR_INVALID_ARG, "hdg_get_launch_config: bad argument");
+  *cfg = g_launch[k];
+  return HDG_OK;
+}
+
 hdg_status hdg_disc_create(int k, int nq, hdg_disc** out) {
   if (!out) return set_error(HDG_ERR_INVALID_ARG, "hdg_disc_create: out is NULL");
   *out = nullptr;
@@ -148,3 +169,21 @@ hdg_status hdg_check_tau(const hdg_mesh* mesh, const double* d_tau, void* stream
 }
 
 }  // extern "C"
+
+namespace hdg {
+
+hdg_tile_config launch_config(int k) { return g_launch[k]; }
+
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
+
+}  // namespace hdg

@@ -13,9 +13,11 @@
 // i.e. the longest work, first); the captured form records them as parallel branches of
 // one hipGraph (a fork/join over one stream per degree), replayed by one graph launch.
 //
-// The autotuner times, for one degree, every persistent grid size in {1, 2, 4, 8, 16}
-// workgroups per compute unit, with and without the XCD-contiguous workgroup order, on
-// the batch itself, and keeps the fastest.
+// The autotuner times, for one degree, every candidate launch shape on the batch itself
+// and keeps the fastest: for the tile kernels the persistent grid size in {1, 2, 4, 8, 16}
+// workgroups per compute unit, with and without the XCD-contiguous workgroup order; for
+// the per-element kernel also the wavefronts per element in {1, 2, 4, 8} (its blocks fill
+// most of the LDS, so at most one or two workgroups fit on a CU).
 #include <algorithm>
 #include <vector>
 
@@ -39,8 +41,6 @@ __global__ void k_batch_zero(const BatchItem* __restrict__ items, int d2) {
   }
 }
 
-constexpr int kWpc[] = {1, 2, 4, 8, 16};
-
 }  // namespace
 }  // namespace hdg
 
@@ -55,7 +55,7 @@ struct hdg_batch {
     int total_units = 0;
     int64_t nelt = 0;
     int64_t max_zero = 0;  // largest nfc * d2 * d2 of the degree's meshes
-    hdg_tile_config cfg{0, 0};
+    hdg_tile_config cfg{0, 0, 1};
     hipStream_t side = nullptr;
     hipEvent_t join = nullptr;
   };
@@ -88,13 +88,31 @@ hdg_status run_degree(hdg_batch* b, int k, hipStream_t s) {
   }
   const int64_t grid = std::min<int64_t>((int64_t)D.cfg.workgroups_per_cu * b->ncu, D.total_units);
   return launch_batch_condense(k, D.tb, D.d_items, nit, D.total_units, (int)std::max<int64_t>(grid, 1),
-                               D.cfg.xcd_remap, s);
+                               D.cfg.xcd_remap, D.cfg.waves_per_element, s);
 }
 
-hdg_status check_cfg(const hdg_tile_config* c) {
+hdg_status check_cfg(int k, const hdg_tile_config* c) {
   if (!c || c->workgroups_per_cu < 1 || c->workgroups_per_cu > 64 || (c->xcd_remap != 0 && c->xcd_remap != 1))
     return set_error(HDG_ERR_INVALID_ARG, "tile config: workgroups_per_cu must be 1..64 and xcd_remap 0 or 1");
+  const int w = c->waves_per_element;
+  if (condense_unit(k) == 4 ? w != 1 : (w != 1 && w != 2 && w != 4 && w != 8))
+    return set_error(HDG_ERR_INVALID_ARG,
+                     "tile config: waves_per_element must be 1 for k = 1..3 and 1, 2, 4 or 8 for k = 0, 4");
   return HDG_OK;
+}
+
+// Candidate shapes of the autotuner for degree k.
+std::vector<hdg_tile_config> candidates(int k) {
+  std::vector<hdg_tile_config> v;
+  if (condense_unit(k) == 4) {
+    for (int wpc : {1, 2, 4, 8, 16})
+      for (int remap = 0; remap <= 1; ++remap) v.push_back({wpc, remap, 1});
+  } else {
+    for (int wpc : {1, 2})
+      for (int remap = 0; remap <= 1; ++remap)
+        for (int w : {1, 2, 4, 8}) v.push_back({wpc, remap, w});
+  }
+  return v;
 }
 
 }  // namespace
@@ -124,7 +142,7 @@ extern "C" hdg_status hdg_batch_create(int n, const hdg_batch_item* items, hdg_b
     if (D.items.empty()) {
       D.tb = it.disc->dev;
       D.d2 = it.disc->host.d2;
-      D.cfg = {condense_unit(k) == 4 ? 8 : 2, 0};
+      D.cfg = launch_config(k);
     }
     BatchItem bi{};
     bi.mesh = *it.mesh;
@@ -193,7 +211,7 @@ extern "C" hdg_status hdg_batch_info(const hdg_batch* b, int k, int64_t* nmesh, 
 
 extern "C" hdg_status hdg_batch_set_config(hdg_batch* b, int k, const hdg_tile_config* cfg) {
   if (!b || k < 0 || k > kMaxDegree) return set_error(HDG_ERR_INVALID_ARG, "hdg_batch_set_config: bad argument");
-  hdg_status st = check_cfg(cfg);
+  hdg_status st = check_cfg(k, cfg);
   if (st) return st;
   b->deg[k].cfg = *cfg;
   drop_graph(b);
@@ -276,9 +294,10 @@ extern "C" hdg_status hdg_autotune(hdg_batch* b, int k, int reps, hdg_tile_confi
   double bms = 1e300;
   int nc = 0;
   hdg_status st = HDG_OK;
-  for (int wpc : kWpc) {
-    for (int remap = 0; remap <= 1 && st == HDG_OK && e == hipSuccess; ++remap) {
-      D.cfg = {wpc, remap};
+  for (const hdg_tile_config& cand : candidates(k)) {
+    {
+      if (st || e != hipSuccess) break;
+      D.cfg = cand;
       st = run_degree(b, k, s);  // warm-up
       if (st) break;
       e = hipEventRecord(t0, s);

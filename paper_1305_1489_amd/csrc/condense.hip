@@ -190,20 +190,23 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   }
 }
 
-template <int K>
-__global__ void __launch_bounds__(64) k_condense(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+// EXPORT selects the debugging form (listed elements, C^K and Cf^K written out instead of
+// scattered); the scatter form is compiled with those pointers known to be null.
+template <int K, int NT, bool EXPORT>
+__global__ void __launch_bounds__(NT) k_condense(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                  const double* __restrict__ cco, const double* __restrict__ fco,
                                                  const double* __restrict__ tau, double* __restrict__ H,
                                                  double* __restrict__ F, double* __restrict__ factors,
                                                  const int* __restrict__ elems, int nwork, double* __restrict__ Cout,
-                                                 double* __restrict__ Cfout) {
-  for (int w = blockIdx.x; w < nwork; w += gridDim.x)
-    condense_element<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, elems, nwork, Cout, Cfout, w);
+                                                 double* __restrict__ Cfout, int xcd_remap) {
+  for (int w = batch_block(xcd_remap); w < nwork; w += gridDim.x)
+    condense_element<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
+                        EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w);
 }
 
 // Persistent batched form: work unit u is element u - unit_begin of its mesh.
-template <int K>
-__global__ void __launch_bounds__(64) k_batch_condense(const BatchItem* __restrict__ items, int nitems, int total_units,
+template <int K, int NT>
+__global__ void __launch_bounds__(NT) k_batch_condense(const BatchItem* __restrict__ items, int nitems, int total_units,
                                                        Tables tb, int xcd_remap) {
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
@@ -233,8 +236,21 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
     HDG_CHECK_LAUNCH("k_zero_diag");
   }
   if (n == 0) return HDG_OK;
-  const int grid = (int)std::min<int64_t>(n, 1 << 20);
-  k_condense<K><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout);
+  const hdg_tile_config lc = launch_config(K);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)lc.workgroups_per_cu * device_cu_count()));
+  const hdg_mesh& m = *mesh;
+  const Tables& tb = disc->dev;
+  const int rm = lc.xcd_remap;
+  if (Cout) {  // export form: one shape is enough
+    k_condense<K, 256, true><<<grid, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm);
+  } else {
+    switch (lc.waves_per_element) {
+      case 1: k_condense<K, 64, false><<<grid, 64, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
+      case 2: k_condense<K, 128, false><<<grid, 128, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
+      case 4: k_condense<K, 256, false><<<grid, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
+      default: k_condense<K, 512, false><<<grid, 512, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
+    }
+  }
   HDG_CHECK_LAUNCH("k_condense");
   return HDG_OK;
 }
@@ -254,9 +270,6 @@ hdg_status dispatch_condense(const hdg_disc* disc, const hdg_mesh* mesh, const d
     return dispatch_condense_tile(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
   switch (disc->host.k) {
     case 0: return run_condense<0>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
-    case 1: return run_condense<1>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
-    case 2: return run_condense<2>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
-    case 3: return run_condense<3>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
     case 4: return run_condense<4>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "unsupported degree");
@@ -269,17 +282,33 @@ hdg_status launch_batch_condense_tile(int k, const Tables& tb, const BatchItem* 
 
 int condense_unit(int k) { return (k >= 1 && k <= 3) ? 4 : 1; }
 
-hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
-                                 int grid, int xcd_remap, hipStream_t s) {
-  if (nitems <= 0 || total_units <= 0) return HDG_OK;
-  if (k >= 1 && k <= 3) return launch_batch_condense_tile(k, tb, d_items, nitems, total_units, grid, xcd_remap, s);
-  switch (k) {
-    case 0: k_batch_condense<0><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
-    case 4: k_batch_condense<4><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
-    default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "batched condensation: unsupported degree");
+namespace {
+
+template <int K>
+hdg_status launch_batch_element(const Tables& tb, const BatchItem* d_items, int nitems, int total_units, int grid,
+                                int xcd_remap, int waves, hipStream_t s) {
+  switch (waves) {
+    case 1: k_batch_condense<K, 64><<<grid, 64, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    case 2: k_batch_condense<K, 128><<<grid, 128, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    case 4: k_batch_condense<K, 256><<<grid, 256, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    case 8: k_batch_condense<K, 512><<<grid, 512, 0, s>>>(d_items, nitems, total_units, tb, xcd_remap); break;
+    default: return set_error(HDG_ERR_INVALID_ARG, "batched condensation: waves_per_element must be 1, 2, 4 or 8");
   }
   HDG_CHECK_LAUNCH("k_batch_condense");
   return HDG_OK;
+}
+
+}  // namespace
+
+hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
+                                 int grid, int xcd_remap, int waves, hipStream_t s) {
+  if (nitems <= 0 || total_units <= 0) return HDG_OK;
+  if (k >= 1 && k <= 3) return launch_batch_condense_tile(k, tb, d_items, nitems, total_units, grid, xcd_remap, s);
+  switch (k) {
+    case 0: return launch_batch_element<0>(tb, d_items, nitems, total_units, grid, xcd_remap, waves, s);
+    case 4: return launch_batch_element<4>(tb, d_items, nitems, total_units, grid, xcd_remap, waves, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "batched condensation: unsupported degree");
 }
 
 hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const char* who) {

@@ -326,15 +326,19 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
   }
 }
 
-template <int K>
+// EXPORT selects the debugging form (listed elements, C^K and Cf^K written out instead of
+// scattered); the scatter form is compiled with those pointers known to be null.
+template <int K, bool EXPORT>
 __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
                                                       const double* __restrict__ tau, double* __restrict__ H,
                                                       double* __restrict__ F, double* __restrict__ factors,
                                                       const int* __restrict__ elems, int nwork,
-                                                      double* __restrict__ Cout, double* __restrict__ Cfout) {
-  for (int w0 = blockIdx.x * 4; w0 < nwork; w0 += gridDim.x * 4)
-    condense_tile_group<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, elems, nwork, Cout, Cfout, w0);
+                                                      double* __restrict__ Cout, double* __restrict__ Cfout,
+                                                      int xcd_remap) {
+  for (int w0 = batch_block(xcd_remap) * 4; w0 < nwork; w0 += gridDim.x * 4)
+    condense_tile_group<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
+                           EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w0);
 }
 
 // Persistent batched form: work unit u is group u - unit_begin of its mesh.
@@ -369,8 +373,14 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
   }
   if (n == 0) return HDG_OK;
   const int64_t groups = (n + 3) / 4;
-  const int grid = (int)std::min<int64_t>(groups, 1 << 20);
-  k_condense_tile<K><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout);
+  const hdg_tile_config lc = launch_config(K);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)lc.workgroups_per_cu * device_cu_count()));
+  if (Cout)
+    k_condense_tile<K, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n,
+                                                 Cout, Cfout, lc.xcd_remap);
+  else
+    k_condense_tile<K, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n,
+                                                  Cout, Cfout, lc.xcd_remap);
   HDG_CHECK_LAUNCH("k_condense_tile");
   return HDG_OK;
 }

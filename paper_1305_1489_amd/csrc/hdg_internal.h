@@ -76,11 +76,17 @@ struct BatchItem {
 // Elements per work unit of the condensation kernel used for degree k.
 int condense_unit(int k);
 
+// Launch shape of the single-mesh condensation for degree k (hdg_set_launch_config).
+hdg_tile_config launch_config(int k);
+// Compute units of the current device (cached per device).
+int device_cu_count();
+
 // Persistent batched condensation of every mesh of degree k listed in d_items (device
 // array, sorted by unit_begin); grid workgroups take the units round-robin, and with
-// xcd_remap each of the eight XCDs takes a contiguous run of units per sweep.
+// xcd_remap each of the eight XCDs takes a contiguous run of units per sweep.  waves is
+// the number of wavefronts per element of the per-element kernel (k = 0, 4; 1, 2, 4 or 8).
 hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_items, int nitems, int total_units,
-                                 int grid, int xcd_remap, hipStream_t s);
+                                 int grid, int xcd_remap, int waves, hipStream_t s);
 
 }  // namespace hdg
 

@@ -70,13 +70,13 @@ def test_batch_equals_per_mesh_launches_bitwise():
     torch.cuda.synchronize()
     _assert_same(systems, refs, "eager")
     # every launch shape gives the same bits
-    for wpc, remap in ((1, 0), (3, 1), (16, 1)):
+    for wpc, remap, waves in ((1, 0, 1), (3, 1, 2), (16, 1, 8), (2, 0, 4)):
         for k in range(5):
-            L.hdg_batch_set_config(b, k, wpc, remap)
+            L.hdg_batch_set_config(b, k, wpc, remap, waves if k in (0, 4) else 1)
         _nan_fill(systems)
         L.hdg_batch_condense(b)
         torch.cuda.synchronize()
-        _assert_same(systems, refs, f"eager wpc={wpc} remap={remap}")
+        _assert_same(systems, refs, f"eager wpc={wpc} remap={remap} waves={waves}")
 
 
 def test_batch_graph_replays_and_autotune():
@@ -96,9 +96,11 @@ def test_batch_graph_replays_and_autotune():
     print("autotune", flush=True)
     for k in range(5):
         res = L.hdg_autotune(b, k, reps=1)
-        assert len(res["candidates"]) == 10
+        assert len(res["candidates"]) == (16 if k in (0, 4) else 10)
         assert res["best_ms"] > 0
-        assert res["best"] in [{kk: c[kk] for kk in ("workgroups_per_cu", "xcd_remap")} for c in res["candidates"]]
+        keys = ("workgroups_per_cu", "xcd_remap", "waves_per_element")
+        assert res["best"] in [{kk: c[kk] for kk in keys} for c in res["candidates"]]
+        assert res["best_ms"] == min(c["ms"] for c in res["candidates"])
         assert L.hdg_batch_get_config(b, k) == res["best"]
     for rep in range(2):
         _nan_fill(systems)
@@ -118,4 +120,28 @@ def test_batch_rejects_bad_items():
     with pytest.raises(L.HdgError):
         L.hdg_batch_set_config(b, 1, 0, 0)
     with pytest.raises(L.HdgError):
+        L.hdg_batch_set_config(b, 1, 4, 0, 2)  # the tile kernels run one wavefront per four elements
+    with pytest.raises(L.HdgError):
         L.hdg_autotune(b, 2, reps=1)  # no mesh of degree 2 in this batch
+
+
+def test_single_mesh_launch_shapes_bitwise():
+    """hdg_assemble_condense under every library-wide launch shape gives the same bits."""
+    from paper_1305_1489_amd import _lib as L
+    systems = _systems()
+    refs = _references(systems)
+    saved = {k: L.hdg_get_launch_config(k) for k in range(5)}
+    try:
+        for wpc, remap, waves in ((1, 0, 1), (16, 1, 2), (3, 1, 4), (2, 0, 8)):
+            for k in range(5):
+                L.hdg_set_launch_config(k, wpc, remap, waves if k in (0, 4) else 1)
+            _nan_fill(systems)
+            for S in systems:
+                S.assemble()
+            torch.cuda.synchronize()
+            _assert_same(systems, refs, f"single-mesh wpc={wpc} remap={remap} waves={waves}")
+        with pytest.raises(L.HdgError):
+            L.hdg_set_launch_config(2, 4, 1, 4)
+    finally:
+        for k, c in saved.items():
+            L.hdg_set_launch_config(k, c["workgroups_per_cu"], c["xcd_remap"], c["waves_per_element"])
