@@ -185,6 +185,9 @@ def batch_metric(args):
             "per_degree": per_k, "tuning_s": tune_s}
 
 
+GNN_CHECKPOINT = os.path.join(ROOT, "paper_1305_1489_amd", "checkpoints", "gnn_k2.safetensors")
+
+
 def solve_metric(args):
     import torch
     from hdg_inputs import config, kuhn_mesh
@@ -195,18 +198,40 @@ def solve_metric(args):
     S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, cfg["k"], cfg["problem"]())
     out = {"workload": "lognormal: Kuhn 32^3 cube, 196608 tets, k=2, kappa=exp(1.5 g) (corr. length 0.1), c=0.1",
            "metric": "solve time to rel.res 1e-10", "unit": "s", "unknowns": int(S.mesh.nfc * S.disc.d2)}
-    for prec, name in ((0, "fp64_block_jacobi"), (1, "fp32_refined")):
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.gnn import LearnedPreconditioner
+    ck = args.gnn or GNN_CHECKPOINT
+    LP = LearnedPreconditioner.load(ck) if os.path.exists(ck) else None
+    forms = [(0, None, "fp64_block_jacobi"), (1, None, "fp32_refined")]
+    if LP is not None:
+        forms += [(0, LP, "learned"), (1, LP, "learned_fp32_refined")]
+    else:
+        log(f"no trained network at {ck}: learned forms skipped")
+    for prec, lp, name in forms:
         S.assemble()
         S.uhat.zero_()
         S.boundary()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = S.solve(rtol=1e-10, precision=prec, check_every=50)
+        learned = None
+        if lp is not None:  # preconditioner set-up (graph + inference) is inside the timed region
+            g, N = lp.prepare(S.disc, S.mesh, S.H)
+            learned = (N, g)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        info = L.hdg_solve(S.disc, S.mesh, S.H, S.F, S.uhat, rtol=1e-10, precision=prec, check_every=50,
+                           learned=learned)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = {"seconds": dt, "iterations": info["iterations"], "outer": info["outer"],
-                     "true_rel_residual": info["rel_residual"]}
-        log(f"solve {name}: {dt:.3f} s, {info['iterations']} it, relres {info['rel_residual']:.2e}")
+                     "true_rel_residual": info["rel_residual"], "fell_back": info["fell_back"],
+                     "setup_seconds": t_setup}
+        log(f"solve {name}: {dt:.3f} s (setup {t_setup:.3f}), {info['iterations']} it, "
+            f"relres {info['rel_residual']:.2e}")
+    if LP is not None:
+        out["network"] = {"checkpoint": os.path.relpath(ck, ROOT), "hidden": LP.hidden, "layers": LP.layers,
+                          **{k: LP.meta[k] for k in ("systems", "train_seconds", "train_steps", "first_loss",
+                                                     "last_loss") if k in LP.meta}}
     return out
 
 
@@ -218,6 +243,7 @@ def main():
     ap.add_argument("--workload", default="jitter_k3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--gnn", default=None, help="checkpoint of the learned preconditioner (default: the packaged one)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-condensation workload")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")

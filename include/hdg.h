@@ -244,12 +244,18 @@ typedef struct {
   int check_every;    /* iterations between host convergence checks (>= 1) */
   int precision;      /* 0: FP64 throughout; 1: FP32 matrix and preconditioner inside
                          an FP64 iterative-refinement loop */
+  int precond;        /* 0: block-Jacobi; 1: learned factor (needs the three arrays below) */
+  const float* d_pre_N;      /* [nnzb][d2][d2] N of the learned factor (hdg_gnn_forward) */
+  const float* d_pre_Linv;   /* [nfc][d2][d2]  hdg_gnn_graph.Linv */
+  const int32_t* d_pre_mirror; /* [nnzb]      hdg_gnn_graph.mirror */
 } hdg_solve_opts;
 
 typedef struct {
-  int iterations;     /* total inner iterations */
+  int iterations;     /* total inner iterations (both attempts when fell_back) */
   int outer;          /* refinement sweeps (precision 1) */
   double rel_residual;/* true relative residual ||b - H x|| / ||b|| in FP64 */
+  int fell_back;      /* 1: the learned-preconditioner run did not converge and block-Jacobi
+                         PCG finished the solve */
 } hdg_solve_info;
 
 hdg_status hdg_solve_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, int precision, size_t* ws_bytes);
@@ -282,6 +288,62 @@ hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
  * ------------------------------------------------------------------------------ */
 hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_tau,
                            const double* d_q, const double* d_u, double* d_ustar, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Learned face-graph preconditioner for eq 6.5 (the paper leaves the solver open).
+ *
+ * With H_ii = L_i L_i^T and Hs_ij = L_i^{-1} H_ij L_j^{-T} (block-Jacobi scaling), the
+ * preconditioner is M^{-1} = L^{-T} G^T G L^{-1} with G = I + N and N strictly block-lower
+ * on the pattern of H.  It is SPD for every N.  A message-passing network over the faces
+ * (FP32; nodes = faces, edges = off-diagonal blocks of H) predicts N.  Its node features
+ * are the face type, the log area and the row energy of Hs; its edge features are the
+ * entries of Hs_ij.  The layers are
+ *     X = relu(W0 a + c0), E = relu(We b + ce),
+ *     M_ij = relu(Wm_l [X_i; X_j; E_ij] + cm_l), X_i += relu(Wu_l [X_i; sum_j M_ij] + cu_l),
+ * and the head is
+ *     N_ij = -Hs_ij + reshape(Wo [X_i; X_j; E_ij] + co)   (j < i, no Dirichlet face).
+ * The parameters form one FP32 vector in the order W0, c0, We, ce, (Wm_l, cm_l, Wu_l,
+ * cu_l) for l = 1..L, Wo, co; matrices are row-major (output, input).
+ * Training objective (the Kaporin measure: G is unit triangular, so the determinant of
+ * G Hs G^T is fixed and its trace is what remains):
+ *     loss = 1/(p n) sum_z (G^T z)^T Hs (G^T z)   over p probe vectors z, n = nfc d2.
+ * Every array is caller-owned device memory.  No call allocates, and every reduction
+ * has a fixed order.
+ * ------------------------------------------------------------------------------ */
+typedef struct {
+  int d2;       /* block size: 1, 3, 6, 10 or 15 (degree 0..4) */
+  int hidden;   /* channels, 1..64 */
+  int layers;   /* message-passing layers, 0..8 */
+} hdg_gnn_shape;
+
+typedef struct {
+  float* Hs;        /* [nnzb][d2][d2]  scaled blocks (diagonal blocks: identity) */
+  float* Linv;      /* [nfc][d2][d2]   L_i^{-1} (lower triangular) */
+  float* node;      /* [nfc][5]        node features */
+  int32_t* erow;    /* [nnzb]          block row of each stored block */
+  int32_t* mirror;  /* [nnzb]          position of the transposed block */
+} hdg_gnn_graph;
+
+hdg_status hdg_gnn_param_count(const hdg_gnn_shape* shape, int64_t* n);
+/* Graph of one system from H after hdg_boundary (Dirichlet rows are the identity).
+ * Workspace: hdg_gnn_graph_workspace_size bytes (FP64 factors).  Errors:
+ * HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE, HDG_ERR_UNSUPPORTED_DEGREE. */
+hdg_status hdg_gnn_graph_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes);
+hdg_status hdg_gnn_build_graph(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H, hdg_gnn_graph* graph,
+                               void* d_ws, size_t ws_bytes, void* stream);
+/* Activations and temporaries of forward / backward for nprobe probe vectors. */
+hdg_status hdg_gnn_workspace_size(const hdg_gnn_shape* shape, const hdg_mesh* mesh, int nprobe, size_t* bytes);
+/* d_N [nnzb][d2][d2]: N on the lower blocks without Dirichlet faces, zero elsewhere. */
+hdg_status hdg_gnn_forward(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
+                           const hdg_gnn_graph* graph, float* d_N, void* d_ws, size_t ws_bytes, void* stream);
+/* Forward, the probe loss and its gradient: d_probes [nprobe][nfc][d2] (drawn by the
+ * caller), d_loss one double (device), d_grad [param_count] (NULL: loss only). */
+hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
+                             const hdg_gnn_graph* graph, const float* d_probes, int nprobe, float* d_N,
+                             double* d_loss, float* d_grad, void* d_ws, size_t ws_bytes, void* stream);
+/* One Adam step (step = 1, 2, ...) on n parameters. */
+hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr,
+                        float beta1, float beta2, float eps, void* stream);
 
 /* ------------------------------------------------------------------------------
  * Batched condensation of many independent meshes of mixed degree in one launch.

@@ -29,7 +29,8 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_solve_workspace_size", "hdg_solve", "hdg_recover", "hdg_postprocess", "hdg_batch_create",
            "hdg_batch_destroy", "hdg_batch_info", "hdg_batch_set_config", "hdg_batch_get_config",
            "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune", "hdg_set_launch_config",
-           "hdg_get_launch_config"]
+           "hdg_get_launch_config", "hdg_gnn_param_count", "hdg_gnn_graph_workspace_size", "hdg_gnn_build_graph",
+           "hdg_gnn_workspace_size", "hdg_gnn_forward", "hdg_gnn_loss_grad", "hdg_gnn_adam"]
 
 
 class HdgError(RuntimeError):
@@ -52,11 +53,13 @@ class hdg_disc_info(C.Structure):
 
 
 class hdg_solve_opts(C.Structure):
-    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("precision", C.c_int)]
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("precision", C.c_int),
+                ("precond", C.c_int), ("d_pre_N", C.c_void_p), ("d_pre_Linv", C.c_void_p),
+                ("d_pre_mirror", C.c_void_p)]
 
 
 class hdg_solve_info(C.Structure):
-    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("rel_residual", C.c_double)]
+    _fields_ = [("iterations", C.c_int), ("outer", C.c_int), ("rel_residual", C.c_double), ("fell_back", C.c_int)]
 
 
 _lib = None
@@ -285,15 +288,23 @@ def hdg_solve_workspace_size(disc: Disc, mesh: Mesh, precision: int = 0) -> int:
 
 
 def hdg_solve(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=100000, check_every=10, precision=0,
-              ws=None, stream=None, raise_on_fail=True):
+              ws=None, stream=None, raise_on_fail=True, learned=None):
+    """learned: None (block-Jacobi) or (N, graph) from hdg_gnn_forward / hdg_gnn_build_graph."""
     need = hdg_solve_workspace_size(disc, mesh, precision)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 8), dtype=torch.uint8, device=mesh.device)
     opts = hdg_solve_opts(rtol=rtol, max_iter=max_iter, check_every=check_every, precision=precision)
+    if learned is not None:
+        N, graph = learned
+        opts.precond = 1
+        opts.d_pre_N = N.data_ptr()
+        opts.d_pre_Linv = graph.Linv.data_ptr()
+        opts.d_pre_mirror = graph.mirror.data_ptr()
     info = hdg_solve_info()
     code = lib().hdg_solve(disc.handle, C.byref(mesh.struct), _ptr(H), _ptr(b), _ptr(uhat), C.byref(opts),
                            C.byref(info), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream))
-    out = {"iterations": info.iterations, "outer": info.outer, "rel_residual": info.rel_residual, "status": code}
+    out = {"iterations": info.iterations, "outer": info.outer, "rel_residual": info.rel_residual, "status": code,
+           "fell_back": bool(info.fell_back)}
     if code != 0 and raise_on_fail:
         _check(code)
     return out
@@ -421,4 +432,91 @@ def hdg_get_launch_config(k: int):
     _check(lib().hdg_get_launch_config(C.c_int(k), C.byref(cfg)))
     return {"workgroups_per_cu": cfg.workgroups_per_cu, "xcd_remap": cfg.xcd_remap,
             "waves_per_element": cfg.waves_per_element}
+
+
+# ----------------------------------------------------------------------------- learned preconditioner
+class hdg_gnn_shape(C.Structure):
+    _fields_ = [("d2", C.c_int), ("hidden", C.c_int), ("layers", C.c_int)]
+
+
+class hdg_gnn_graph(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("Hs", "Linv", "node", "erow", "mirror")]
+
+
+class GnnGraph:
+    """Owns the graph arrays of one system (hdg_gnn_build_graph)."""
+
+    def __init__(self, nfc, nnzb, d2, device):
+        f32 = dict(dtype=torch.float32, device=device)
+        self.Hs = torch.zeros((nnzb, d2, d2), **f32)
+        self.Linv = torch.zeros((nfc, d2, d2), **f32)
+        self.node = torch.zeros((nfc, 5), **f32)
+        self.erow = torch.zeros(nnzb, dtype=torch.int32, device=device)
+        self.mirror = torch.zeros(nnzb, dtype=torch.int32, device=device)
+        g = hdg_gnn_graph()
+        for n in ("Hs", "Linv", "node", "erow", "mirror"):
+            setattr(g, n, getattr(self, n).data_ptr())
+        self.struct = g
+
+
+def _shape(shape):
+    return shape if isinstance(shape, hdg_gnn_shape) else hdg_gnn_shape(*shape)
+
+
+def hdg_gnn_param_count(shape) -> int:
+    n = C.c_int64()
+    _check(lib().hdg_gnn_param_count(C.byref(_shape(shape)), C.byref(n)))
+    return n.value
+
+
+def hdg_gnn_build_graph(disc: Disc, mesh: Mesh, H, stream=None) -> GnnGraph:
+    g = GnnGraph(mesh.nfc, mesh.nnzb, disc.d2, mesh.device)
+    need = C.c_size_t()
+    _check(lib().hdg_gnn_graph_workspace_size(disc.handle, C.byref(mesh.struct), C.byref(need)))
+    ws = torch.empty(max(need.value, 8), dtype=torch.uint8, device=mesh.device)
+    _check(lib().hdg_gnn_build_graph(disc.handle, C.byref(mesh.struct), _ptr(H), C.byref(g.struct), _ptr(ws),
+                                     C.c_size_t(ws.numel()), _stream(stream)))
+    g._ws = ws  # kept until the queued kernels are done with it
+    return g
+
+
+def hdg_gnn_workspace(shape, mesh: Mesh, nprobe=0):
+    need = C.c_size_t()
+    _check(lib().hdg_gnn_workspace_size(C.byref(_shape(shape)), C.byref(mesh.struct), C.c_int(nprobe),
+                                        C.byref(need)))
+    return torch.empty(max(need.value, 8), dtype=torch.uint8, device=mesh.device)
+
+
+def hdg_gnn_forward(shape, params, mesh: Mesh, graph: GnnGraph, N=None, ws=None, stream=None):
+    shp = _shape(shape)
+    if N is None:
+        N = torch.empty((mesh.nnzb, shp.d2, shp.d2), dtype=torch.float32, device=mesh.device)
+    if ws is None:
+        ws = hdg_gnn_workspace(shp, mesh, 0)
+    _check(lib().hdg_gnn_forward(C.byref(shp), _ptr(params), C.byref(mesh.struct), C.byref(graph.struct), _ptr(N),
+                                 _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return N
+
+
+def hdg_gnn_loss_grad(shape, params, mesh: Mesh, graph: GnnGraph, probes, N=None, grad=None, want_grad=True,
+                      ws=None, stream=None):
+    """Returns (loss as a 1-element device tensor, grad, N)."""
+    shp = _shape(shape)
+    np_ = probes.shape[0]
+    if N is None:
+        N = torch.empty((mesh.nnzb, shp.d2, shp.d2), dtype=torch.float32, device=mesh.device)
+    if want_grad and grad is None:
+        grad = torch.empty(hdg_gnn_param_count(shp), dtype=torch.float32, device=mesh.device)
+    if ws is None:
+        ws = hdg_gnn_workspace(shp, mesh, np_)
+    loss = torch.empty(1, dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_gnn_loss_grad(C.byref(shp), _ptr(params), C.byref(mesh.struct), C.byref(graph.struct),
+                                   _ptr(probes), C.c_int(np_), _ptr(N), _ptr(loss), _ptr(grad) if want_grad else None,
+                                   _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return loss, grad, N
+
+
+def hdg_gnn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().hdg_gnn_adam(C.c_int64(params.numel()), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), C.c_int(step),
+                              C.c_float(lr), C.c_float(beta1), C.c_float(beta2), C.c_float(eps), _stream(stream)))
 

@@ -143,6 +143,96 @@ __global__ void k_precond(const TM* __restrict__ Minv, const TV* __restrict__ r,
   z[i] = (TV)s;
 }
 
+// Learned factor M^{-1} = L^{-T} G^T G L^{-1}, G = I + N (N strictly block-lower, FP32,
+// stored at the positions of the lower blocks of H; Linv the FP32 inverse Cholesky factors
+// of the diagonal blocks).  Two sweeps, one thread per face, FP64 accumulation:
+//   s_i = t_i + sum_{j < i} N_ij t_j,  t = L^{-1} r            (lower rows)
+//   z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i)              (through the mirror index)
+// One thread per (face, component), the faces of a workgroup contiguous (Lpre::FACES), so
+// that the threads of a face read whole block rows and the workgroup exchanges a face's
+// components through LDS.
+template <int D2>
+struct Lpre {
+  static constexpr int FACES = 256 / D2;
+  static constexpr int THREADS = FACES * D2;
+};
+
+// t = L^{-1} r
+template <int D2, class TV>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_scale(const float* __restrict__ Linv,
+                                                                  const TV* __restrict__ r, TV* __restrict__ t,
+                                                                  int nfc) {
+  const int i = blockIdx.x * Lpre<D2>::FACES + threadIdx.x / D2, a = threadIdx.x % D2;
+  if (i >= nfc) return;
+  const float* La = Linv + ((size_t)i * D2 + a) * D2;
+  const TV* ri = r + (size_t)i * D2;
+  double acc = 0.0;
+#pragma unroll
+  for (int b = 0; b < D2; ++b)
+    if (b <= a) acc += (double)La[b] * (double)ri[b];
+  t[(size_t)i * D2 + a] = (TV)acc;
+}
+
+// s_i = t_i + sum_{j < i} N_ij t_j: the lower blocks of row i are the entries before the
+// diagonal (columns ascend)
+template <int D2, class TV>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_lower(const int* __restrict__ row_ptr,
+                                                                  const int* __restrict__ diag,
+                                                                  const int* __restrict__ col,
+                                                                  const float* __restrict__ N,
+                                                                  const TV* __restrict__ t, TV* __restrict__ s,
+                                                                  int nfc) {
+  const int i = blockIdx.x * Lpre<D2>::FACES + threadIdx.x / D2, a = threadIdx.x % D2;
+  if (i >= nfc) return;
+  const int e0 = row_ptr[i], e1 = diag[i];
+  double acc = (double)t[(size_t)i * D2 + a];
+#pragma unroll 3
+  for (int e = e0; e < e1; ++e) {
+    const TV* tj = t + (size_t)col[e] * D2;
+    const float* Na = N + ((size_t)e * D2 + a) * D2;
+#pragma unroll
+    for (int b = 0; b < D2; ++b) acc += (double)Na[b] * (double)tj[b];
+  }
+  s[(size_t)i * D2 + a] = (TV)acc;
+}
+
+// z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i): the upper entries of row j, each read
+// through its mirror (block N_ij, column a)
+template <int D2, class TV>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_upper(const int* __restrict__ row_ptr,
+                                                                  const int* __restrict__ diag,
+                                                                  const int* __restrict__ col,
+                                                                  const int* __restrict__ mirror,
+                                                                  const float* __restrict__ N,
+                                                                  const float* __restrict__ Linv,
+                                                                  const TV* __restrict__ s, TV* __restrict__ z,
+                                                                  int nfc) {
+  __shared__ double ys[Lpre<D2>::THREADS];
+  const int lf = threadIdx.x / D2, a = threadIdx.x % D2;
+  const int j = blockIdx.x * Lpre<D2>::FACES + lf;
+  double y = 0.0;
+  if (j < nfc) {
+    y = (double)s[(size_t)j * D2 + a];
+    const int e0 = diag[j] + 1, e1 = row_ptr[j + 1];
+#pragma unroll 3
+    for (int e = e0; e < e1; ++e) {
+      const float* Nb = N + (size_t)mirror[e] * D2 * D2 + a;
+      const TV* si = s + (size_t)col[e] * D2;
+#pragma unroll
+      for (int b = 0; b < D2; ++b) y += (double)Nb[b * D2] * (double)si[b];
+    }
+  }
+  ys[threadIdx.x] = y;
+  __syncthreads();
+  if (j >= nfc) return;
+  const float* Lj = Linv + (size_t)j * D2 * D2;
+  double v = 0.0;
+#pragma unroll
+  for (int b = 0; b < D2; ++b)
+    if (b >= a) v += (double)Lj[b * D2 + a] * ys[lf * D2 + b];
+  z[(size_t)j * D2 + a] = (TV)v;
+}
+
 // scal[0] = rz, scal[1] = pAp, scal[2] = rz_new, scal[3] = rr
 // x += alpha p, r -= alpha Ap, alpha = rz / pAp
 template <class TV>
@@ -216,12 +306,12 @@ size_t ws_size(const hdg_mesh* mesh, int d2, int precision) {
   const size_t n = (size_t)mesh->nfc * d2;
   size_t b = 0;
   auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
-  for (int i = 0; i < 4; ++i) add(n * sizeof(double));  // r z p Ap
+  for (int i = 0; i < 5; ++i) add(n * sizeof(double));  // r z p Ap, and the learned factor's sweep
   add((size_t)mesh->nfc * d2 * d2 * sizeof(double));    // Minv
   add(kRedBlocks * sizeof(double));
   add(8 * sizeof(double));
   if (precision == 1) {
-    for (int i = 0; i < 5; ++i) add(n * sizeof(float));  // d r z p Ap (inner)
+    for (int i = 0; i < 6; ++i) add(n * sizeof(float));  // d r z p Ap sweep (inner)
     add((size_t)mesh->nnzb * d2 * d2 * sizeof(float));   // H in FP32
     add((size_t)mesh->nfc * d2 * d2 * sizeof(float));    // Minv in FP32
   }
@@ -259,12 +349,14 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   double* z = cv.take<double>(n);
   double* p = cv.take<double>(n);
   double* Ap = cv.take<double>(n);
+  double* sw = cv.take<double>(n);
   double* Minv = cv.take<double>((size_t)mesh->nfc * D2 * D2);
   double* part = cv.take<double>(kRedBlocks);
   double* scal = cv.take<double>(8);
   float *d32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *H32 = nullptr,
-        *Minv32 = nullptr;
+        *Minv32 = nullptr, *sw32 = nullptr;
   if (o->precision == 1) {
+    sw32 = cv.take<float>(n);
     d32 = cv.take<float>(n);
     r32 = cv.take<float>(n);
     z32 = cv.take<float>(n);
@@ -279,6 +371,31 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   const unsigned gr = (unsigned)((n + T - 1) / T);
   Solver<D2> S{mesh, s, n, gv, gr, part, scal};
   const int nfc = (int)mesh->nfc;
+  const bool learned = o->precond == 1;
+  const unsigned gf = (unsigned)((nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES);
+  constexpr unsigned TL = Lpre<D2>::THREADS;
+  auto pre64 = [&](const double* rr_, double* zz_) {
+    if (learned) {  // t -> zz_, s -> sw, then z -> zz_
+      k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
+      k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N, zz_,
+                                                 sw, nfc);
+      k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_mirror,
+                                                 o->d_pre_N, o->d_pre_Linv, sw, zz_, nfc);
+    } else {
+      k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, rr_, zz_, nfc);
+    }
+  };
+  auto pre32 = [&](const float* rr_, float* zz_) {
+    if (learned) {
+      k_lpre_scale<D2, float><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
+      k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N, zz_,
+                                                sw32, nfc);
+      k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_mirror,
+                                                o->d_pre_N, o->d_pre_Linv, sw32, zz_, nfc);
+    } else {
+      k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, rr_, zz_, nfc);
+    }
+  };
   k_bj_setup<D2, double><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv);
   // ||b||
   S.dot(b, b, scal + 4);
@@ -295,7 +412,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   const int every = std::max(1, o->check_every);
   if (o->precision == 0) {
     k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
-    k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, r, z, nfc);
+    pre64(r, z);
     k_copy<double><<<gv, T, 0, s>>>(z, p, n);
     S.dot(r, z, scal + 0);
     int it = 0;
@@ -306,6 +423,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
         HDG_CHECK_LAUNCH("hdg_solve");
         if (!std::isfinite(rr)) {
           info->iterations = it;
+          info->rel_residual = std::nan("");
           return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: breakdown (non-finite residual)");
         }
         if (rr <= tol2 || it >= o->max_iter) {
@@ -319,7 +437,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
           if (it >= o->max_iter)
             return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: iteration limit reached");
           // residual replacement and restart
-          k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, r, z, nfc);
+          pre64(r, z);
           k_copy<double><<<gv, T, 0, s>>>(z, p, n);
           S.dot(r, z, scal + 0);
         }
@@ -327,7 +445,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       k_spmv<D2, double, double><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, p, Ap, nfc);
       S.dot(p, Ap, scal + 1);
       k_update_xr<double><<<gv, T, 0, s>>>(x, r, p, Ap, scal, n);
-      k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, r, z, nfc);
+      pre64(r, z);
       S.dot(r, z, scal + 2);
       k_update_p<double><<<gv, T, 0, s>>>(p, z, scal, n);
       k_shift_rz<<<1, 1, 0, s>>>(scal);
@@ -348,13 +466,16 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
     info->outer = outer;
     info->iterations = total;
     info->rel_residual = std::sqrt(rr / bb);
-    if (!std::isfinite(rr)) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: breakdown in refinement");
+    if (!std::isfinite(rr)) {
+      info->rel_residual = std::nan("");
+      return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: breakdown in refinement");
+    }
     if (rr <= tol2) return HDG_OK;
     if (total >= o->max_iter) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve: iteration limit reached");
     // inner: H d = r / ||r|| in FP32 storage, d = 0
     k_scale_cast<double, float><<<gv, T, 0, s>>>(r, r32, n, scal + 5);
     k_fill<float><<<gv, T, 0, s>>>(d32, n, 0.0);
-    k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, r32, z32, nfc);
+    pre32(r32, z32);
     k_copy<float><<<gv, T, 0, s>>>(z32, p32, n);
     S.dot(r32, z32, scal + 0);
     const double in_tol2 = inner_rtol * inner_rtol;  // relative to ||r32|| = 1
@@ -367,7 +488,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       k_spmv<D2, float, float><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H32, p32, Ap32, nfc);
       S.dot(p32, Ap32, scal + 1);
       k_update_xr<float><<<gv, T, 0, s>>>(d32, r32, p32, Ap32, scal, n);
-      k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, r32, z32, nfc);
+      pre32(r32, z32);
       S.dot(r32, z32, scal + 2);
       k_update_p<float><<<gv, T, 0, s>>>(p32, z32, scal, n);
       k_shift_rz<<<1, 1, 0, s>>>(scal);
@@ -401,17 +522,38 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
   if (st) return st;
   if (!d_H || !d_b || !d_uhat || !opts || !info || !mesh->d_row_ptr || !mesh->d_col_idx)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: NULL argument");
-  if (!(opts->rtol > 0) || opts->max_iter < 0 || (opts->precision != 0 && opts->precision != 1))
+  if (!(opts->rtol > 0) || opts->max_iter < 0 || (opts->precision != 0 && opts->precision != 1) ||
+      (opts->precond != 0 && opts->precond != 1))
     return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: bad options");
+  if (opts->precond == 1 && (!opts->d_pre_N || !opts->d_pre_Linv || !opts->d_pre_mirror))
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: the learned preconditioner needs N, Linv and mirror");
   if (!d_ws || ws_bytes < ws_size(mesh, disc->host.d2, opts->precision))
     return set_error(HDG_ERR_WORKSPACE, "hdg_solve: workspace too small");
   hipStream_t s = (hipStream_t)stream;
-  switch (disc->host.k) {
-    case 0: return run_solve<dim2(0)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
-    case 1: return run_solve<dim2(1)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
-    case 2: return run_solve<dim2(2)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
-    case 3: return run_solve<dim2(3)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
-    case 4: return run_solve<dim2(4)>(mesh, d_H, d_b, d_uhat, opts, info, d_ws, ws_bytes, s);
+  auto run = [&](const hdg_solve_opts* o, hdg_solve_info* inf) -> hdg_status {
+    switch (disc->host.k) {
+      case 0: return run_solve<dim2(0)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+      case 1: return run_solve<dim2(1)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+      case 2: return run_solve<dim2(2)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+      case 3: return run_solve<dim2(3)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+      case 4: return run_solve<dim2(4)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+    }
+    return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve: unsupported degree");
+  };
+  info->fell_back = 0;
+  hdg_status st2 = run(opts, info);
+  if (st2 != HDG_ERR_NOT_CONVERGED || opts->precond == 0) return st2;
+  // fallback: block-Jacobi from the current iterate (or from zero after a breakdown)
+  const int used = info->iterations;
+  hdg_solve_opts bj = *opts;
+  bj.precond = 0;
+  if (!std::isfinite(info->rel_residual) || info->rel_residual > 1.0) {
+    const size_t n = (size_t)mesh->nfc * disc->host.d2;
+    k_fill<double><<<(unsigned)std::min<size_t>((n + 255) / 256, 8192), 256, 0, s>>>(d_uhat, n, 0.0);
+    HDG_CHECK_LAUNCH("hdg_solve: fallback reset");
   }
-  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve: unsupported degree");
+  st2 = run(&bj, info);
+  info->fell_back = 1;
+  info->iterations += used;
+  return st2;
 }
