@@ -290,6 +290,30 @@ hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const dou
                            const double* d_q, const double* d_u, double* d_ustar, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * Condensation with FP32 local factorisations and FP64 iterative refinement (degrees
+ * 1..3; eq 5.1-5.6, scatter of eq 6.5).
+ *
+ * X = A1^{-1} [A2 | Af] (eq 5.2-5.4) is computed by refinement X += P(B - A1 X).  The
+ * residual uses A1's block structure and runs in FP64; P is the block elimination of A1
+ * (M, and the Schur complement S = Mc + tauPP + sum_s C_s M^{-1} C_s^T) with FP32
+ * Cholesky factors, applied on the FP32 matrix cores.  Sweeps stop once the correction
+ * is at most 1e-15 of X, or at max_sweeps (1..20).  Then C^K = A3 X_2 + tauDD and
+ * Cf^K = A3 X_f (FP64) are scattered into H and F exactly as by hdg_assemble_condense.
+ *   d_X       double [nelt][4 d3][4 d2 + 1]  X, kept for hdg_recover_ir (may be NULL);
+ *             hdg_ir_store_len gives 4 d3 (4 d2 + 1)
+ *   d_sweeps  int32 [nelt]  sweeps used per element (may be NULL)
+ * Errors: HDG_ERR_UNSUPPORTED_DEGREE (k = 0 or 4), HDG_ERR_INVALID_ARG.
+ * ------------------------------------------------------------------------------ */
+hdg_status hdg_ir_store_len(const hdg_disc* disc, int64_t* n);
+hdg_status hdg_assemble_condense_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                    const double* d_c, const double* d_f, const double* d_tau, double* d_H,
+                                    double* d_F, double* d_X, int max_sweeps, int32_t* d_sweeps, void* stream);
+/* Reconstruction from the stored X: [q; u] = X_f - X_2 uhat_K (Section 6).  Outputs as in
+ * hdg_recover; the postprocess is hdg_postprocess. */
+hdg_status hdg_recover_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_X, const double* d_uhat,
+                          double* d_q, double* d_u, void* stream);
+
+/* ------------------------------------------------------------------------------
  * Learned face-graph preconditioner for eq 6.5 (the paper leaves the solver open).
  *
  * With H_ii = L_i L_i^T and Hs_ij = L_i^{-1} H_ij L_j^{-T} (block-Jacobi scaling), the

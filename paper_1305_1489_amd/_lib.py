@@ -30,7 +30,8 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_batch_destroy", "hdg_batch_info", "hdg_batch_set_config", "hdg_batch_get_config",
            "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune", "hdg_set_launch_config",
            "hdg_get_launch_config", "hdg_gnn_param_count", "hdg_gnn_graph_workspace_size", "hdg_gnn_build_graph",
-           "hdg_gnn_workspace_size", "hdg_gnn_forward", "hdg_gnn_loss_grad", "hdg_gnn_adam"]
+           "hdg_gnn_workspace_size", "hdg_gnn_forward", "hdg_gnn_loss_grad", "hdg_gnn_adam", "hdg_ir_store_len",
+           "hdg_assemble_condense_ir", "hdg_recover_ir"]
 
 
 class HdgError(RuntimeError):
@@ -519,4 +520,28 @@ def hdg_gnn_loss_grad(shape, params, mesh: Mesh, graph: GnnGraph, probes, N=None
 def hdg_gnn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(lib().hdg_gnn_adam(C.c_int64(params.numel()), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), C.c_int(step),
                               C.c_float(lr), C.c_float(beta1), C.c_float(beta2), C.c_float(eps), _stream(stream)))
+
+
+# ----------------------------------------------------------------------------- FP32 factors + FP64 refinement
+def hdg_ir_store_len(disc: Disc) -> int:
+    n = C.c_int64()
+    _check(lib().hdg_ir_store_len(disc.handle, C.byref(n)))
+    return n.value
+
+
+def hdg_assemble_condense_ir(disc: Disc, mesh: Mesh, kappa, c, f, tau, H, F, X=None, max_sweeps=6, sweeps=None,
+                             stream=None):
+    _check(lib().hdg_assemble_condense_ir(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(tau),
+                                          _ptr(H), _ptr(F), _ptr(X), C.c_int(max_sweeps), _ptr(sweeps),
+                                          _stream(stream)))
+
+
+def hdg_recover_ir(disc: Disc, mesh: Mesh, X, uhat, q=None, u=None, stream=None):
+    if q is None:
+        q = torch.empty((mesh.nelt, 3, disc.d3), dtype=torch.float64, device=mesh.device)
+    if u is None:
+        u = torch.empty((mesh.nelt, disc.d3), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_recover_ir(disc.handle, C.byref(mesh.struct), _ptr(X), _ptr(uhat), _ptr(q), _ptr(u),
+                                _stream(stream)))
+    return q, u
 
