@@ -124,6 +124,38 @@ def traffic_record(kernel, kernel_src_sha):
     return rec.get("bytes_per_launch")
 
 
+def precision_metric(S, stream, fp64_ms, reps=5):
+    """The FP32-factor + FP64-refinement condensation on the same workload: its launch time
+    next to the FP64 kernel's, and H, F against the FP64 path (the per-field errors against
+    the oracle are the GPU test of the precision table)."""
+    import torch
+    from paper_1305_1489_amd import _lib as L
+    H64, F64 = S.H.clone(), S.F.clone()
+    L.hdg_assemble_condense(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, H64, F64, S.factors)
+    Hir, Fir = torch.empty_like(S.H), torch.empty_like(S.F)
+    X = torch.empty((S.mesh.nelt, L.hdg_ir_store_len(S.disc)), dtype=torch.float64, device="cuda")
+    sweeps = torch.zeros(S.mesh.nelt, dtype=torch.int32, device="cuda")
+    run = lambda: L.hdg_assemble_condense_ir(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, Hir, Fir, X, 8, sweeps)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    eh = float(((Hir - H64).abs().max() / H64.abs().max()).item())
+    ef = float(((Fir - F64).abs().max() / F64.abs().max()).item())
+    sw = sweeps.float()
+    log(f"fp32 factors + fp64 refinement: {ms:.3f} ms (fp64 {fp64_ms:.3f} ms), sweeps {sw.mean().item():.2f}")
+    return {"form": "FP32 local factors on the FP32 matrix cores, FP64 iterative refinement of the local solve",
+            "kernel": "k_condense_ir", "ms": ms, "fp64_ms": fp64_ms, "elements_per_s": S.mesh.nelt / (ms * 1e-3),
+            "sweeps_mean": sw.mean().item(), "sweeps_max": int(sw.max().item()),
+            "rel_err_vs_fp64": {"H": eh, "F": ef},
+            "oracle_table": "profiles/precision_table_jitter_k3.json"}
+
+
 def batch_metric(args):
     """The batch workload: 256 independent cubes (n ~ U{4..12}, k ~ U{1..4}) condensed by one
     graph launch of the batched persistent kernels, with autotuned shapes per degree; compared
@@ -244,6 +276,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--gnn", default=None, help="checkpoint of the learned preconditioner (default: the packaged one)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32-refined condensation timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-condensation workload")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
@@ -341,6 +374,8 @@ def main():
     dom = max(kernels, key=lambda n: kernels[n]["avg_launch_ms"])
     roofline = dict(kernels[dom])
     roofline["other_kernels"] = {n: v for n, v in kernels.items() if n != dom}
+    if not args.no_precision:
+        result_precision = precision_metric(S, stream, cond_ms)
     if args.calibrate_copy:
         x = torch.empty(args.calibrate_copy // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
@@ -369,6 +404,8 @@ def main():
                                 "postprocess": pp_ms}},
         "roofline": roofline,
     }
+    if not args.no_precision:
+        result["precision"] = result_precision
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(cfg)

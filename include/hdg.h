@@ -308,6 +308,11 @@ hdg_status hdg_ir_store_len(const hdg_disc* disc, int64_t* n);
 hdg_status hdg_assemble_condense_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                     const double* d_c, const double* d_f, const double* d_tau, double* d_H,
                                     double* d_F, double* d_X, int max_sweeps, int32_t* d_sweeps, void* stream);
+/* Per-element C^K [n][m][m], Cf^K [n][m] and (optional) X [n][4 d3][m + 1] of the listed
+ * elements from the same refined local solve, instead of the scatter (for tests). */
+hdg_status hdg_export_local_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_c,
+                               const double* d_f, const double* d_tau, const int32_t* d_elems, int64_t n, double* d_C,
+                               double* d_Cf, double* d_X, int max_sweeps, void* stream);
 /* Reconstruction from the stored X: [q; u] = X_f - X_2 uhat_K (Section 6).  Outputs as in
  * hdg_recover; the postprocess is hdg_postprocess. */
 hdg_status hdg_recover_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_X, const double* d_uhat,

@@ -31,7 +31,7 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune", "hdg_set_launch_config",
            "hdg_get_launch_config", "hdg_gnn_param_count", "hdg_gnn_graph_workspace_size", "hdg_gnn_build_graph",
            "hdg_gnn_workspace_size", "hdg_gnn_forward", "hdg_gnn_loss_grad", "hdg_gnn_adam", "hdg_ir_store_len",
-           "hdg_assemble_condense_ir", "hdg_recover_ir"]
+           "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir"]
 
 
 class HdgError(RuntimeError):
@@ -544,4 +544,17 @@ def hdg_recover_ir(disc: Disc, mesh: Mesh, X, uhat, q=None, u=None, stream=None)
     _check(lib().hdg_recover_ir(disc.handle, C.byref(mesh.struct), _ptr(X), _ptr(uhat), _ptr(q), _ptr(u),
                                 _stream(stream)))
     return q, u
+
+
+def hdg_export_local_ir(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, max_sweeps=6, want_x=False, stream=None):
+    elems = _dev(elems, torch.int32, mesh.device)
+    n = elems.numel()
+    m = disc.m
+    Cm = torch.empty((n, m, m), dtype=torch.float64, device=mesh.device)
+    Cf = torch.empty((n, m), dtype=torch.float64, device=mesh.device)
+    X = torch.empty((n, hdg_ir_store_len(disc)), dtype=torch.float64, device=mesh.device) if want_x else None
+    _check(lib().hdg_export_local_ir(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(tau),
+                                     _ptr(elems), C.c_int64(n), _ptr(Cm), _ptr(Cf), _ptr(X), C.c_int(max_sweeps),
+                                     _stream(stream)))
+    return Cm, Cf, X
 

@@ -117,13 +117,17 @@ __global__ void __launch_bounds__(kIrThreads) k_condense_ir(hdg_mesh mesh, Table
                                                             const double* __restrict__ fco,
                                                             const double* __restrict__ tau, double* __restrict__ H,
                                                             double* __restrict__ F, double* __restrict__ Xout,
-                                                            int max_sweeps, int* __restrict__ sweeps_out) {
+                                                            int max_sweeps, int* __restrict__ sweeps_out,
+                                                            const int* __restrict__ elems, int nwork,
+                                                            double* __restrict__ Cout, double* __restrict__ Cfout) {
   using D = ID<K>;
   constexpr int D3 = D::D3, D2 = D::D2, M = D::M, NR = D::NR, NQD = D::NQD, PD = D::PD, PR = D::PR, N4 = D::N4;
   __shared__ IrSmem<K> sm;
   __shared__ ElemGeom sg;
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int E = blockIdx.x; E < mesh.nelt; E += gridDim.x) {
+  for (int w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int E = elems ? elems[w] : w;
+    if (E < 0 || E >= mesh.nelt) continue;  // uniform across the workgroup
     __syncthreads();
     if (t == 0) load_geometry(E, mesh, tau, sg);
     // zero the padded FP32 buffers (their padding must stay zero / identity)
@@ -259,7 +263,7 @@ __global__ void __launch_bounds__(kIrThreads) k_condense_ir(hdg_mesh mesh, Table
         break;
       }
     }
-    if (sweeps_out && t == 0) sweeps_out[E] = sweep;
+    if (sweeps_out && t == 0) sweeps_out[w] = sweep;
     // ---- C^K = A3 X_2 + tauDD (upper triangle, mirrored), Cf^K = A3 X_f; scatter
     for (int idx = t; idx < M * NR; idx += nt) {
       const int a = idx / NR, b = idx % NR;
@@ -273,10 +277,18 @@ __global__ void __launch_bounds__(kIrThreads) k_condense_ir(hdg_mesh mesh, Table
                    g.n[la][2] * sm.X[(2 * D3 + j) * NR + b] + g.T[la] * sm.X[(3 * D3 + j) * NR + b]);
       }
       if (b == M) {
-        unsafeAtomicAdd(&F[(size_t)mesh.d_facebyele[4 * E + la] * D2 + ia], v);
+        if (Cfout)
+          Cfout[(size_t)w * M + a] = v;
+        else
+          unsafeAtomicAdd(&F[(size_t)mesh.d_facebyele[4 * E + la] * D2 + ia], v);
         continue;
       }
       if (a == b) v += g.T[la];
+      if (Cout) {
+        Cout[((size_t)w * M + a) * M + b] = v;
+        Cout[((size_t)w * M + b) * M + a] = v;
+        continue;
+      }
       const int lb = b / D2, ib = b % D2;
       const size_t s1 = mesh.d_slot[16 * E + 4 * la + lb];
       if (la == lb) {
@@ -289,7 +301,7 @@ __global__ void __launch_bounds__(kIrThreads) k_condense_ir(hdg_mesh mesh, Table
       }
     }
     if (Xout)
-      for (int idx = t; idx < N4 * NR; idx += nt) Xout[(size_t)E * N4 * NR + idx] = sm.X[idx];
+      for (int idx = t; idx < N4 * NR; idx += nt) Xout[(size_t)w * N4 * NR + idx] = sm.X[idx];
   }
 }
 
@@ -327,12 +339,17 @@ __global__ void k_recover_x(hdg_mesh mesh, const double* __restrict__ X, const d
 
 template <int K>
 hdg_status run_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c, const double* f,
-                  const double* tau, double* H, double* F, double* X, int max_sweeps, int* sweeps, hipStream_t s) {
+                  const double* tau, double* H, double* F, double* X, int max_sweeps, int* sweeps, const int* elems,
+                  int64_t n, double* Cout, double* Cfout, hipStream_t s) {
   using D = ID<K>;
-  const size_t tot = (size_t)mesh->nfc * D::D2 * D::D2;
-  k_zero_diag_ir<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, (int)mesh->nfc, H, F);
-  const int grid = (int)std::min<int64_t>(mesh->nelt, 4 * device_cu_count());
-  k_condense_ir<K><<<grid, kIrThreads, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, X, max_sweeps, sweeps);
+  if (!Cout) {
+    const size_t tot = (size_t)mesh->nfc * D::D2 * D::D2;
+    k_zero_diag_ir<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, (int)mesh->nfc, H, F);
+  }
+  if (n == 0) return HDG_OK;
+  const int grid = (int)std::min<int64_t>(n, 4 * device_cu_count());
+  k_condense_ir<K><<<grid, kIrThreads, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, X, max_sweeps, sweeps, elems,
+                                               (int)n, Cout, Cfout);
   HDG_CHECK_LAUNCH("k_condense_ir");
   return HDG_OK;
 }
@@ -370,12 +387,30 @@ extern "C" hdg_status hdg_assemble_condense_ir(const hdg_disc* disc, const hdg_m
   if (!d_kappa || !d_c || !d_f || !d_tau || !d_H || !d_F || max_sweeps < 1 || max_sweeps > 20)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense_ir: NULL array or max_sweeps outside 1..20");
   hipStream_t s = (hipStream_t)stream;
+  const int64_t n = mesh->nelt;
   switch (disc->host.k) {
-    case 1: return run_ir<1>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, s);
-    case 2: return run_ir<2>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, s);
-    case 3: return run_ir<3>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, s);
+    case 1: return run_ir<1>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, nullptr, n, nullptr, nullptr, s);
+    case 2: return run_ir<2>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, nullptr, n, nullptr, nullptr, s);
+    case 3: return run_ir<3>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, nullptr, n, nullptr, nullptr, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_assemble_condense_ir: degrees 1..3 only");
+}
+
+extern "C" hdg_status hdg_export_local_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                          const double* d_c, const double* d_f, const double* d_tau,
+                                          const int32_t* d_elems, int64_t n, double* d_C, double* d_Cf,
+                                          double* d_X, int max_sweeps, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_export_local_ir");
+  if (st) return st;
+  if (!d_kappa || !d_c || !d_f || !d_tau || !d_elems || !d_C || !d_Cf || n < 0 || max_sweeps < 1 || max_sweeps > 20)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_export_local_ir: NULL array, n < 0 or max_sweeps outside 1..20");
+  hipStream_t s = (hipStream_t)stream;
+  switch (disc->host.k) {
+    case 1: return run_ir<1>(disc, mesh, d_kappa, d_c, d_f, d_tau, nullptr, nullptr, d_X, max_sweeps, nullptr, d_elems, n, d_C, d_Cf, s);
+    case 2: return run_ir<2>(disc, mesh, d_kappa, d_c, d_f, d_tau, nullptr, nullptr, d_X, max_sweeps, nullptr, d_elems, n, d_C, d_Cf, s);
+    case 3: return run_ir<3>(disc, mesh, d_kappa, d_c, d_f, d_tau, nullptr, nullptr, d_X, max_sweeps, nullptr, d_elems, n, d_C, d_Cf, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_export_local_ir: degrees 1..3 only");
 }
 
 extern "C" hdg_status hdg_recover_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_X,

@@ -1,0 +1,102 @@
+"""Per-field error of the FP32-factor + FP64-refinement form at the k = 3 throughput
+workload (Kuhn 24^3, 82,944 jittered tets).
+
+Against the FP64 oracle on 256 sampled elements:
+  * the local solution X = A1^{-1} [A2 | Af] and the condensed C^K, Cf^K (eq 5.5-5.6);
+  * q, u (Section 6, "Reconstruction") and u* (eq 9.11) for one seeded synthetic trace
+    vector, shared by both sides.
+The FP64 path is listed beside it.  On the whole mesh, against the library's FP64 path:
+H, F, the solved traces uhat (both solves to the same true residual), and q, u, u*.
+The table is printed and, when gpurun_out/ exists, written there as JSON.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from _gpu_helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_precision_table_jitter_k3():
+    from hdg_inputs import config, kuhn_mesh
+    from oracle import globalsys as OG, local as OL, mesh as OM
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem
+    cfg = config("jitter_k3")
+    k = cfg["k"]
+    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
+                  neumann_sides=cfg["neumann"])
+    pb = cfg["problem"]()
+    print("precision table: set-up", flush=True)
+    S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, pb)
+    mesh, disc = S.mesh, S.disc
+    nelt, d2 = mesh.nelt, disc.d2
+    # FP64 path
+    S.assemble()
+    H64, F64 = S.H.clone(), S.F.clone()
+    S.boundary()
+    F64b = S.F.clone()
+    i64 = S.solve(rtol=1e-12, check_every=50)
+    q64, u64, us64 = S.recover()
+    # FP32 factors + FP64 refinement
+    print("precision table: refined path", flush=True)
+    Hir, Fir = torch.empty_like(S.H), torch.empty_like(S.F)
+    X = torch.empty((nelt, L.hdg_ir_store_len(disc)), dtype=torch.float64, device="cuda")
+    sweeps = torch.zeros(nelt, dtype=torch.int32, device="cuda")
+    L.hdg_assemble_condense_ir(disc, mesh, S.kappa, S.c, S.f, S.tau, Hir, Fir, X, 8, sweeps)
+    Hir0, Fir0 = Hir.clone(), Fir.clone()
+    uhir = torch.empty_like(S.uhat)
+    L.hdg_boundary(disc, mesh, S.uD, S.gN, Hir, Fir, uhir)
+    iir = L.hdg_solve(disc, mesh, Hir, Fir, uhir, rtol=1e-12, check_every=50)
+    qir, uir = L.hdg_recover_ir(disc, mesh, X, uhir)
+    usir = L.hdg_postprocess(disc, mesh, S.kappa, S.tau, qir, uir)
+    torch.cuda.synchronize()
+    c = lambda t: t.cpu().numpy()
+    whole = {"H": rel(c(Hir0), c(H64)), "F": rel(c(Fir0), c(F64)), "uhat": rel(c(uhir), c(S.uhat)),
+             "q": rel(c(qir), c(q64)), "u": rel(c(uir), c(u64)), "ustar": rel(c(usir), c(us64))}
+    sw = c(sweeps)
+    # oracle on sampled elements
+    print("precision table: oracle sample", flush=True)
+    rng = np.random.default_rng(2024)
+    el = np.sort(rng.choice(nelt, 256, replace=False))
+    ex = OM.expand(m.coordinates, m.elements, m.dirichlet, m.neumann)
+    R = OL.rules(k)
+    b = OL.local_blocks(ex, pb, R, el)
+    A1, A2, Af, _ = OL.local_solver_matrices(b)
+    Xref = np.linalg.solve(A1, np.concatenate([A2, Af[:, :, None]], axis=2))
+    Cref, Cfref = OL.condense(b)
+    Cir, Cfir, Xs = L.hdg_export_local_ir(disc, mesh, S.kappa, S.c, S.f, S.tau, el, max_sweeps=8, want_x=True)
+    C64, Cf64 = L.hdg_export_local(disc, mesh, S.kappa, S.c, S.f, S.tau, el)
+    uh = rng.standard_normal((ex.nfc, d2))
+    uhd = torch.as_tensor(uh, device="cuda").contiguous()
+    qa, ua, usa = L.hdg_recover(disc, mesh, S.kappa, S.tau, S.factors, uhd)
+    qb, ub = L.hdg_recover_ir(disc, mesh, X, uhd)
+    usb = L.hdg_postprocess(disc, mesh, S.kappa, S.tau, qb, ub)
+    torch.cuda.synchronize()
+    qo, uo = OL.recover(b, uh[ex.facebyele[el]].reshape(el.size, -1))
+    uso = OG.postprocess(ex, pb, R, qo, uo, el)
+    oracle = {
+        "fp32_refined": {"X": rel(c(Xs).reshape(Xref.shape), Xref), "C": rel(c(Cir), Cref), "Cf": rel(c(Cfir), Cfref),
+                         "q": rel(c(qb)[el], qo), "u": rel(c(ub)[el], uo), "ustar": rel(c(usb)[el], uso)},
+        "fp64": {"C": rel(c(C64), Cref), "Cf": rel(c(Cf64), Cfref), "q": rel(c(qa)[el], qo), "u": rel(c(ua)[el], uo),
+                 "ustar": rel(c(usa)[el], uso)},
+    }
+    table = {"workload": "jitter_k3: Kuhn 24^3, 82944 tets, k=3", "metric": "max |x - x_ref| / max |x_ref| per field",
+             "vs_oracle_256_sampled_elements": oracle, "fp32_refined_vs_fp64_whole_mesh": whole,
+             "sweeps": {"min": int(sw.min()), "max": int(sw.max()), "mean": float(sw.mean())},
+             "solve_iterations": {"fp64": i64["iterations"], "fp32_refined": iir["iterations"]}}
+    print(json.dumps(table, indent=1), flush=True)
+    out = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(out):
+        json.dump(table, open(os.path.join(out, "precision_table.json"), "w"), indent=1)
+    for form in oracle.values():
+        for v in form.values():
+            assert v < 1e-12
+    for v in whole.values():
+        assert v < 1e-9  # whole-mesh fields after two independent global solves to 1e-12
