@@ -11,14 +11,20 @@
 // gradient rows of mode 0 vanish: S* is set to the identity on mode 0 (and on the padding
 // modes), rhs_0 = u_0, and one SPD solve gives every coefficient.
 //
-// Layouts.  The right-hand side is a contraction over the 3 x nqd (direction, point)
-// pairs with a single right-hand side per element; putting one element per matrix-core
-// block would leave three of the four columns of every product idle.  It is computed
-// split-K instead: the tile columns are the four elements of the group and the four
-// blocks take interleaved chunks of the quadrature points; a cross-block sum finishes it.
-// The stiffness matrix, its blocked Cholesky and the two triangular solves use the
-// element-per-block layout of the condensation kernels (vectors as tiles whose four
-// columns are equal).
+// Two kernels, each keeping the tables it streams resident in LDS and shared by the
+// wavefronts of a workgroup (each wavefront runs its own persistent loop over groups of
+// four elements):
+//   k_pp_rhs    the right-hand side, into the u* array (gradient tables: 131 KB at k = 3).
+//               The contraction over the 3 x nqd (direction, point) pairs has a single
+//               right-hand side per element; one element per matrix-core block would leave
+//               three of the four columns of every product idle.  It runs split-K instead:
+//               the tile columns are the four elements of the group, the four blocks take
+//               interleaved chunks of the quadrature points, and a cross-block sum
+//               finishes it.
+//   k_pp_solve  S* from the six stiffness tables (LDS), blocked Cholesky, the two
+//               triangular solves, in the element-per-block layout of the condensation
+//               kernels (vectors as tiles whose four columns are equal).
+// Geometry is computed by lanes 0..3 (one element each) and shared by lane permutes.
 #include "tile.h"
 
 namespace hdg {
@@ -36,122 +42,156 @@ struct PD {
   static constexpr int JT = D3P4 / 4;        // tiles of the degree-k modes
   static constexpr int TS = (D3P + 3) / 4;   // tiles of the degree-(k+1) modes
   static constexpr int NUS = TS * (TS + 1) / 2;
+  static constexpr int D3PP4 = 4 * TS;
+  static constexpr int P1_LEN = 3 * NQP * D3PP4, PT_LEN = NQP * D3P4, SH_LEN = 6 * NUS * 16;
+  // the gradient tables stay in global memory when they do not fit next to each other in LDS
+  static constexpr bool RHS_LDS = (P1_LEN + PT_LEN) * 8 <= 144 * 1024;
 };
 
-enum { PG_A = 0, PG_DET = 9, PG_VOL = 10, PG_LEN = 11 };
+constexpr int kRhsWaves = 8, kSolveWaves = 4;
 
-__device__ __forceinline__ double lane_read(double v, int src) {
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
-  return __hiloint2double(hi, lo);
+// Geometry of element E (lanes 0..3; E < 0: the reference element, data zero).
+struct PGeo {
+  double a[9], det, vol;
+};
+
+__device__ __forceinline__ PGeo pp_geometry(int E, const hdg_mesh& mesh, const double* tau) {
+  PGeo p{};
+  if (E >= 0) {
+    ElemGeom g;
+    load_geometry(E, mesh, tau, g);
+    for (int i = 0; i < 9; ++i) p.a[i] = g.a[i / 3][i % 3];
+    p.det = g.det;
+    p.vol = g.vol;
+  } else {
+    p.a[0] = p.a[4] = p.a[8] = 1.0;
+    p.det = 1.0;
+    p.vol = 1.0 / 6.0;
+  }
+  return p;
 }
 
 template <int K>
-__global__ void __launch_bounds__(64) k_postprocess(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
-                                                    const double* __restrict__ tau, const double* __restrict__ qin,
-                                                    const double* __restrict__ uin, double* __restrict__ usout) {
+__global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+                                                           const double* __restrict__ tau,
+                                                           const double* __restrict__ qin,
+                                                           const double* __restrict__ uin,
+                                                           double* __restrict__ rhs_out) {
   using D = PD<K>;
   constexpr int D3 = D::D3, D3P = D::D3P, NQD = D::NQD, NQP = D::NQP, QT = D::QT, QI = D::QI;
-  constexpr int D3P4 = D::D3P4, JT = D::JT, TS = D::TS, NUS = D::NUS, D3PP4 = 4 * TS;
-  __shared__ double s_geo[4][PG_LEN];
-  __shared__ int s_E[4];
-  __shared__ double s_x[64];
+  constexpr int D3P4 = D::D3P4, JT = D::JT, TS = D::TS, D3PP4 = D::D3PP4;
+  __shared__ double s_p1t[D::RHS_LDS ? D::P1_LEN : 1];
+  __shared__ double s_ptt[D::RHS_LDS ? D::PT_LEN : 1];
+  if constexpr (D::RHS_LDS) {
+    for (int i = threadIdx.x; i < D::P1_LEN; i += blockDim.x) s_p1t[i] = tb.P1gt[i];
+    for (int i = threadIdx.x; i < D::PT_LEN; i += blockDim.x) s_ptt[i] = tb.Pt[i];
+    __syncthreads();
+  }
+  const double* s_p1 = D::RHS_LDS ? s_p1t : tb.P1gt;
+  const double* s_pt = D::RHS_LDS ? s_ptt : tb.Pt;
   const int ngroups = (mesh.nelt + 3) / 4;
-  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    // per-group opaque lane index: keeps the table addresses derived from it inside the
-    // loop (hoisted, they would outlive the register file)
-    int lane = threadIdx.x;
+  const int wave = threadIdx.x >> 6;
+  for (int grp = blockIdx.x * kRhsWaves + wave; grp < ngroups; grp += gridDim.x * kRhsWaves) {
+    int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
     const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
-    __syncthreads();
-    if (lane < 4) {
-      const int E = 4 * grp + lane < mesh.nelt ? 4 * grp + lane : -1;
-      s_E[lane] = E;
-      ElemGeom g;
-      if (E >= 0) {
-        load_geometry(E, mesh, tau, g);
-      } else {  // padding element: reference geometry, zero data, outputs not written
-        g = ElemGeom{};
-        g.a[0][0] = g.a[1][1] = g.a[2][2] = 1.0;
-        g.det = 1.0;
-        g.vol = 1.0 / 6.0;
-      }
-      for (int i = 0; i < 9; ++i) s_geo[lane][PG_A + i] = g.a[i / 3][i % 3];
-      s_geo[lane][PG_DET] = g.det;
-      s_geo[lane][PG_VOL] = g.vol;
-    }
-    __syncthreads();
+    const int Em = 4 * grp + (lane & 3);
+    const int Eown = Em < mesh.nelt ? Em : -1;
+    PGeo gl{};
+    if (lane < 4) gl = pp_geometry(Eown, mesh, tau);
+    // element c's geometry (lane c computed it)
+    double a[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) a[i] = lane_read(gl.a[i], c);
+    const double wscale = lane_read(gl.vol, c) / lane_read(gl.det, c);
+    const int Ec = 4 * grp + c < mesh.nelt ? 4 * grp + c : -1;
 
     // ---- V = Q a, elements in the tile columns: lane (r, c) of tile J holds V_c[4J + r][h]
     double V[3][JT];
-    {
-      const int E = s_E[c];
-      const double* a = s_geo[c] + PG_A;
 #pragma unroll
-      for (int J = 0; J < JT; ++J) {
-        const int j = 4 * J + r;
-        double qs[3] = {0.0, 0.0, 0.0};
-        if (E >= 0 && j < D3) {
+    for (int J = 0; J < JT; ++J) {
+      const int j = 4 * J + r;
+      double qs[3] = {0.0, 0.0, 0.0};
+      if (Ec >= 0 && j < D3) {
 #pragma unroll
-          for (int s = 0; s < 3; ++s) qs[s] = qin[((size_t)E * 3 + s) * D3 + j];
-        }
-#pragma unroll
-        for (int h = 0; h < 3; ++h) V[h][J] = qs[0] * a[h] + qs[1] * a[3 + h] + qs[2] * a[6 + h];
+        for (int s = 0; s < 3; ++s) qs[s] = qin[((size_t)Ec * 3 + s) * D3 + j];
       }
+#pragma unroll
+      for (int h = 0; h < 3; ++h) V[h][J] = qs[0] * a[h] + qs[1] * a[3 + h] + qs[2] * a[6 + h];
     }
-
-    // ---- rhs, split-K over the points: block blk takes point tiles blk, blk + 4, ...
+    // ---- split-K over the points: block blk takes point tiles blk, blk + 4, ...
     double R[TS];
 #pragma unroll
     for (int I = 0; I < TS; ++I) R[I] = 0.0;
-    {
-      const int E = s_E[c];
-      const double wscale = s_geo[c][PG_VOL] / s_geo[c][PG_DET];
-#pragma unroll 1
-      for (int qi = 0; qi < QI; ++qi) {
-        const int Qt = 4 * qi + blk;
-        const int Ql = Qt < QT ? Qt : QT - 1;  // tiles past the end load in bounds, weigh zero
-        // Y_h tile: rows = points 4Qt + r, columns = elements
-        double xp[JT];
+#pragma unroll 2
+    for (int qi = 0; qi < QI; ++qi) {
+      const int Qt = 4 * qi + blk;
+      const int Ql = Qt < QT ? Qt : QT - 1;  // tiles past the end read in bounds, weigh zero
+      double xp[JT];
 #pragma unroll
-        for (int J = 0; J < JT; ++J) xp[J] = tb.Pt[(4 * Ql + c) * D3P4 + 4 * J + r];
-        const int q = 4 * Qt + r;
-        double wr = 0.0;
-        if (Qt < QT && q < NQD && E >= 0) wr = wscale * tb.vol_w[q] / kappa[(size_t)E * NQD + q];
-        double y[3];
+      for (int J = 0; J < JT; ++J) xp[J] = s_pt[(4 * Ql + c) * D3P4 + 4 * J + r];
+      const int q = 4 * Qt + r;
+      double wr = 0.0;
+      if (Qt < QT && q < NQD && Ec >= 0) wr = wscale * tb.vol_w[q] / kappa[(size_t)Ec * NQD + q];
+      double y[3];
 #pragma unroll
-        for (int h = 0; h < 3; ++h) {
-          double acc = 0.0;
+      for (int h = 0; h < 3; ++h) {
+        double acc = 0.0;
 #pragma unroll
-          for (int J = 0; J < JT; ++J) acc = mfma4(xp[J], V[h][J], acc);
-          y[h] = wr * acc;
-        }
+        for (int J = 0; J < JT; ++J) acc = mfma4(xp[J], V[h][J], acc);
+        y[h] = wr * acc;
+      }
 #pragma unroll
-        for (int h = 0; h < 3; ++h) {
-          const double* g = tb.P1gt + ((size_t)h * NQP + 4 * Ql + r) * D3PP4 + c;
+      for (int h = 0; h < 3; ++h) {
+        const double* g = s_p1 + (h * NQP + 4 * Ql + r) * D3PP4 + c;
 #pragma unroll
-          for (int I = 0; I < TS; ++I) R[I] = mfma4(g[4 * I], y[h], R[I]);
-        }
+        for (int I = 0; I < TS; ++I) R[I] = mfma4(g[4 * I], y[h], R[I]);
       }
     }
-    // sum over the four point chunks (identical, order-independent result in every block),
-    // then to the element-per-block layout: lane (r, blk, c) takes R[r][blk]
-    double rhs[TS];
+    // sum over the four point chunks (every block gets the same value, whatever the
+    // order), then lane (r, blk, 0) stores mode 4I + r of element blk
+    const int Eb = 4 * grp + blk < mesh.nelt ? 4 * grp + blk : -1;
 #pragma unroll
     for (int I = 0; I < TS; ++I) {
       double v = R[I];
       v += lane_read(v, lane ^ 4);
       v += lane_read(v, lane ^ 8);
-      rhs[I] = -lane_read(v, (lane & 0x3c) | blk);
+      v = -lane_read(v, (lane & 0x3c) | blk);
+      const int i = 4 * I + r;
+      if (i == 0) v = Eb >= 0 ? uin[(size_t)Eb * D3] : 0.0;  // mean condition: u*_0 = u_0
+      if (Eb >= 0 && c == 0 && i < D3P) rhs_out[(size_t)Eb * D3P + i] = v;
     }
-    const int Eb = s_E[blk];
-    if (r == 0) rhs[0] = Eb >= 0 ? uin[(size_t)Eb * D3] : 0.0;  // mean condition: u*_0 = u_0
+  }
+}
 
+template <int K>
+__global__ void __launch_bounds__(64 * kSolveWaves) k_pp_solve(hdg_mesh mesh, Tables tb,
+                                                               const double* __restrict__ tau,
+                                                               double* __restrict__ us) {
+  using D = PD<K>;
+  constexpr int D3P = D::D3P, TS = D::TS, NUS = D::NUS;
+  __shared__ double s_sh[D::SH_LEN];
+  __shared__ double s_x[kSolveWaves][64];
+  for (int i = threadIdx.x; i < D::SH_LEN; i += blockDim.x) s_sh[i] = tb.Shatt[i];
+  __syncthreads();
+  const int ngroups = (mesh.nelt + 3) / 4;
+  const int wave = threadIdx.x >> 6;
+  double* xch = s_x[wave];
+  for (int grp = blockIdx.x * kSolveWaves + wave; grp < ngroups; grp += gridDim.x * kSolveWaves) {
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
+    const int Em = 4 * grp + (lane & 3);
+    PGeo gl{};
+    if (lane < 4) gl = pp_geometry(Em < mesh.nelt ? Em : -1, mesh, tau);
+    const int Eb = 4 * grp + blk < mesh.nelt ? 4 * grp + blk : -1;
     // ---- S* = sum_p cf_p Shat_p on the upper tiles, identity on mode 0 and the padding
     double S[NUS];
     {
-      const double* a = s_geo[blk] + PG_A;
-      const double idet = 1.0 / s_geo[blk][PG_DET];
+      double a[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) a[i] = lane_read(gl.a[i], blk);
+      const double idet = 1.0 / lane_read(gl.det, blk);
       double G[3][3];
 #pragma unroll
       for (int h = 0; h < 3; ++h)
@@ -159,23 +199,30 @@ __global__ void __launch_bounds__(64) k_postprocess(hdg_mesh mesh, Tables tb, co
         for (int k = 0; k < 3; ++k) G[h][k] = (a[h] * a[k] + a[3 + h] * a[3 + k] + a[6 + h] * a[6 + k]) * idet;
       const double cf[6] = {G[0][0], G[1][1], G[2][2], G[0][1], G[0][2], G[1][2]};
 #pragma unroll
-      for (int I = 0; I < TS; ++I)
+      for (int I = 0; I < TS; ++I) {
 #pragma unroll
         for (int N = I; N < TS; ++N) {
           const int u = utile(I, N, TS);
           double s = 0.0;
 #pragma unroll
-          for (int p = 0; p < 6; ++p) s += cf[p] * tb.Shatt[(p * NUS + u) * 16 + 4 * r + c];
+          for (int p = 0; p < 6; ++p) s += cf[p] * s_sh[(p * NUS + u) * 16 + 4 * r + c];
           const int i = 4 * I + r, j = 4 * N + c;
           if (i == 0 || j == 0 || i >= D3P || j >= D3P) s = (i == j) ? 1.0 : 0.0;
           S[u] = s;
         }
+        __builtin_amdgcn_sched_barrier(0);  // one tile row of table reads in flight at a time
+      }
     }
-    __builtin_amdgcn_sched_barrier(0);
-
     // ---- S* = U^T U, then U^T y = rhs, U x = y
     double Vd[TS];
-    tile_cholesky<TS>(S, Vd, s_x);
+    tile_cholesky<TS, true>(S, Vd, xch);
+    // right-hand side (written by k_pp_rhs into the u* array), column-replicated tiles
+    double rhs[TS];
+#pragma unroll
+    for (int I = 0; I < TS; ++I) {
+      const int i = 4 * I + r;
+      rhs[I] = (Eb >= 0 && i < D3P) ? us[(size_t)Eb * D3P + i] : 0.0;
+    }
     double x[TS];
 #pragma unroll
     for (int I = 0; I < TS; ++I) {
@@ -195,31 +242,41 @@ __global__ void __launch_bounds__(64) k_postprocess(hdg_mesh mesh, Tables tb, co
 #pragma unroll
       for (int I = 0; I < TS; ++I) {
         const int i = 4 * I + r;
-        if (i < D3P) usout[(size_t)Eb * D3P + i] = x[I];
+        if (i < D3P) us[(size_t)Eb * D3P + i] = x[I];
       }
     }
   }
 }
 
+template <int K>
+hdg_status run_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
+                           const double* q, const double* u, double* us, hipStream_t s) {
+  const int64_t groups = (mesh->nelt + 3) / 4;
+  const int ncu = device_cu_count();
+  const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kRhsWaves - 1) / kRhsWaves, ncu));
+  k_pp_rhs<K><<<g1, 64 * kRhsWaves, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us);
+  const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kSolveWaves - 1) / kSolveWaves, 2 * ncu));
+  k_pp_solve<K><<<g2, 64 * kSolveWaves, 0, s>>>(*mesh, disc->dev, tau, us);
+  HDG_CHECK_LAUNCH("k_pp_rhs / k_pp_solve");
+  return HDG_OK;
+}
+
 }  // namespace
 
 // Launches the postprocess for degree k on every element of the mesh; q and u are the
-// recovered fields (layouts of hdg_recover).
+// recovered fields (layouts of hdg_recover).  us doubles as the right-hand side between
+// the two kernels.
 hdg_status launch_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
                               const double* q, const double* u, double* us, hipStream_t s) {
-  const int64_t groups = (mesh->nelt + 3) / 4;
-  if (groups == 0) return HDG_OK;
-  const int grid = (int)std::min<int64_t>(groups, 1 << 20);
+  if (mesh->nelt == 0) return HDG_OK;
   switch (disc->host.k) {
-    case 0: k_postprocess<0><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us); break;
-    case 1: k_postprocess<1><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us); break;
-    case 2: k_postprocess<2><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us); break;
-    case 3: k_postprocess<3><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us); break;
-    case 4: k_postprocess<4><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us); break;
-    default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover: unsupported degree");
+    case 0: return run_postprocess<0>(disc, mesh, kappa, tau, q, u, us, s);
+    case 1: return run_postprocess<1>(disc, mesh, kappa, tau, q, u, us, s);
+    case 2: return run_postprocess<2>(disc, mesh, kappa, tau, q, u, us, s);
+    case 3: return run_postprocess<3>(disc, mesh, kappa, tau, q, u, us, s);
+    case 4: return run_postprocess<4>(disc, mesh, kappa, tau, q, u, us, s);
   }
-  HDG_CHECK_LAUNCH("k_postprocess");
-  return HDG_OK;
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover: unsupported degree");
 }
 
 hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const char* who);

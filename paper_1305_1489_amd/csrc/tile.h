@@ -24,14 +24,24 @@ __device__ __forceinline__ double mfma4(double x, double y, double acc) {
 // Index of tile (I, N), I <= N, in the packed upper triangle of a T x T tile matrix.
 __host__ __device__ constexpr int utile(int I, int N, int T) { return I * T - I * (I - 1) / 2 + (N - I); }
 
+// Ordering of LDS traffic inside one wavefront (the wavefront runs in lockstep; the fences
+// keep the compiler from moving LDS accesses across this point).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Upper Cholesky of one 4x4 SPD tile per block (A = U^T U) and the inverse V = U^{-1}.
 // Every lane of the block reads the whole tile through LDS and factors it redundantly;
-// it returns its own entries U[r][c] and V[r][c].  xch: 64 doubles of LDS.
+// it returns its own entries U[r][c] and V[r][c].  xch: 64 doubles of LDS, private to the
+// wavefront when WAVE (then only the wavefront is synchronised), else to the workgroup.
+template <bool WAVE = false>
 __device__ __forceinline__ void diag_chol4(double a_rc, double* xch, double& u_rc, double& v_rc) {
   const int lane = threadIdx.x & 63, r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
-  __syncthreads();
+  if (WAVE) wave_lds_sync(); else __syncthreads();
   xch[blk * 16 + r * 4 + c] = a_rc;
-  __syncthreads();
+  if (WAVE) wave_lds_sync(); else __syncthreads();
   double a[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -77,14 +87,17 @@ __device__ __forceinline__ void diag_chol4(double a_rc, double* xch, double& u_r
   v_rc = vr;
 }
 
-// Transpose of each block's 4x4 tile: the lane (r, c) receives X[c][r] (cross-lane
-// permute, no LDS storage).
-__device__ __forceinline__ double tile_transpose(double v) {
-  const int lane = threadIdx.x & 63;
-  const int src = 16 * (lane & 3) + (lane & 12) + (lane >> 4);
+// The value v of lane src (cross-lane permute, no LDS storage).
+__device__ __forceinline__ double lane_read(double v, int src) {
   const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
   const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
   return __hiloint2double(hi, lo);
+}
+
+// Transpose of each block's 4x4 tile: the lane (r, c) receives X[c][r].
+__device__ __forceinline__ double tile_transpose(double v) {
+  const int lane = threadIdx.x & 63;
+  return lane_read(v, 16 * (lane & 3) + (lane & 12) + (lane >> 4));
 }
 
 // Inverse of the upper Cholesky factor: given U (packed upper tiles) and Vd[J] =
@@ -113,12 +126,12 @@ __device__ __forceinline__ void tile_upper_inverse(const double (&U)[T * (T + 1)
 
 // Blocked upper Cholesky in place on the packed upper tiles A (T x T tiles, symmetric
 // matrix): afterwards A holds U (A = U^T U) and Vd[J] = U(J,J)^{-1}.
-template <int T>
+template <int T, bool WAVE = false>
 __device__ __forceinline__ void tile_cholesky(double (&A)[T * (T + 1) / 2], double (&Vd)[T], double* xch) {
 #pragma unroll
   for (int J = 0; J < T; ++J) {
     double u, v;
-    diag_chol4(A[utile(J, J, T)], xch, u, v);
+    diag_chol4<WAVE>(A[utile(J, J, T)], xch, u, v);
     A[utile(J, J, T)] = u;
     Vd[J] = v;
     // panel: U(J,I) = U(J,J)^{-T} A(J,I)
