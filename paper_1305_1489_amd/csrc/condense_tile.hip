@@ -118,6 +118,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     for (int i = 0; i < NU; ++i) Ma[i] = Sa[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < T; ++i) fa[i] = 0.0;
+#pragma unroll 4  // next point tiles' table reads overlap the current products
     for (int kq = 0; kq < QT; ++kq) {
       const int q = 4 * kq + r;
       double pv[T];
@@ -182,13 +183,20 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // ---- W_s = L^{-1} C_s^T streamed by tile rows: S += W_s^T W_s, B += n_{ls} W_s^T Z_l
+    // ---- W_s = L^{-1} C_s^T streamed by tile rows: S += W_s^T W_s, B += n_{ls} W_s^T Z_l.
+    // The transposed Chat tables (element-independent) are staged in LDS, in the space of
+    // the Gram weights, which are dead by now.
+    constexpr int L3 = D3P4 * D3P4;
+    static_assert(3 * L3 <= 3 * 4 * NQP, "Chat tables must fit in the weight buffer");
+    double* s_ct = &s_w[0][0][0];
+    __syncthreads();
+    for (int i = lane; i < 3 * L3; i += 64) s_ct[i] = tb.ChatT[i];
+    __syncthreads();
     double B[T][MT];
 #pragma unroll
     for (int I = 0; I < T; ++I)
 #pragma unroll
       for (int N = 0; N < MT; ++N) B[I][N] = 0.0;
-    constexpr int L3 = D3P4 * D3P4;
     for (int s = 0; s < 3; ++s) {
       const double a0 = geo[G_A + 3 * s], a1 = geo[G_A + 3 * s + 1], a2 = geo[G_A + 3 * s + 2];
       double nls[MT];
@@ -203,11 +211,10 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 #pragma unroll
           for (int J = 0; J <= Kk; ++J) {
             const int o = (4 * J + r) * D3P4 + 4 * N + c;
-            const double ct = a0 * tb.ChatT[o] + a1 * tb.ChatT[L3 + o] + a2 * tb.ChatT[2 * L3 + o];
+            const double ct = a0 * s_ct[o] + a1 * s_ct[L3 + o] + a2 * s_ct[2 * L3 + o];
             acc = mfma4(Ui[utile(J, Kk, T)], ct, acc);
           }
           Wr[N] = acc;
-          __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int I = 0; I < T; ++I)
@@ -276,7 +283,6 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       for (int Kk = 0; Kk < T; ++Kk) zi[Kk] = s_Z[Kk * MT + I][lane];
 #pragma unroll
       for (int N = I; N < MT; ++N) {
-        __builtin_amdgcn_sched_barrier(0);
         double g1 = 0.0, g2 = 0.0;
 #pragma unroll
         for (int Kk = 0; Kk < T; ++Kk) {
