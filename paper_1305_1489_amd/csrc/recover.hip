@@ -182,11 +182,214 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
   }
 }
 
+// ---- degrees 1..3: four elements per wavefront on the FP64 matrix cores, with the tile
+// factor store of the condensation (U^{-1} and Us^{-1} as packed upper 4x4 tiles, f as
+// tiles with the values in column 0).  Vectors are tiles whose four columns are equal.
+// With mfma4(A, B) = A^T B:
+//   U^T v:  (U^T v)(K) = sum_{J<=K} mfma4(U(J,K), v(J))
+//   U v:    (U v)(J)   = sum_{K>=J} mfma4(U(J,K)^T, v(K))   (tiles transposed once)
+template <int K>
+struct RD {
+  static constexpr int D3 = dim3(K), D2 = dim2(K), T = (D3 + 3) / 4, JT = (D2 + 3) / 4;
+  static constexpr int NU = T * (T + 1) / 2, D3P4 = 4 * T, D2P4 = 4 * JT;
+  static constexpr int FLEN = (2 * NU + T) * 16;
+};
+
+template <int T>
+__device__ __forceinline__ void apply_Ut(const double (&U)[T * (T + 1) / 2], const double (&v)[T], double (&y)[T]) {
+#pragma unroll
+  for (int Kt = 0; Kt < T; ++Kt) {
+    double acc = 0.0;
+#pragma unroll
+    for (int J = 0; J <= Kt; ++J) acc = mfma4(U[utile(J, Kt, T)], v[J], acc);
+    y[Kt] = acc;
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void apply_U(const double (&UT)[T * (T + 1) / 2], const double (&y)[T], double (&x)[T]) {
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    double acc = 0.0;
+#pragma unroll
+    for (int Kt = J; Kt < T; ++Kt) acc = mfma4(UT[utile(J, Kt, T)], y[Kt], acc);
+    x[J] = acc;
+  }
+}
+
+constexpr int kRecWaves = 4;
+
+template <int K>
+__global__ void __launch_bounds__(64 * kRecWaves) k_recover_tile(hdg_mesh mesh, Tables tb,
+                                                                 const double* __restrict__ tau,
+                                                                 const double* __restrict__ factors,
+                                                                 const double* __restrict__ uhat,
+                                                                 double* __restrict__ qout,
+                                                                 double* __restrict__ uout) {
+  using D = RD<K>;
+  constexpr int D3 = D::D3, D2 = D::D2, T = D::T, JT = D::JT, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
+  constexpr int L3 = D3P4 * D3P4, LDP = 24 * D3P4 * D2P4;
+  // the DP and Chat tables, shared by the workgroup's wavefronts
+  __shared__ double s_dpt[LDP], s_cht[3 * L3];
+  for (int i = threadIdx.x; i < LDP; i += blockDim.x) s_dpt[i] = tb.DPT[i];
+  for (int i = threadIdx.x; i < 3 * L3; i += blockDim.x) s_cht[i] = tb.ChatT[i];
+  __syncthreads();
+  // per-wavefront geometry (each wavefront runs its own loop, so only the wavefront syncs)
+  __shared__ double s_a_[kRecWaves][4][9], s_n_[kRecWaves][4][12], s_T_[kRecWaves][4][4];
+  __shared__ int s_mu_[kRecWaves][4][4], s_fbe_[kRecWaves][4][4], s_E_[kRecWaves][4];
+  const int wave = threadIdx.x >> 6;
+  auto& s_a = s_a_[wave];
+  auto& s_n = s_n_[wave];
+  auto& s_T = s_T_[wave];
+  auto& s_mu = s_mu_[wave];
+  auto& s_fbe = s_fbe_[wave];
+  auto& s_E = s_E_[wave];
+  const int ngroups = (mesh.nelt + 3) / 4;
+  for (int grp = blockIdx.x * kRecWaves + wave; grp < ngroups; grp += gridDim.x * kRecWaves) {
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
+    wave_lds_sync();
+    if (lane < 4) {
+      const int E = 4 * grp + lane < mesh.nelt ? 4 * grp + lane : -1;
+      s_E[lane] = E;
+      ElemGeom g{};
+      if (E >= 0) load_geometry(E, mesh, tau, g);
+      for (int i = 0; i < 9; ++i) s_a[lane][i] = g.a[i / 3][i % 3];
+      for (int i = 0; i < 12; ++i) s_n[lane][i] = g.n[i / 3][i % 3];
+      for (int l = 0; l < 4; ++l) {
+        s_T[lane][l] = g.T[l];
+        s_mu[lane][l] = E >= 0 ? g.mu[l] : 0;
+        s_fbe[lane][l] = E >= 0 ? mesh.d_facebyele[4 * E + l] : 0;
+      }
+    }
+    wave_lds_sync();
+    const int E = s_E[blk];
+    const double* fa = factors + (size_t)(E >= 0 ? E : 0) * D::FLEN;  // padding lanes read element 0
+    double Ui[NU], UiT[NU];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+      Ui[i] = fa[i * 16 + 4 * r + c];
+      UiT[i] = tile_transpose(Ui[i]);
+    }
+    // t_l = DP_l^T uhat_l, folded into r_s = sum_l n_ls t_l and rhs = f + sum_l T_l t_l
+    double rs[3][T], ru[T];
+#pragma unroll
+    for (int Kt = 0; Kt < T; ++Kt) {
+      ru[Kt] = fa[(2 * NU + Kt) * 16 + 4 * r];  // f (column 0 of its tile)
+      rs[0][Kt] = rs[1][Kt] = rs[2][Kt] = 0.0;
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int fbe = s_fbe[blk][l];
+      const double* dpt = s_dpt + (s_mu[blk][l] * 4 + l) * D3P4 * D2P4;
+      double uh[JT];
+#pragma unroll
+      for (int J = 0; J < JT; ++J) {
+        const int i = 4 * J + r;
+        uh[J] = (E >= 0 && i < D2) ? uhat[(size_t)fbe * D2 + i] : 0.0;
+      }
+      const double n0 = s_n[blk][3 * l], n1 = s_n[blk][3 * l + 1], n2 = s_n[blk][3 * l + 2], Tl = s_T[blk][l];
+#pragma unroll
+      for (int Kt = 0; Kt < T; ++Kt) {
+        double t = 0.0;
+#pragma unroll
+        for (int J = 0; J < JT; ++J) t = mfma4(dpt[(4 * Kt + c) * D2P4 + 4 * J + r], uh[J], t);
+        rs[0][Kt] += n0 * t;
+        rs[1][Kt] += n1 * t;
+        rs[2][Kt] += n2 * t;
+        ru[Kt] += Tl * t;
+      }
+    }
+    const double* a = s_a[blk];
+    // x_s = M^{-1} r_s, v_h = sum_s a_sh x_s, rhs += sum_h Chat^h v_h
+    {
+      double xs[3][T];
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        double y[T];
+        apply_Ut<T>(Ui, rs[s], y);
+        apply_U<T>(UiT, y, xs[s]);
+      }
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        double v[T];
+#pragma unroll
+        for (int J = 0; J < T; ++J) v[J] = a[h] * xs[0][J] + a[3 + h] * xs[1][J] + a[6 + h] * xs[2][J];
+#pragma unroll
+        for (int Kt = 0; Kt < T; ++Kt) {
+          double acc = ru[Kt];
+#pragma unroll
+          for (int J = 0; J < T; ++J) acc = mfma4(s_cht[h * L3 + (4 * J + r) * D3P4 + 4 * Kt + c], v[J], acc);
+          ru[Kt] = acc;
+        }
+      }
+    }
+    // u = S^{-1} rhs with the factors of S
+    double uu[T];
+    {
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {
+        Ui[i] = fa[(NU + i) * 16 + 4 * r + c];
+        UiT[i] = tile_transpose(Ui[i]);
+      }
+      double y[T];
+      apply_Ut<T>(Ui, ru, y);
+      apply_U<T>(UiT, y, uu);
+#pragma unroll
+      for (int i = 0; i < NU; ++i) {  // back to the factors of M
+        Ui[i] = fa[i * 16 + 4 * r + c];
+        UiT[i] = tile_transpose(Ui[i]);
+      }
+    }
+    // x_s = C_s^T u - r_s = sum_h a_sh Chat^{hT} u - r_s, q_s = M^{-1} x_s
+    double w[3][T];
+#pragma unroll
+    for (int h = 0; h < 3; ++h)
+#pragma unroll
+      for (int Kt = 0; Kt < T; ++Kt) {
+        double acc = 0.0;
+#pragma unroll
+        for (int J = 0; J < T; ++J) acc = mfma4(s_cht[h * L3 + (4 * Kt + c) * D3P4 + 4 * J + r], uu[J], acc);
+        w[h][Kt] = acc;
+      }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double x[T], y[T], qs[T];
+#pragma unroll
+      for (int Kt = 0; Kt < T; ++Kt) x[Kt] = a[3 * s] * w[0][Kt] + a[3 * s + 1] * w[1][Kt] + a[3 * s + 2] * w[2][Kt] - rs[s][Kt];
+      apply_Ut<T>(Ui, x, y);
+      apply_U<T>(UiT, y, qs);
+      if (E >= 0 && c == 0) {
+#pragma unroll
+        for (int Kt = 0; Kt < T; ++Kt) {
+          const int i = 4 * Kt + r;
+          if (i < D3) qout[((size_t)E * 3 + s) * D3 + i] = qs[Kt];
+        }
+      }
+    }
+    if (E >= 0 && c == 0) {
+#pragma unroll
+      for (int Kt = 0; Kt < T; ++Kt) {
+        const int i = 4 * Kt + r;
+        if (i < D3) uout[(size_t)E * D3 + i] = uu[Kt];
+      }
+    }
+  }
+}
+
 template <int K>
 hdg_status run_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
                        const double* factors, const double* uhat, double* q, double* u, double* us, hipStream_t s) {
-  const int grid = (int)std::min<int64_t>(mesh->nelt, 1 << 20);
-  k_recover<K, (K >= 1 && K <= 3)><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
+  if constexpr (K >= 1 && K <= 3) {
+    const int64_t groups = (mesh->nelt + 3) / 4;
+    const int64_t wgs = (groups + kRecWaves - 1) / kRecWaves;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, 2 * (int64_t)device_cu_count()));
+    k_recover_tile<K><<<grid, 64 * kRecWaves, 0, s>>>(*mesh, disc->dev, tau, factors, uhat, q, u);
+  } else {
+    const int grid = (int)std::min<int64_t>(mesh->nelt, 1 << 20);
+    k_recover<K, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
+  }
   HDG_CHECK_LAUNCH("k_recover");
   return us ? launch_postprocess(disc, mesh, kappa, tau, q, u, us, s) : HDG_OK;
 }
