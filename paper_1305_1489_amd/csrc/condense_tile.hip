@@ -46,7 +46,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
   using D = TD<K>;
   constexpr int T = D::T, MT = D::MT, QT = D::QT, D3 = D::D3, D2 = D::D2, M = D::M;
   constexpr int NQD = D::NQD, NQP = D::NQP, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
-  __shared__ double s_w[3][4][NQP];
+  __shared__ double s_w[3][4][NQP + 1];  // +1: the four elements' rows start in different banks
   __shared__ double s_geo[4][G_LEN];
   __shared__ int s_mu[4][4];
   __shared__ int s_slot[4][16];
@@ -187,7 +187,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     // The transposed Chat tables (element-independent) are staged in LDS, in the space of
     // the Gram weights, which are dead by now.
     constexpr int L3 = D3P4 * D3P4;
-    static_assert(3 * L3 <= 3 * 4 * NQP, "Chat tables must fit in the weight buffer");
+    static_assert(3 * L3 <= 3 * 4 * (NQP + 1), "Chat tables must fit in the weight buffer");
     double* s_ct = &s_w[0][0][0];
     __syncthreads();
     for (int i = lane; i < 3 * L3; i += 64) s_ct[i] = tb.ChatT[i];

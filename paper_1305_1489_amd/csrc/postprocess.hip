@@ -44,8 +44,12 @@ struct PD {
   static constexpr int NUS = TS * (TS + 1) / 2;
   static constexpr int D3PP4 = 4 * TS;
   static constexpr int P1_LEN = 3 * NQP * D3PP4, PT_LEN = NQP * D3P4, SH_LEN = 6 * NUS * 16;
+  // LDS copies: row strides padded by one double, so that the four blocks' point tiles
+  // (4 rows apart) start in different banks
+  static constexpr int P1_LD = D3PP4 + 1, PT_LD = D3P4 + 1;
+  static constexpr int P1_LDS_LEN = 3 * NQP * P1_LD, PT_LDS_LEN = NQP * PT_LD;
   // the gradient tables stay in global memory when they do not fit next to each other in LDS
-  static constexpr bool RHS_LDS = (P1_LEN + PT_LEN) * 8 <= 144 * 1024;
+  static constexpr bool RHS_LDS = (P1_LDS_LEN + PT_LDS_LEN) * 8 <= 144 * 1024;
 };
 
 constexpr int kRhsWaves = 8, kSolveWaves = 4;
@@ -80,15 +84,16 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
   using D = PD<K>;
   constexpr int D3 = D::D3, D3P = D::D3P, NQD = D::NQD, NQP = D::NQP, QT = D::QT, QI = D::QI;
   constexpr int D3P4 = D::D3P4, JT = D::JT, TS = D::TS, D3PP4 = D::D3PP4;
-  __shared__ double s_p1t[D::RHS_LDS ? D::P1_LEN : 1];
-  __shared__ double s_ptt[D::RHS_LDS ? D::PT_LEN : 1];
+  __shared__ double s_p1t[D::RHS_LDS ? D::P1_LDS_LEN : 1];
+  __shared__ double s_ptt[D::RHS_LDS ? D::PT_LDS_LEN : 1];
   if constexpr (D::RHS_LDS) {
-    for (int i = threadIdx.x; i < D::P1_LEN; i += blockDim.x) s_p1t[i] = tb.P1gt[i];
-    for (int i = threadIdx.x; i < D::PT_LEN; i += blockDim.x) s_ptt[i] = tb.Pt[i];
+    for (int i = threadIdx.x; i < D::P1_LEN; i += blockDim.x) s_p1t[(i / D3PP4) * D::P1_LD + i % D3PP4] = tb.P1gt[i];
+    for (int i = threadIdx.x; i < D::PT_LEN; i += blockDim.x) s_ptt[(i / D3P4) * D::PT_LD + i % D3P4] = tb.Pt[i];
     __syncthreads();
   }
   const double* s_p1 = D::RHS_LDS ? s_p1t : tb.P1gt;
   const double* s_pt = D::RHS_LDS ? s_ptt : tb.Pt;
+  constexpr int P1S = D::RHS_LDS ? D::P1_LD : D3PP4, PTS = D::RHS_LDS ? D::PT_LD : D3P4;
   const int ngroups = (mesh.nelt + 3) / 4;
   const int wave = threadIdx.x >> 6;
   for (int grp = blockIdx.x * kRhsWaves + wave; grp < ngroups; grp += gridDim.x * kRhsWaves) {
@@ -129,7 +134,7 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
       const int Ql = Qt < QT ? Qt : QT - 1;  // tiles past the end read in bounds, weigh zero
       double xp[JT];
 #pragma unroll
-      for (int J = 0; J < JT; ++J) xp[J] = s_pt[(4 * Ql + c) * D3P4 + 4 * J + r];
+      for (int J = 0; J < JT; ++J) xp[J] = s_pt[(4 * Ql + c) * PTS + 4 * J + r];
       const int q = 4 * Qt + r;
       double wr = 0.0;
       if (Qt < QT && q < NQD && Ec >= 0) wr = wscale * tb.vol_w[q] / kappa[(size_t)Ec * NQD + q];
@@ -143,7 +148,7 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
       }
 #pragma unroll
       for (int h = 0; h < 3; ++h) {
-        const double* g = s_p1 + (h * NQP + 4 * Ql + r) * D3PP4 + c;
+        const double* g = s_p1 + (h * NQP + 4 * Ql + r) * P1S + c;
 #pragma unroll
         for (int I = 0; I < TS; ++I) R[I] = mfma4(g[4 * I], y[h], R[I]);
       }
