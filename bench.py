@@ -2,7 +2,7 @@
 """Throughput of the HDG element hot path on one MI355X.
 
 A step is one pass of the element-local hot path over the whole mesh:
-  hdg_assemble_condense  (geometry, volume and face blocks, static condensation,
+  hdg_assemble_condense_ws  (geometry, volume and face blocks, static condensation,
                           scatter into the block-sparse trace matrix H and F)
   hdg_boundary           (Dirichlet data, Neumann load, Dirichlet elimination)
   hdg_recover            (reconstruction of q and u from the face traces)
@@ -313,7 +313,7 @@ def main():
     def step(ev=None):
         if ev is not None:
             ev[0].record(stream)
-        L.hdg_assemble_condense(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors)
+        L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors, ws=S.condense_ws)
         if ev is not None:
             ev[1].record(stream)
         L.hdg_boundary(S.disc, S.mesh, S.uD, S.gN, S.H, S.F, uhat_bc)
@@ -353,7 +353,8 @@ def main():
     peak = 78.6  # MI355X FP64: dense matrix and vector rate are both 78.6 TFLOP/s
     tile = 1 <= k <= 3
     kernels = {
-        "condense": {"kernel": "k_condense_tile" if tile else "k_condense", "call": "hdg_assemble_condense",
+        "condense": {"kernel": "k_condense_tile" if tile else "k_condense", "call": "hdg_assemble_condense_ws",
+                     "call_also_launches": ["k_diag_sum"] if tile else ["k_zero_diag"],
                      "source": "condense_tile.hip" if tile else "condense.hip",
                      "bound": "mfma" if tile else "alu", "achieved": round(ach_c, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(ach_c / peak, 4), "avg_launch_ms": round(cond_ms, 4),

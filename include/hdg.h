@@ -289,6 +289,17 @@ hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
 hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_tau,
                            const double* d_q, const double* d_u, double* d_ustar, void* stream);
 
+/* Same results as hdg_assemble_condense, bit for bit, without atomics.  Each element's
+ * contributions to its diagonal face blocks and to F go to the caller's workspace (one
+ * d2 x d2 block and d2 entries per (element, face)), and a second kernel sums the one or
+ * two contributions of each face in a fixed order.  Workspace: hdg_condense_workspace_size
+ * bytes (0 for degrees 0 and 4, which always use the atomic scatter).  Errors: those of
+ * hdg_assemble_condense, HDG_ERR_WORKSPACE. */
+hdg_status hdg_condense_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes);
+hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                    const double* d_c, const double* d_f, const double* d_tau, double* d_H, double* d_F,
+                                    double* d_factors, void* d_ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------------
  * Condensation with FP32 local factorisations and FP64 iterative refinement (degrees
  * 1..3; eq 5.1-5.6, scatter of eq 6.5).

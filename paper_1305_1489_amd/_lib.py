@@ -25,7 +25,7 @@ STATUS = {0: "HDG_OK", 1: "HDG_ERR_INVALID_ARG", 2: "HDG_ERR_UNSUPPORTED_DEGREE"
 
 EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expand", "hdg_disc_create",
            "hdg_disc_destroy", "hdg_disc_get_info", "hdg_disc_table", "hdg_reference_table", "hdg_qp_coords", "hdg_face_qp_coords",
-           "hdg_assemble_condense", "hdg_check_tau", "hdg_export_local", "hdg_boundary",
+           "hdg_assemble_condense", "hdg_condense_workspace_size", "hdg_assemble_condense_ws", "hdg_check_tau", "hdg_export_local", "hdg_boundary",
            "hdg_solve_workspace_size", "hdg_solve", "hdg_recover", "hdg_postprocess", "hdg_batch_create",
            "hdg_batch_destroy", "hdg_batch_info", "hdg_batch_set_config", "hdg_batch_get_config",
            "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune", "hdg_set_launch_config",
@@ -260,6 +260,24 @@ def hdg_assemble_condense(disc: Disc, mesh: Mesh, kappa, c, f, tau, H=None, F=No
         factors = torch.empty((mesh.nelt, disc.factor_len), dtype=torch.float64, device=mesh.device)
     _check(lib().hdg_assemble_condense(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(tau),
                                        _ptr(H), _ptr(F), _ptr(factors), _stream(stream)))
+    return H, F, factors
+
+
+def hdg_condense_workspace_size(disc: Disc, mesh: Mesh) -> int:
+    n = C.c_size_t(0)
+    _check(lib().hdg_condense_workspace_size(disc.handle, C.byref(mesh.struct), C.byref(n)))
+    return n.value
+
+
+def hdg_assemble_condense_ws(disc: Disc, mesh: Mesh, kappa, c, f, tau, H, F, factors, ws=None, stream=None):
+    """hdg_assemble_condense without atomics (same bits); ws: a uint8 device tensor of at least
+    hdg_condense_workspace_size bytes, allocated here when None."""
+    need = hdg_condense_workspace_size(disc, mesh)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=mesh.device)
+    _check(lib().hdg_assemble_condense_ws(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(tau),
+                                          _ptr(H), _ptr(F), _ptr(factors), _ptr(ws), C.c_size_t(ws.numel()),
+                                          _stream(stream)))
     return H, F, factors
 
 

@@ -259,15 +259,17 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
 
 hdg_status dispatch_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
                                   const double* f, const double* tau, double* H, double* F, double* factors,
-                                  const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s);
+                                  const int* elems, int64_t n, double* Cout, double* Cfout, double* dws,
+                                  hipStream_t s);
 
 namespace {
 
 hdg_status dispatch_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
                              const double* f, const double* tau, double* H, double* F, double* factors,
-                             const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s) {
+                             const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s,
+                             double* dws = nullptr) {
   if (disc->host.k >= 1 && disc->host.k <= 3)
-    return dispatch_condense_tile(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
+    return dispatch_condense_tile(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, dws, s);
   switch (disc->host.k) {
     case 0: return run_condense<0>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
     case 4: return run_condense<4>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
@@ -334,6 +336,29 @@ extern "C" hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh
     return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense: NULL array");
   return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
                            nullptr, (hipStream_t)stream);
+}
+
+extern "C" hdg_status hdg_condense_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes) {
+  if (!disc || !mesh || !bytes) return set_error(HDG_ERR_INVALID_ARG, "hdg_condense_workspace_size: NULL argument");
+  const int d2 = disc->host.d2;
+  *bytes = (disc->host.k >= 1 && disc->host.k <= 3) ? (size_t)4 * mesh->nelt * (d2 * d2 + d2) * sizeof(double) : 0;
+  return HDG_OK;
+}
+
+extern "C" hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                               const double* d_c, const double* d_f, const double* d_tau,
+                                               double* d_H, double* d_F, double* d_factors, void* d_ws,
+                                               size_t ws_bytes, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_assemble_condense_ws");
+  if (st) return st;
+  if (!d_kappa || !d_c || !d_f || !d_tau || !d_H || !d_F || !mesh->d_face_elem)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense_ws: NULL array");
+  size_t need = 0;
+  hdg_condense_workspace_size(disc, mesh, &need);
+  if (need && (!d_ws || ws_bytes < need))
+    return set_error(HDG_ERR_WORKSPACE, "hdg_assemble_condense_ws: workspace too small");
+  return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
+                           nullptr, (hipStream_t)stream, need ? (double*)d_ws : nullptr);
 }
 
 extern "C" hdg_status hdg_export_local(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,

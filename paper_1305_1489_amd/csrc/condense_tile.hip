@@ -35,14 +35,17 @@ struct TD {
 
 enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_LEN = 43 };
 
-// One group of four elements (w0 .. w0+3 of the work list) on one wavefront.
-template <int K>
+// One group of four elements (w0 .. w0+3 of the work list) on one wavefront.  With DWS the
+// diagonal face blocks and F entries of C^K, Cf^K go to the per-(element, face) buffer dws
+// ([4 nelt][d2 d2 + d2]) with plain stores, to be summed per face by k_diag_sum; without it
+// they are atomic adds onto zeros.
+template <int K, bool DWS>
 __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const Tables& tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
                                                       const double* __restrict__ tau, double* __restrict__ H,
                                                       double* __restrict__ F, double* __restrict__ factors,
                                                       const int* __restrict__ elems, int nwork,
-                                                      double* __restrict__ Cout, double* __restrict__ Cfout, int w0) {
+                                                      double* __restrict__ Cout, double* __restrict__ Cfout, int w0, double* __restrict__ dws) {
   using D = TD<K>;
   constexpr int T = D::T, MT = D::MT, QT = D::QT, D3 = D::D3, D2 = D::D2, M = D::M;
   constexpr int NQD = D::NQD, NQP = D::NQP, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
@@ -303,8 +306,14 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
           } else {
             const size_t s1 = s_slot[blk][4 * la + lb];
             if (la == lb) {
-              unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
-              if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
+              if constexpr (DWS) {
+                double* d = dws + (size_t)(4 * E + la) * (D2 * D2 + D2);
+                d[ia * D2 + ib] = val;
+                if (ia != ib) d[ib * D2 + ia] = val;
+              } else {
+                unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
+                if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
+              }
             } else {
               H[(s1 * D2 + ia) * D2 + ib] = val;
             }
@@ -325,6 +334,8 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       if (E >= 0 && c == 0) {
         if (Cfout)
           Cfout[(size_t)(w0 + blk) * M + a] = h;
+        else if constexpr (DWS)
+          dws[(size_t)(4 * E + la) * (D2 * D2 + D2) + D2 * D2 + ia] = h;
         else
           unsafeAtomicAdd(&F[(size_t)s_fbe[blk][la] * D2 + ia], h);
       }
@@ -334,17 +345,17 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 
 // EXPORT selects the debugging form (listed elements, C^K and Cf^K written out instead of
 // scattered); the scatter form is compiled with those pointers known to be null.
-template <int K, bool EXPORT>
+template <int K, bool EXPORT, bool DWS>
 __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
                                                       const double* __restrict__ tau, double* __restrict__ H,
                                                       double* __restrict__ F, double* __restrict__ factors,
                                                       const int* __restrict__ elems, int nwork,
                                                       double* __restrict__ Cout, double* __restrict__ Cfout,
-                                                      int xcd_remap) {
+                                                      int xcd_remap, double* __restrict__ dws) {
   for (int w0 = batch_block(xcd_remap) * 4; w0 < nwork; w0 += gridDim.x * 4)
-    condense_tile_group<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
-                           EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w0);
+    condense_tile_group<K, DWS>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
+                                EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w0, dws);
 }
 
 // Persistent batched form: work unit u is group u - unit_begin of its mesh.
@@ -353,8 +364,8 @@ __global__ void __launch_bounds__(64) k_batch_condense_tile(const BatchItem* __r
                                                             int total_units, Tables tb, int xcd_remap) {
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
-    condense_tile_group<K>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
-                           (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin));
+    condense_tile_group<K, false>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
+                                  (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin), nullptr);
   }
 }
 
@@ -367,12 +378,31 @@ __global__ void k_zero_diag_t(const int* __restrict__ diag, int nfc, double* __r
   if (e < D2) F[f * D2 + e] = 0.0;
 }
 
+// H_ff (diagonal block) and F_f from the per-(element, face) contributions of the (one or
+// two) elements holding face f, in a fixed order; (0 + a) + b equals the atomic result.
+template <int D2>
+__global__ void k_diag_sum(const int* __restrict__ diag, const int* __restrict__ face_elem, int nfc,
+                           const double* __restrict__ dws, double* __restrict__ H, double* __restrict__ F) {
+  constexpr int W = D2 * D2 + D2;
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i >= (size_t)nfc * W) return;
+  const size_t f = i / W;
+  const int e = (int)(i % W);
+  const int v0 = face_elem[2 * f], v1 = face_elem[2 * f + 1];
+  double v = 0.0 + dws[(size_t)v0 * W + e];
+  if (v1 >= 0) v += dws[(size_t)v1 * W + e];
+  if (e < D2 * D2)
+    H[(size_t)diag[f] * D2 * D2 + e] = v;
+  else
+    F[f * D2 + (e - D2 * D2)] = v;
+}
+
 template <int K>
 hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
                              const double* f, const double* tau, double* H, double* F, double* factors,
-                             const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s) {
+                             const int* elems, int64_t n, double* Cout, double* Cfout, double* dws, hipStream_t s) {
   using D = TD<K>;
-  if (!Cout) {
+  if (!Cout && !dws) {
     const size_t tot = (size_t)mesh->nfc * D::D2 * D::D2;
     k_zero_diag_t<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, (int)mesh->nfc, H, F);
     HDG_CHECK_LAUNCH("k_zero_diag");
@@ -381,12 +411,19 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
   const int64_t groups = (n + 3) / 4;
   const hdg_tile_config lc = launch_config(K);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)lc.workgroups_per_cu * device_cu_count()));
-  if (Cout)
-    k_condense_tile<K, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n,
-                                                 Cout, Cfout, lc.xcd_remap);
-  else
-    k_condense_tile<K, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems, (int)n,
-                                                  Cout, Cfout, lc.xcd_remap);
+  if (Cout) {
+    k_condense_tile<K, true, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
+                                                        (int)n, Cout, Cfout, lc.xcd_remap, nullptr);
+  } else if (dws) {
+    k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
+                                                        (int)n, Cout, Cfout, lc.xcd_remap, dws);
+    const size_t tot = (size_t)mesh->nfc * (D::D2 * D::D2 + D::D2);
+    k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
+                                                                     dws, H, F);
+  } else {
+    k_condense_tile<K, false, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
+                                                         (int)n, Cout, Cfout, lc.xcd_remap, nullptr);
+  }
   HDG_CHECK_LAUNCH("k_condense_tile");
   return HDG_OK;
 }
@@ -416,11 +453,12 @@ hdg_status launch_batch_condense_tile(int k, const Tables& tb, const BatchItem* 
 
 hdg_status dispatch_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
                                   const double* f, const double* tau, double* H, double* F, double* factors,
-                                  const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s) {
+                                  const int* elems, int64_t n, double* Cout, double* Cfout, double* dws,
+                                  hipStream_t s) {
   switch (disc->host.k) {
-    case 1: return run_condense_tile<1>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
-    case 2: return run_condense_tile<2>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
-    case 3: return run_condense_tile<3>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, s);
+    case 1: return run_condense_tile<1>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, dws, s);
+    case 2: return run_condense_tile<2>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, dws, s);
+    case 3: return run_condense_tile<3>(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, dws, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "tile condensation: unsupported degree");
 }

@@ -63,11 +63,19 @@ class HDGSystem:
         self.F = torch.empty((m.nfc, d2), dtype=torch.float64, device=self.device)
         self.factors = torch.empty((m.nelt, self.disc.factor_len), dtype=torch.float64, device=self.device)
         self.uhat = torch.zeros((m.nfc, d2), dtype=torch.float64, device=self.device)
+        # per-(element, face) buffer of the atomic-free condensation (empty for k = 0, 4)
+        self.condense_ws = torch.empty(max(L.hdg_condense_workspace_size(self.disc, m), 1), dtype=torch.uint8,
+                                       device=self.device)
 
     # ---- stages
-    def assemble(self):
-        L.hdg_assemble_condense(self.disc, self.mesh, self.kappa, self.c, self.f, self.tau, self.H, self.F,
-                                self.factors, stream=self.stream)
+    def assemble(self, atomic=False):
+        """Condensation into H, F, factors; atomic=True selects the atomic scatter (same bits)."""
+        if atomic:
+            L.hdg_assemble_condense(self.disc, self.mesh, self.kappa, self.c, self.f, self.tau, self.H, self.F,
+                                    self.factors, stream=self.stream)
+        else:
+            L.hdg_assemble_condense_ws(self.disc, self.mesh, self.kappa, self.c, self.f, self.tau, self.H, self.F,
+                                       self.factors, ws=self.condense_ws, stream=self.stream)
 
     def boundary(self):
         L.hdg_boundary(self.disc, self.mesh, self.uD, self.gN, self.H, self.F, self.uhat, stream=self.stream)

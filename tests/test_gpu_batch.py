@@ -145,3 +145,39 @@ def test_single_mesh_launch_shapes_bitwise():
     finally:
         for k, c in saved.items():
             L.hdg_set_launch_config(k, c["workgroups_per_cu"], c["xcd_remap"], c["waves_per_element"])
+
+
+def test_workspace_condensation_equals_atomic_scatter_bitwise():
+    """hdg_assemble_condense_ws (per-face sums of the stored contributions) gives the bits of
+    hdg_assemble_condense (atomic adds onto zeros) for every degree, under two launch shapes;
+    a short workspace is refused."""
+    from paper_1305_1489_amd import _lib as L
+    systems = _systems()
+    saved = {k: L.hdg_get_launch_config(k) for k in range(5)}
+    try:
+        for wpc, remap in ((4, 1), (1, 0)):
+            for k in range(1, 4):
+                L.hdg_set_launch_config(k, wpc, remap, 1)
+            for i, S in enumerate(systems):
+                need = L.hdg_condense_workspace_size(S.disc, S.mesh)
+                d2 = S.disc.d2
+                assert need == (4 * S.mesh.nelt * (d2 * d2 + d2) * 8 if 1 <= S.k <= 3 else 0)
+                H0, F0, X0 = L.hdg_assemble_condense(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau)
+                H1 = torch.full_like(H0, float("nan"))
+                F1 = torch.full_like(F0, float("nan"))
+                X1 = torch.full_like(X0, float("nan"))
+                ws = torch.full((max(need, 1) // 8,), float("nan"), dtype=torch.float64, device="cuda")
+                L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, H1, F1, X1,
+                                           ws=ws.view(torch.uint8))
+                torch.cuda.synchronize()
+                what = f"mesh {i} (k={S.k}) wpc={wpc} remap={remap}"
+                assert torch.equal(_bits(H0), _bits(H1)), what
+                assert torch.equal(_bits(F0), _bits(F1)), what
+                assert torch.equal(_bits(X0), _bits(X1)), what
+                if need:
+                    with pytest.raises(L.HdgError):
+                        L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, H1, F1, X1,
+                                                   ws=ws.view(torch.uint8)[: need - 8])
+    finally:
+        for k, c in saved.items():
+            L.hdg_set_launch_config(k, c["workgroups_per_cu"], c["xcd_remap"], c["waves_per_element"])
