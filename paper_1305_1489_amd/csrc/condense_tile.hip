@@ -71,6 +71,8 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       if (wi < nwork) {
         E = elems ? elems[wi] : wi;
         if (E < 0 || E >= mesh.nelt) E = -1;
+      } else if (DWS) {
+        E = w0;  // padding repeats the group's first element: the same values to the same places
       }
       s_E[lane] = E;
       ElemGeom g;
@@ -88,28 +90,56 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       for (int l = 0; l < 4; ++l) {
         s_geo[lane][G_T + l] = g.T[l];
         s_mu[lane][l] = g.mu[l];
-        s_fbe[lane][l] = E >= 0 ? mesh.d_facebyele[4 * E + l] : 0;
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 4; ++m)
           s_geo[lane][G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
-          s_slot[lane][4 * l + m] = (E >= 0 && !Cout) ? mesh.d_slot[16 * E + 4 * l + m] : 0;
-        }
       }
     }
-    __syncthreads();
-    for (int idx = lane; idx < 4 * NQP; idx += 64) {
-      const int e = idx / NQP, q = idx % NQP;
-      const int E = s_E[e];
-      double wk = 0, wc = 0, wf = 0;
-      if (E >= 0 && q < NQD) {
-        const double wq = s_geo[e][G_VOL] * tb.vol_w[q];
-        const size_t o = (size_t)E * NQD + q;
-        wk = wq / kappa[o];
-        wc = wq * cco[o];
-        wf = wq * fco[o];
+    {
+      // face numbers and block slots: one (element, entry) per lane, loaded unconditionally
+      // (clamped index) so that the loads of all lanes are in flight together
+      const int e = lane >> 4, i = lane & 15;
+      const int wi = w0 + e;
+      int Ee = -1;
+      if (wi < nwork) {
+        Ee = elems ? elems[wi] : wi;
+        if (Ee < 0 || Ee >= mesh.nelt) Ee = -1;
+      } else if (DWS) {
+        Ee = w0;
       }
-      s_w[0][e][q] = wk;
-      s_w[1][e][q] = wc;
-      s_w[2][e][q] = wf;
+      const size_t Es = Ee >= 0 ? (size_t)Ee : 0;
+      const int sl = mesh.d_slot[16 * Es + i];
+      const int fb = mesh.d_facebyele[4 * Es + (i & 3)];
+      s_slot[e][i] = (Ee >= 0 && !Cout) ? sl : 0;
+      if (i < 4) s_fbe[e][i] = Ee >= 0 ? fb : 0;
+    }
+    __syncthreads();
+    // all the coefficient loads of the group are issued before any is used (indices clamped
+    // instead of branched around), so that their latencies overlap
+    constexpr int WIT = (4 * NQP + 63) / 64;
+    double kv[WIT], cv[WIT], fv[WIT], vw[WIT];
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) {
+      const int idx = lane + 64 * it;
+      const int e = min(idx / NQP, 3), q = idx % NQP;
+      const int Ee = s_E[e];
+      const bool ok = idx < 4 * NQP && Ee >= 0 && q < NQD;
+      const size_t o = ok ? (size_t)Ee * NQD + q : 0;
+      kv[it] = kappa[o];
+      cv[it] = cco[o];
+      fv[it] = fco[o];
+      vw[it] = tb.vol_w[ok ? q : 0];
+    }
+#pragma unroll
+    for (int it = 0; it < WIT; ++it) {
+      const int idx = lane + 64 * it;
+      const int e = min(idx / NQP, 3), q = idx % NQP;
+      const bool ok = idx < 4 * NQP && s_E[e] >= 0 && q < NQD;
+      const double wq = ok ? s_geo[e][G_VOL] * vw[it] : 0.0;
+      if (idx < 4 * NQP) {
+        s_w[0][e][q] = ok ? wq / kv[it] : 0.0;
+        s_w[1][e][q] = wq * cv[it];
+        s_w[2][e][q] = wq * fv[it];
+      }
     }
     __syncthreads();
     const int E = s_E[blk];
@@ -277,67 +307,117 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       fa[Kk] = acc;
     }
     __builtin_amdgcn_sched_barrier(0);
-    // ---- C^K tiles and Cf^K, straight to H and F (or to the export arrays)
+    if constexpr (DWS && K < 3) {
+      // ---- C^K tiles and Cf^K into H (off-diagonal face blocks) and the per-(element, face)
+      // buffer (diagonal blocks, F).  Each tile row first runs all of its products, then
+      // stores with addresses chosen by selects: no branch splits a row, so the products of
+      // one row overlap the stores of the previous one.  (At k = 3, where the register file
+      // is full, the per-tile form below measures faster.)
+      constexpr int W = D2 * D2 + D2;
+      double* dwe = dws + (size_t)(4 * E) * W;
 #pragma unroll
-    for (int I = 0; I < MT; ++I) {
-      const int a = 4 * I + r, la = a / D2, ia = a % D2;
-      double zi[T];
+      for (int I = 0; I < MT; ++I) {
+        const int a = 4 * I + r, la = a / D2, ia = a % D2;
+        const double tl = geo[G_T + la];
+        double zi[T];
 #pragma unroll
-      for (int Kk = 0; Kk < T; ++Kk) zi[Kk] = s_Z[Kk * MT + I][lane];
+        for (int Kk = 0; Kk < T; ++Kk) zi[Kk] = s_Z[Kk * MT + I][lane];
+        double val[MT];
 #pragma unroll
-      for (int N = I; N < MT; ++N) {
-        double g1 = 0.0, g2 = 0.0;
+        for (int N = I; N < MT; ++N) {
+          double g1 = 0.0, g2 = 0.0;
 #pragma unroll
-        for (int Kk = 0; Kk < T; ++Kk) {
-          g1 = mfma4(zi[Kk], s_Z[Kk * MT + N][lane], g1);
-          g2 = mfma4(B[Kk][I], B[Kk][N], g2);
+          for (int Kk = 0; Kk < T; ++Kk) {
+            g1 = mfma4(zi[Kk], s_Z[Kk * MT + N][lane], g1);
+            g2 = mfma4(B[Kk][I], B[Kk][N], g2);
+          }
+          const int b = 4 * N + c, lb = b / D2;
+          val[N] = geo[G_NN + 4 * la + lb] * g1 - g2 + (a == b ? tl : 0.0);
         }
-        const int b = 4 * N + c, lb = b / D2, ib = b % D2;
-        double val = geo[G_NN + 4 * la + lb] * g1 - g2;
-        if (a == b) val += geo[G_T + la];
-        // only entries of the upper triangle (a <= b) are ever written; their mirror images
-        // are written from the transposed tile, so each 4-lane row of a store is contiguous
-        const double tv = tile_transpose(val);  // lane (r, c) now holds C[4I + c][4N + r]
-        if (E >= 0 && (I != N || r <= c)) {
-          if (Cout) {
-            const size_t base = (size_t)(w0 + blk) * M * M;
-            Cout[base + (size_t)a * M + b] = val;
-            Cout[base + (size_t)b * M + a] = val;
-          } else {
-            const size_t s1 = s_slot[blk][4 * la + lb];
-            if (la == lb) {
-              if constexpr (DWS) {
-                double* d = dws + (size_t)(4 * E + la) * (D2 * D2 + D2);
-                d[ia * D2 + ib] = val;
-                if (ia != ib) d[ib * D2 + ia] = val;
-              } else {
-                unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
-                if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
-              }
+        double h = 0.0;
+#pragma unroll
+        for (int Kk = 0; Kk < T; ++Kk) h = mfma4(B[Kk][I], fa[Kk], h);
+#pragma unroll
+        for (int N = I; N < MT; ++N) {
+          const int b = 4 * N + c, lb = b / D2, ib = b % D2;
+          // lane (r, c) now holds the upper entry (a2, b2) = (4I + c, 4N + r), stored mirrored
+          const double tv = tile_transpose(val[N]);
+          const int a2 = 4 * I + c, b2 = 4 * N + r, la2 = a2 / D2, lb2 = b2 / D2;
+          // both slots are read whichever array is written, and kept opaque, so the compiler
+          // selects between the two addresses instead of branching around the reads
+          int sl1 = s_slot[blk][4 * la + lb], sl2 = s_slot[blk][4 * lb2 + la2];
+          asm volatile("" : "+v"(sl1), "+v"(sl2));
+          double* p1 = la == lb ? dwe + la * W + ia * D2 + ib : H + ((size_t)sl1 * D2 + ia) * D2 + ib;
+          double* p2 = la2 == lb2 ? dwe + la2 * W + (b2 % D2) * D2 + a2 % D2
+                                  : H + ((size_t)sl2 * D2 + b2 % D2) * D2 + a2 % D2;
+          if (I != N || r <= c) *p1 = val[N];
+          if (I != N || c < r) *p2 = tv;
+        }
+        if (c == 0) dwe[la * W + D2 * D2 + ia] = h;
+      }
+    } else {
+      // ---- C^K tiles and Cf^K, straight to H and F (or to the export arrays)
+#pragma unroll
+      for (int I = 0; I < MT; ++I) {
+        const int a = 4 * I + r, la = a / D2, ia = a % D2;
+        double zi[T];
+#pragma unroll
+        for (int Kk = 0; Kk < T; ++Kk) zi[Kk] = s_Z[Kk * MT + I][lane];
+#pragma unroll
+        for (int N = I; N < MT; ++N) {
+          double g1 = 0.0, g2 = 0.0;
+#pragma unroll
+          for (int Kk = 0; Kk < T; ++Kk) {
+            g1 = mfma4(zi[Kk], s_Z[Kk * MT + N][lane], g1);
+            g2 = mfma4(B[Kk][I], B[Kk][N], g2);
+          }
+          const int b = 4 * N + c, lb = b / D2, ib = b % D2;
+          double val = geo[G_NN + 4 * la + lb] * g1 - g2;
+          if (a == b) val += geo[G_T + la];
+          // only entries of the upper triangle (a <= b) are ever written; their mirror images
+          // are written from the transposed tile, so each 4-lane row of a store is contiguous
+          const double tv = tile_transpose(val);  // lane (r, c) now holds C[4I + c][4N + r]
+          if (E >= 0 && (I != N || r <= c)) {
+            if (Cout) {
+              const size_t base = (size_t)(w0 + blk) * M * M;
+              Cout[base + (size_t)a * M + b] = val;
+              Cout[base + (size_t)b * M + a] = val;
             } else {
-              H[(s1 * D2 + ia) * D2 + ib] = val;
+              const size_t s1 = s_slot[blk][4 * la + lb];
+              if (la == lb) {
+                if constexpr (DWS) {
+                  double* d = dws + (size_t)(4 * E + la) * (D2 * D2 + D2);
+                  d[ia * D2 + ib] = val;
+                  if (ia != ib) d[ib * D2 + ia] = val;
+                } else {
+                  unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
+                  if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
+                }
+              } else {
+                H[(s1 * D2 + ia) * D2 + ib] = val;
+              }
+            }
+          }
+          {
+            const int a2 = 4 * I + c, b2 = 4 * N + r;  // the upper entry now held by this lane
+            const int la2 = a2 / D2, lb2 = b2 / D2;
+            if (!Cout && E >= 0 && (I != N || c <= r) && la2 != lb2) {
+              const size_t s2 = s_slot[blk][4 * lb2 + la2];
+              H[(s2 * D2 + b2 % D2) * D2 + a2 % D2] = tv;
             }
           }
         }
-        {
-          const int a2 = 4 * I + c, b2 = 4 * N + r;  // the upper entry now held by this lane
-          const int la2 = a2 / D2, lb2 = b2 / D2;
-          if (!Cout && E >= 0 && (I != N || c <= r) && la2 != lb2) {
-            const size_t s2 = s_slot[blk][4 * lb2 + la2];
-            H[(s2 * D2 + b2 % D2) * D2 + a2 % D2] = tv;
-          }
-        }
-      }
-      double h = 0.0;
+        double h = 0.0;
 #pragma unroll
-      for (int Kk = 0; Kk < T; ++Kk) h = mfma4(B[Kk][I], fa[Kk], h);
-      if (E >= 0 && c == 0) {
-        if (Cfout)
-          Cfout[(size_t)(w0 + blk) * M + a] = h;
-        else if constexpr (DWS)
-          dws[(size_t)(4 * E + la) * (D2 * D2 + D2) + D2 * D2 + ia] = h;
-        else
-          unsafeAtomicAdd(&F[(size_t)s_fbe[blk][la] * D2 + ia], h);
+        for (int Kk = 0; Kk < T; ++Kk) h = mfma4(B[Kk][I], fa[Kk], h);
+        if (E >= 0 && c == 0) {
+          if (Cfout)
+            Cfout[(size_t)(w0 + blk) * M + a] = h;
+          else if constexpr (DWS)
+            dws[(size_t)(4 * E + la) * (D2 * D2 + D2) + D2 * D2 + ia] = h;
+          else
+            unsafeAtomicAdd(&F[(size_t)s_fbe[blk][la] * D2 + ia], h);
+        }
       }
     }
   }
