@@ -65,6 +65,11 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     asm volatile("" : "+v"(lane));
     const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
     __syncthreads();
+    // the basis table of the Gram loop goes to the Z buffer (free until the Z phase) while
+    // the geometry and coefficients load
+    static_assert(lds_stage_bytes<NQP * D3P4>() <= (int)sizeof(s_Z), "Pt must fit in the Z buffer");
+    double* s_pt = &s_Z[0][0];
+    lds_stage<NQP * D3P4>(tb.Pt, s_pt, lane);
     if (lane < 4) {
       const int wi = w0 + lane;
       int E = -1;
@@ -151,12 +156,13 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     for (int i = 0; i < NU; ++i) Ma[i] = Sa[i] = 0.0;
 #pragma unroll
     for (int i = 0; i < T; ++i) fa[i] = 0.0;
-#pragma unroll 4  // next point tiles' table reads overlap the current products
+    lds_stage_wait();
+#pragma unroll 4
     for (int kq = 0; kq < QT; ++kq) {
       const int q = 4 * kq + r;
       double pv[T];
 #pragma unroll
-      for (int J = 0; J < T; ++J) pv[J] = tb.Pt[q * D3P4 + 4 * J + c];
+      for (int J = 0; J < T; ++J) pv[J] = s_pt[q * D3P4 + 4 * J + c];
       const double wk = s_w[0][blk][q], wc = s_w[1][blk][q], wf = s_w[2][blk][q];
 #pragma unroll
       for (int N = 0; N < T; ++N) {
@@ -171,6 +177,13 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = mfma4(pv[I], yf, fa[I]);
     }
+    // the transposed Chat tables (element-independent) go to the weight buffer, dead from
+    // here on, while the factorisations and the Z phase run
+    constexpr int L3 = D3P4 * D3P4;
+    static_assert(lds_stage_bytes<3 * L3>() <= (int)sizeof(s_w), "Chat tables must fit in the weight buffer");
+    double* s_ct = &s_w[0][0][0];
+    wave_lds_sync();
+    lds_stage<3 * L3>(tb.ChatT, s_ct, lane);
     // tau PP (eq 4.5) and identity on the padded / unused part
     {
       const double T0 = geo[G_T], T1 = geo[G_T + 1], T2 = geo[G_T + 2], T3 = geo[G_T + 3];
@@ -217,14 +230,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     __builtin_amdgcn_sched_barrier(0);
 
     // ---- W_s = L^{-1} C_s^T streamed by tile rows: S += W_s^T W_s, B += n_{ls} W_s^T Z_l.
-    // The transposed Chat tables (element-independent) are staged in LDS, in the space of
-    // the Gram weights, which are dead by now.
-    constexpr int L3 = D3P4 * D3P4;
-    static_assert(3 * L3 <= 3 * 4 * (NQP + 1), "Chat tables must fit in the weight buffer");
-    double* s_ct = &s_w[0][0][0];
-    __syncthreads();
-    for (int i = lane; i < 3 * L3; i += 64) s_ct[i] = tb.ChatT[i];
-    __syncthreads();
+    lds_stage_wait();
     double B[T][MT];
 #pragma unroll
     for (int I = 0; I < T; ++I)
@@ -307,12 +313,11 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       fa[Kk] = acc;
     }
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DWS && K < 3) {
+    if constexpr (DWS) {
       // ---- C^K tiles and Cf^K into H (off-diagonal face blocks) and the per-(element, face)
       // buffer (diagonal blocks, F).  Each tile row first runs all of its products, then
       // stores with addresses chosen by selects: no branch splits a row, so the products of
-      // one row overlap the stores of the previous one.  (At k = 3, where the register file
-      // is full, the per-tile form below measures faster.)
+      // one row overlap the stores of the previous one.
       constexpr int W = D2 * D2 + D2;
       double* dwe = dws + (size_t)(4 * E) * W;
 #pragma unroll
@@ -385,14 +390,8 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
             } else {
               const size_t s1 = s_slot[blk][4 * la + lb];
               if (la == lb) {
-                if constexpr (DWS) {
-                  double* d = dws + (size_t)(4 * E + la) * (D2 * D2 + D2);
-                  d[ia * D2 + ib] = val;
-                  if (ia != ib) d[ib * D2 + ia] = val;
-                } else {
-                  unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
-                  if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
-                }
+                unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], val);
+                if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], val);
               } else {
                 H[(s1 * D2 + ia) * D2 + ib] = val;
               }
@@ -413,8 +412,6 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
         if (E >= 0 && c == 0) {
           if (Cfout)
             Cfout[(size_t)(w0 + blk) * M + a] = h;
-          else if constexpr (DWS)
-            dws[(size_t)(4 * E + la) * (D2 * D2 + D2) + D2 * D2 + ia] = h;
           else
             unsafeAtomicAdd(&F[(size_t)s_fbe[blk][la] * D2 + ia], h);
         }

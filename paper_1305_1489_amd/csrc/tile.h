@@ -32,6 +32,28 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Asynchronous copy of an element-independent table (N doubles, N even, 16-byte aligned)
+// from global memory straight into LDS, 1 KB per wavefront instruction and no registers:
+// lane t of copy i moves doubles 128 i + 2t, +1 (clamped to the table, so the source is
+// never overrun); the LDS destination must hold whole kilobytes, ceil(8N / 1024) of them.
+// Completion is awaited with lds_stage_wait() before the first read.
+template <int N>
+__device__ __forceinline__ void lds_stage(const double* __restrict__ src, double* dst, int lane) {
+  static_assert(N % 2 == 0, "tables are staged in pairs of doubles");
+  constexpr int NI = (N * 8 + 1023) / 1024;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int o = min(128 * i + 2 * lane, N - 2);
+    __builtin_amdgcn_global_load_lds(src + o, (__attribute__((address_space(3))) void*)(dst + 128 * i), 16, 0, 0);
+  }
+}
+template <int N>
+constexpr int lds_stage_bytes() { return (N * 8 + 1023) / 1024 * 1024; }
+__device__ __forceinline__ void lds_stage_wait() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  wave_lds_sync();
+}
+
 // Upper Cholesky of one 4x4 SPD tile per block (A = U^T U) and the inverse V = U^{-1}.
 // Every lane of the block reads the whole tile through LDS and factors it redundantly;
 // it returns its own entries U[r][c] and V[r][c].  xch: 64 doubles of LDS, private to the
