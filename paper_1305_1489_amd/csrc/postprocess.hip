@@ -112,23 +112,37 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
     const int Ec = 4 * grp + c < mesh.nelt ? 4 * grp + c : -1;
 
     // ---- V = Q a, elements in the tile columns: lane (r, c) of tile J holds V_c[4J + r][h]
-    double V[3][JT];
+    // every global load of the group is issued before any is used (indices clamped instead
+    // of branched around), so that their latencies overlap
+    constexpr bool PRE = QI <= 8;  // the point coefficients too, while registers allow
+    double qv[JT][3], kap[PRE ? QI : 1], vw[PRE ? QI : 1];
 #pragma unroll
     for (int J = 0; J < JT; ++J) {
       const int j = 4 * J + r;
-      double qs[3] = {0.0, 0.0, 0.0};
-      if (Ec >= 0 && j < D3) {
+      const size_t o = (Ec >= 0 && j < D3) ? (size_t)Ec * 3 * D3 + j : 0;
 #pragma unroll
-        for (int s = 0; s < 3; ++s) qs[s] = qin[((size_t)Ec * 3 + s) * D3 + j];
-      }
+      for (int s = 0; s < 3; ++s) qv[J][s] = qin[o + (size_t)s * D3];
+    }
 #pragma unroll
-      for (int h = 0; h < 3; ++h) V[h][J] = qs[0] * a[h] + qs[1] * a[3 + h] + qs[2] * a[6 + h];
+    for (int qi = 0; qi < (PRE ? QI : 0); ++qi) {
+      const int Qt = 4 * qi + blk, q = 4 * Qt + r;
+      const bool ok = Qt < QT && q < NQD && Ec >= 0;
+      kap[qi] = kappa[ok ? (size_t)Ec * NQD + q : 0];
+      vw[qi] = tb.vol_w[ok ? q : 0];
+    }
+    double V[3][JT];
+#pragma unroll
+    for (int J = 0; J < JT; ++J) {
+      const bool ok = Ec >= 0 && 4 * J + r < D3;
+      const double q0 = ok ? qv[J][0] : 0.0, q1 = ok ? qv[J][1] : 0.0, q2 = ok ? qv[J][2] : 0.0;
+#pragma unroll
+      for (int h = 0; h < 3; ++h) V[h][J] = q0 * a[h] + q1 * a[3 + h] + q2 * a[6 + h];
     }
     // ---- split-K over the points: block blk takes point tiles blk, blk + 4, ...
     double R[TS];
 #pragma unroll
     for (int I = 0; I < TS; ++I) R[I] = 0.0;
-#pragma unroll 2
+#pragma unroll(PRE ? QI : 2)
     for (int qi = 0; qi < QI; ++qi) {
       const int Qt = 4 * qi + blk;
       const int Ql = Qt < QT ? Qt : QT - 1;  // tiles past the end read in bounds, weigh zero
@@ -137,7 +151,11 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
       for (int J = 0; J < JT; ++J) xp[J] = s_pt[(4 * Ql + c) * PTS + 4 * J + r];
       const int q = 4 * Qt + r;
       double wr = 0.0;
-      if (Qt < QT && q < NQD && Ec >= 0) wr = wscale * tb.vol_w[q] / kappa[(size_t)Ec * NQD + q];
+      if constexpr (PRE) {
+        wr = (Qt < QT && q < NQD && Ec >= 0) ? wscale * vw[qi] / kap[qi] : 0.0;
+      } else {
+        if (Qt < QT && q < NQD && Ec >= 0) wr = wscale * tb.vol_w[q] / kappa[(size_t)Ec * NQD + q];
+      }
       double y[3];
 #pragma unroll
       for (int h = 0; h < 3; ++h) {
