@@ -22,6 +22,8 @@
 // The factor store keeps U, Us (packed upper tiles) and f (tiles, column 0) per element.
 #include "tile.h"
 
+#include <type_traits>
+
 namespace hdg {
 namespace {
 
@@ -457,21 +459,38 @@ __global__ void k_zero_diag_t(const int* __restrict__ diag, int nfc, double* __r
 
 // H_ff (diagonal block) and F_f from the per-(element, face) contributions of the (one or
 // two) elements holding face f, in a fixed order; (0 + a) + b equals the atomic result.
+// P = 2 doubles per thread where d2 d2 is even (then every base is 16-byte aligned), else 1.
 template <int D2>
 __global__ void k_diag_sum(const int* __restrict__ diag, const int* __restrict__ face_elem, int nfc,
                            const double* __restrict__ dws, double* __restrict__ H, double* __restrict__ F) {
-  constexpr int W = D2 * D2 + D2;
-  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  if (i >= (size_t)nfc * W) return;
-  const size_t f = i / W;
-  const int e = (int)(i % W);
+  constexpr int W = D2 * D2 + D2, P = (D2 * D2) % 2 == 0 ? 2 : 1, WP = W / P;
+  using V = typename std::conditional<P == 2, double2, double>::type;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nfc * WP) return;
+  const int f = (int)(i / WP);
+  const int e = P * (int)(i - (int64_t)f * WP);
   const int v0 = face_elem[2 * f], v1 = face_elem[2 * f + 1];
-  double v = 0.0 + dws[(size_t)v0 * W + e];
-  if (v1 >= 0) v += dws[(size_t)v1 * W + e];
+  const V a = *reinterpret_cast<const V*>(dws + (size_t)v0 * W + e);
+  V v = a;
+  if constexpr (P == 2) {
+    v.x = 0.0 + a.x;
+    v.y = 0.0 + a.y;
+  } else {
+    v = 0.0 + a;
+  }
+  if (v1 >= 0) {
+    const V b = *reinterpret_cast<const V*>(dws + (size_t)v1 * W + e);
+    if constexpr (P == 2) {
+      v.x += b.x;
+      v.y += b.y;
+    } else {
+      v += b;
+    }
+  }
   if (e < D2 * D2)
-    H[(size_t)diag[f] * D2 * D2 + e] = v;
+    *reinterpret_cast<V*>(H + (size_t)diag[f] * D2 * D2 + e) = v;
   else
-    F[f * D2 + (e - D2 * D2)] = v;
+    *reinterpret_cast<V*>(F + (size_t)f * D2 + (e - D2 * D2)) = v;
 }
 
 template <int K>
@@ -494,7 +513,7 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
   } else if (dws) {
     k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
                                                         (int)n, Cout, Cfout, lc.xcd_remap, dws);
-    const size_t tot = (size_t)mesh->nfc * (D::D2 * D::D2 + D::D2);
+    const size_t tot = (size_t)mesh->nfc * (D::D2 * D::D2 + D::D2) / ((D::D2 * D::D2) % 2 == 0 ? 2 : 1);
     k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
                                                                      dws, H, F);
   } else {
