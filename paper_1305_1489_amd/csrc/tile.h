@@ -69,31 +69,33 @@ __device__ __forceinline__ void diag_chol4(double a_rc, double* xch, double& u_r
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) a[i][j] = xch[blk * 16 + i * 4 + j];
-  double u[4][4] = {}, v[4][4] = {};
+  // one reciprocal square root per pivot and no division: FP64 vector work is issued on
+  // the matrix cores' time, and this chain is serial
+  double u[4][4] = {}, v[4][4] = {}, dinv[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     double s = a[i][i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s -= u[k][i] * u[k][i];
-    u[i][i] = sqrt(s);
-    const double inv = 1.0 / u[i][i];
+    dinv[i] = rsqrt(s);
+    u[i][i] = s * dinv[i];
 #pragma unroll
     for (int j = i + 1; j < 4; ++j) {
       double t = a[i][j];
 #pragma unroll
       for (int k = 0; k < i; ++k) t -= u[k][i] * u[k][j];
-      u[i][j] = t * inv;
+      u[i][j] = t * dinv[i];
     }
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    v[j][j] = 1.0 / u[j][j];
+    v[j][j] = dinv[j];
 #pragma unroll
     for (int i = j - 1; i >= 0; --i) {
       double t = 0;
 #pragma unroll
       for (int k = i + 1; k <= j; ++k) t += u[i][k] * v[k][j];
-      v[i][j] = -t / u[i][i];
+      v[i][j] = -t * dinv[i];
     }
   }
   double ur = 0, vr = 0;
