@@ -54,6 +54,16 @@ __device__ __forceinline__ void lds_stage_wait() {
   wave_lds_sync();
 }
 
+// 1/sqrt(s) for a positive normal s (a Cholesky pivot): the hardware estimate (relative
+// error about 2^-23) refined by two Newton steps y <- y (3/2 - s y^2 / 2), to round-off.
+__device__ __forceinline__ double pivot_rsqrt(double s) {
+  double y = __builtin_amdgcn_rsq(s);
+  const double hs = 0.5 * s;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-hs * y, y, 0.5), y);
+  return y;
+}
+
 // Upper Cholesky of one 4x4 SPD tile per block (A = U^T U) and the inverse V = U^{-1}.
 // Every lane of the block reads the whole tile through LDS and factors it redundantly;
 // it returns its own entries U[r][c] and V[r][c].  xch: 64 doubles of LDS, private to the
@@ -77,7 +87,7 @@ __device__ __forceinline__ void diag_chol4(double a_rc, double* xch, double& u_r
     double s = a[i][i];
 #pragma unroll
     for (int k = 0; k < i; ++k) s -= u[k][i] * u[k][i];
-    dinv[i] = rsqrt(s);
+    dinv[i] = pivot_rsqrt(s);
     u[i][i] = s * dinv[i];
 #pragma unroll
     for (int j = i + 1; j < 4; ++j) {
