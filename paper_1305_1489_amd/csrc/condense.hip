@@ -340,8 +340,7 @@ extern "C" hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh
 
 extern "C" hdg_status hdg_condense_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes) {
   if (!disc || !mesh || !bytes) return set_error(HDG_ERR_INVALID_ARG, "hdg_condense_workspace_size: NULL argument");
-  const int d2 = disc->host.d2;
-  *bytes = (disc->host.k >= 1 && disc->host.k <= 3) ? (size_t)4 * mesh->nelt * (d2 * d2 + d2) * sizeof(double) : 0;
+  *bytes = (disc->host.k >= 1 && disc->host.k <= 3) ? condense_ws_bytes(disc->host.d2, mesh->nelt) : 0;
   return HDG_OK;
 }
 

@@ -35,7 +35,47 @@ struct TD {
   static constexpr int FACTOR_LEN = (2 * NU + T) * 16;
 };
 
-enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_LEN = 43 };
+enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_MU = 43, G_REC = kGeoRecord };
+static_assert(G_MU + 4 <= G_REC, "geometry record layout");
+
+// The geometry record of element E (E < 0: a reference element with no data), laid out as
+// above, perm - 1 stored as small integers in doubles.  No FMA contraction here or in
+// load_geometry, so that the records precomputed by k_geo_records and the ones computed
+// inline by the other forms of the condensation are the same bits.
+__device__ inline void tile_geo_record(int E, const hdg_mesh& mesh, const double* __restrict__ tau, double* rec) {
+#pragma clang fp contract(off)
+  ElemGeom g;
+  if (E >= 0) {
+    load_geometry(E, mesh, tau, g);
+  } else {
+    g = ElemGeom{};
+    g.vol = 1.0;
+    g.det = 6.0;
+  }
+  for (int i = 0; i < 9; ++i) rec[G_A + i] = g.a[i / 3][i % 3];
+  rec[G_DET] = g.det;
+  rec[G_VOL] = g.vol;
+  for (int i = 0; i < 12; ++i) rec[G_N + i] = g.n[i / 3][i % 3];
+  for (int l = 0; l < 4; ++l) {
+    rec[G_T + l] = g.T[l];
+    rec[G_MU + l] = (double)g.mu[l];
+    for (int m = 0; m < 4; ++m)
+      rec[G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
+  }
+  for (int i = G_MU + 4; i < G_REC; ++i) rec[i] = 0.0;
+}
+
+// One geometry record per element, for the workspace form of the condensation.
+__global__ void __launch_bounds__(256) k_geo_records(hdg_mesh mesh, const double* __restrict__ tau,
+                                                     double* __restrict__ rec) {
+  const int E = blockIdx.x * blockDim.x + threadIdx.x;
+  if (E >= mesh.nelt) return;
+  double r[G_REC];
+  tile_geo_record(E, mesh, tau, r);
+  double2* out = reinterpret_cast<double2*>(rec + (size_t)E * G_REC);
+#pragma unroll
+  for (int i = 0; i < G_REC / 2; ++i) out[i] = double2{r[2 * i], r[2 * i + 1]};
+}
 
 // One group of four elements (w0 .. w0+3 of the work list) on one wavefront.  With DWS the
 // diagonal face blocks and F entries of C^K, Cf^K go to the per-(element, face) buffer dws
@@ -47,13 +87,13 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
                                                       const double* __restrict__ tau, double* __restrict__ H,
                                                       double* __restrict__ F, double* __restrict__ factors,
                                                       const int* __restrict__ elems, int nwork,
-                                                      double* __restrict__ Cout, double* __restrict__ Cfout, int w0, double* __restrict__ dws) {
+                                                      double* __restrict__ Cout, double* __restrict__ Cfout, int w0, double* __restrict__ dws,
+                                                      const double* __restrict__ geo_rec) {
   using D = TD<K>;
   constexpr int T = D::T, MT = D::MT, QT = D::QT, D3 = D::D3, D2 = D::D2, M = D::M;
   constexpr int NQD = D::NQD, NQP = D::NQP, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
   __shared__ double s_w[3][4][NQP + 1];  // +1: the four elements' rows start in different banks
-  __shared__ double s_geo[4][G_LEN];
-  __shared__ int s_mu[4][4];
+  __shared__ double s_geo[4][G_REC];
   __shared__ int s_slot[4][16];
   __shared__ int s_fbe[4][4];
   __shared__ int s_E[4];
@@ -72,70 +112,81 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     static_assert(lds_stage_bytes<NQP * D3P4>() <= (int)sizeof(s_Z), "Pt must fit in the Z buffer");
     double* s_pt = &s_Z[0][0];
     lds_stage<NQP * D3P4>(tb.Pt, s_pt, lane);
-    if (lane < 4) {
-      const int wi = w0 + lane;
-      int E = -1;
-      if (wi < nwork) {
-        E = elems ? elems[wi] : wi;
-        if (E < 0 || E >= mesh.nelt) E = -1;
-      } else if (DWS) {
-        E = w0;  // padding repeats the group's first element: the same values to the same places
-      }
-      s_E[lane] = E;
-      ElemGeom g;
-      if (E >= 0) {
-        load_geometry(E, mesh, tau, g);
-      } else {
-        g = ElemGeom{};
-        g.vol = 1.0;
-        g.det = 6.0;
-      }
-      for (int i = 0; i < 9; ++i) s_geo[lane][G_A + i] = g.a[i / 3][i % 3];
-      s_geo[lane][G_DET] = g.det;
-      s_geo[lane][G_VOL] = g.vol;
-      for (int i = 0; i < 12; ++i) s_geo[lane][G_N + i] = g.n[i / 3][i % 3];
-      for (int l = 0; l < 4; ++l) {
-        s_geo[lane][G_T + l] = g.T[l];
-        s_mu[lane][l] = g.mu[l];
-        for (int m = 0; m < 4; ++m)
-          s_geo[lane][G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
-      }
-    }
-    {
-      // face numbers and block slots: one (element, entry) per lane, loaded unconditionally
-      // (clamped index) so that the loads of all lanes are in flight together
-      const int e = lane >> 4, i = lane & 15;
-      const int wi = w0 + e;
-      int Ee = -1;
-      if (wi < nwork) {
-        Ee = elems ? elems[wi] : wi;
-        if (Ee < 0 || Ee >= mesh.nelt) Ee = -1;
-      } else if (DWS) {
-        Ee = w0;
-      }
-      const size_t Es = Ee >= 0 ? (size_t)Ee : 0;
-      const int sl = mesh.d_slot[16 * Es + i];
-      const int fb = mesh.d_facebyele[4 * Es + (i & 3)];
-      s_slot[e][i] = (Ee >= 0 && !Cout) ? sl : 0;
-      if (i < 4) s_fbe[e][i] = Ee >= 0 ? fb : 0;
-    }
-    __syncthreads();
-    // all the coefficient loads of the group are issued before any is used (indices clamped
-    // instead of branched around), so that their latencies overlap
     constexpr int WIT = (4 * NQP + 63) / 64;
     double kv[WIT], cv[WIT], fv[WIT], vw[WIT];
+    if constexpr (DWS) {
+      // the precomputed geometry records, the block slots and the coefficients of the
+      // group: every load is issued before any is used (the padding of a ragged last group
+      // repeats its first element), so that all their latencies overlap in one round trip
+      const auto elem = [&](int e) { return w0 + e < nwork ? w0 + e : w0; };
+      static_assert(4 * G_REC % 64 == 0, "geometry records in whole passes");
+      constexpr int GIT = 4 * G_REC / 64;
+      double gv[GIT];
 #pragma unroll
-    for (int it = 0; it < WIT; ++it) {
-      const int idx = lane + 64 * it;
-      const int e = min(idx / NQP, 3), q = idx % NQP;
-      const int Ee = s_E[e];
-      const bool ok = idx < 4 * NQP && Ee >= 0 && q < NQD;
-      const size_t o = ok ? (size_t)Ee * NQD + q : 0;
-      kv[it] = kappa[o];
-      cv[it] = cco[o];
-      fv[it] = fco[o];
-      vw[it] = tb.vol_w[ok ? q : 0];
+      for (int j = 0; j < GIT; ++j) {
+        const int idx = lane + 64 * j;
+        gv[j] = geo_rec[(size_t)elem(idx / G_REC) * G_REC + idx % G_REC];
+      }
+      const int sl = mesh.d_slot[16 * (size_t)elem(lane >> 4) + (lane & 15)];
+#pragma unroll
+      for (int it = 0; it < WIT; ++it) {
+        const int idx = lane + 64 * it;
+        const int e = min(idx / NQP, 3), q = idx % NQP;
+        const bool ok = idx < 4 * NQP && q < NQD;
+        const size_t o = ok ? (size_t)elem(e) * NQD + q : 0;
+        kv[it] = kappa[o];
+        cv[it] = cco[o];
+        fv[it] = fco[o];
+        vw[it] = tb.vol_w[ok ? q : 0];
+      }
+#pragma unroll
+      for (int j = 0; j < GIT; ++j) (&s_geo[0][0])[lane + 64 * j] = gv[j];
+      s_slot[lane >> 4][lane & 15] = sl;
+      if (lane < 4) s_E[lane] = elem(lane);
+    } else {
+      if (lane < 4) {
+        const int wi = w0 + lane;
+        int E = -1;
+        if (wi < nwork) {
+          E = elems ? elems[wi] : wi;
+          if (E < 0 || E >= mesh.nelt) E = -1;
+        }
+        s_E[lane] = E;
+        tile_geo_record(E, mesh, tau, s_geo[lane]);
+      }
+      {
+        // face numbers and block slots: one (element, entry) per lane, loaded
+        // unconditionally (clamped index) so that the loads of all lanes are in flight together
+        const int e = lane >> 4, i = lane & 15;
+        const int wi = w0 + e;
+        int Ee = -1;
+        if (wi < nwork) {
+          Ee = elems ? elems[wi] : wi;
+          if (Ee < 0 || Ee >= mesh.nelt) Ee = -1;
+        }
+        const size_t Es = Ee >= 0 ? (size_t)Ee : 0;
+        const int sl = mesh.d_slot[16 * Es + i];
+        const int fb = mesh.d_facebyele[4 * Es + (i & 3)];
+        s_slot[e][i] = (Ee >= 0 && !Cout) ? sl : 0;
+        if (i < 4) s_fbe[e][i] = Ee >= 0 ? fb : 0;
+      }
+      __syncthreads();
+      // all the coefficient loads of the group are issued before any is used (indices
+      // clamped instead of branched around), so that their latencies overlap
+#pragma unroll
+      for (int it = 0; it < WIT; ++it) {
+        const int idx = lane + 64 * it;
+        const int e = min(idx / NQP, 3), q = idx % NQP;
+        const int Ee = s_E[e];
+        const bool ok = idx < 4 * NQP && Ee >= 0 && q < NQD;
+        const size_t o = ok ? (size_t)Ee * NQD + q : 0;
+        kv[it] = kappa[o];
+        cv[it] = cco[o];
+        fv[it] = fco[o];
+        vw[it] = tb.vol_w[ok ? q : 0];
+      }
     }
+    __syncthreads();
 #pragma unroll
     for (int it = 0; it < WIT; ++it) {
       const int idx = lane + 64 * it;
@@ -217,7 +268,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 #pragma unroll
     for (int N = 0; N < MT; ++N) {
       const int j = 4 * N + c, l = j / D2, i = j % D2;
-      const double* dpt = tb.DPT + (size_t)(s_mu[blk][l] * 4 + l) * D3P4 * D2P4 + i;
+      const double* dpt = tb.DPT + (size_t)((int)geo[G_MU + l] * 4 + l) * D3P4 * D2P4 + i;
       double rhs[T];
 #pragma unroll
       for (int J = 0; J < T; ++J) rhs[J] = dpt[(4 * J + r) * D2P4];
@@ -275,7 +326,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     for (int N = 0; N < MT; ++N) {
       const int j = 4 * N + c, l = j / D2, i = j % D2;
       const double Tl = geo[G_T + l];
-      const double* dpt = tb.DPT + (size_t)(s_mu[blk][l] * 4 + l) * D3P4 * D2P4 + i;
+      const double* dpt = tb.DPT + (size_t)((int)geo[G_MU + l] * 4 + l) * D3P4 * D2P4 + i;
 #pragma unroll
       for (int I = 0; I < T; ++I) B[I][N] += Tl * dpt[(4 * I + r) * D2P4];
     }
@@ -431,10 +482,11 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
                                                       double* __restrict__ F, double* __restrict__ factors,
                                                       const int* __restrict__ elems, int nwork,
                                                       double* __restrict__ Cout, double* __restrict__ Cfout,
-                                                      int xcd_remap, double* __restrict__ dws) {
+                                                      int xcd_remap, double* __restrict__ dws,
+                                                      const double* __restrict__ geo_rec) {
   for (int w0 = batch_block(xcd_remap) * 4; w0 < nwork; w0 += gridDim.x * 4)
     condense_tile_group<K, DWS>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
-                                EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w0, dws);
+                                EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w0, dws, DWS ? geo_rec : nullptr);
 }
 
 // Persistent batched form: work unit u is group u - unit_begin of its mesh.
@@ -444,7 +496,7 @@ __global__ void __launch_bounds__(64) k_batch_condense_tile(const BatchItem* __r
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
     condense_tile_group<K, false>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
-                                  (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin), nullptr);
+                                  (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin), nullptr, nullptr);
   }
 }
 
@@ -509,16 +561,18 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)lc.workgroups_per_cu * device_cu_count()));
   if (Cout) {
     k_condense_tile<K, true, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
-                                                        (int)n, Cout, Cfout, lc.xcd_remap, nullptr);
+                                                        (int)n, Cout, Cfout, lc.xcd_remap, nullptr, nullptr);
   } else if (dws) {
+    double* geo_rec = reinterpret_cast<double*>(reinterpret_cast<char*>(dws) + condense_ws_geo_offset(D::D2, mesh->nelt));
+    k_geo_records<<<(unsigned)((mesh->nelt + 255) / 256), 256, 0, s>>>(*mesh, tau, geo_rec);
     k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
-                                                        (int)n, Cout, Cfout, lc.xcd_remap, dws);
+                                                        (int)n, Cout, Cfout, lc.xcd_remap, dws, geo_rec);
     const size_t tot = (size_t)mesh->nfc * (D::D2 * D::D2 + D::D2) / ((D::D2 * D::D2) % 2 == 0 ? 2 : 1);
     k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
                                                                      dws, H, F);
   } else {
     k_condense_tile<K, false, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
-                                                         (int)n, Cout, Cfout, lc.xcd_remap, nullptr);
+                                                         (int)n, Cout, Cfout, lc.xcd_remap, nullptr, nullptr);
   }
   HDG_CHECK_LAUNCH("k_condense_tile");
   return HDG_OK;

@@ -29,6 +29,8 @@ struct ElemGeom {
 };
 
 __device__ inline void load_geometry(int K, const hdg_mesh& mesh, const double* __restrict__ tau, ElemGeom& g) {
+  // no FMA contraction: every kernel, whichever way it is compiled, gets the same bits
+#pragma clang fp contract(off)
   const int* el = mesh.d_elements + 4 * K;
   double p[4][3];
   for (int i = 0; i < 4; ++i) {

@@ -18,6 +18,19 @@ inline constexpr int dim2(int k) { return (k + 1) * (k + 2) / 2; }
 inline constexpr int tri(int n) { return n * (n + 1) / 2; }
 
 // Offsets (in doubles) of every reference table inside the device table buffer.
+// Doubles per element of the precomputed geometry record of the tile condensation (its
+// workspace form): cofactors, det, |K|, normals, T_l, (n_l.n_m), perm, padding.
+constexpr int kGeoRecord = 48;
+
+// Byte layout of the workspace of hdg_assemble_condense_ws: the per-(element, face)
+// diagonal contributions, then the geometry records, each 256-byte aligned.
+inline size_t condense_ws_geo_offset(int d2, int64_t nelt) {
+  return ((size_t)4 * nelt * (d2 * d2 + d2) * sizeof(double) + 255) / 256 * 256;
+}
+inline size_t condense_ws_bytes(int d2, int64_t nelt) {
+  return condense_ws_geo_offset(d2, nelt) + (size_t)nelt * kGeoRecord * sizeof(double);
+}
+
 struct TableOffsets {
   int vol_pts, vol_w, lambda, P, Pg, tri_pts, tri_w, xi, D, Pface, Chat, PP, DP, P1g, Shat;
   // zero-padded copies for the 4x4-tile kernels (dimensions rounded up to multiples of 4)
