@@ -105,7 +105,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     // (hoisted, they outlive the register file and spill)
     int lane = threadIdx.x;
     asm volatile("" : "+v"(lane));
-    const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
+    const int r = (lane >> 4) & 3, c = lane & 3, blk = (lane >> 2) & 3;
     __syncthreads();
     // the basis table of the Gram loop goes to the Z buffer (free until the Z phase) while
     // the geometry and coefficients load
@@ -246,14 +246,14 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
         for (int N = I; N < T; ++N) {
           const int o = (4 * I + r) * D3P4 + 4 * N + c;
           constexpr int L4 = D3P4 * D3P4;
-          Sa[utile(I, N, T)] += T0 * tb.PPt[o] + T1 * tb.PPt[L4 + o] + T2 * tb.PPt[2 * L4 + o] + T3 * tb.PPt[3 * L4 + o];
-          if (I == N && r == c && (4 * I + r >= D3 || E < 0)) {
-            Ma[utile(I, N, T)] = 1.0;
-            Sa[utile(I, N, T)] = 1.0;
-          } else if (E < 0) {
-            Ma[utile(I, N, T)] = 0.0;
-            Sa[utile(I, N, T)] = 0.0;
-          }
+          const double sv =
+              Sa[utile(I, N, T)] + (T0 * tb.PPt[o] + T1 * tb.PPt[L4 + o] + T2 * tb.PPt[2 * L4 + o] + T3 * tb.PPt[3 * L4 + o]);
+          // selects, not branches (a branch here reshuffles the whole Gram state); the
+          // workspace form has no empty slot (its padding repeats a real element)
+          const bool empty = !DWS && E < 0;
+          const bool unit = I == N && r == c && (4 * I + r >= D3 || empty);
+          Ma[utile(I, N, T)] = unit ? 1.0 : (empty ? 0.0 : Ma[utile(I, N, T)]);
+          Sa[utile(I, N, T)] = unit ? 1.0 : (empty ? 0.0 : sv);
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -282,45 +282,60 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     }
     __builtin_amdgcn_sched_barrier(0);
 
-    // ---- W_s = L^{-1} C_s^T streamed by tile rows: S += W_s^T W_s, B += n_{ls} W_s^T Z_l.
+    // ---- W_s = L^{-1} C_s^T streamed by tile rows, the three directions together:
+    // S += sum_s W_s^T W_s, and B += sum_s n_{ls} W_s^T Z_l = U_l^T Z_l with
+    // U_l = sum_s n_{ls} W_s, so that each face's columns take one product per tile (two for
+    // a tile whose columns straddle two faces, each with the other face's columns masked).
     lds_stage_wait();
     double B[T][MT];
 #pragma unroll
     for (int I = 0; I < T; ++I)
 #pragma unroll
       for (int N = 0; N < MT; ++N) B[I][N] = 0.0;
-    for (int s = 0; s < 3; ++s) {
-      const double a0 = geo[G_A + 3 * s], a1 = geo[G_A + 3 * s + 1], a2 = geo[G_A + 3 * s + 2];
-      double nls[MT];
 #pragma unroll
-      for (int N = 0; N < MT; ++N) nls[N] = geo[G_N + 3 * ((4 * N + c) / D2) + s];
+    for (int Kk = 0; Kk < T; ++Kk) {
+      double Wr[3][T];
 #pragma unroll
-      for (int Kk = 0; Kk < T; ++Kk) {
-        double Wr[T];
+      for (int N = 0; N < T; ++N) {
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
 #pragma unroll
-        for (int N = 0; N < T; ++N) {
-          double acc = 0.0;
-#pragma unroll
-          for (int J = 0; J <= Kk; ++J) {
-            const int o = (4 * J + r) * D3P4 + 4 * N + c;
-            const double ct = a0 * s_ct[o] + a1 * s_ct[L3 + o] + a2 * s_ct[2 * L3 + o];
-            acc = mfma4(Ui[utile(J, Kk, T)], ct, acc);
-          }
-          Wr[N] = acc;
+        for (int J = 0; J <= Kk; ++J) {
+          const int o = (4 * J + r) * D3P4 + 4 * N + c;
+          const double h0 = s_ct[o], h1 = s_ct[L3 + o], h2 = s_ct[2 * L3 + o];
+          const double u = Ui[utile(J, Kk, T)];
+          acc0 = mfma4(u, geo[G_A + 0] * h0 + geo[G_A + 1] * h1 + geo[G_A + 2] * h2, acc0);
+          acc1 = mfma4(u, geo[G_A + 3] * h0 + geo[G_A + 4] * h1 + geo[G_A + 5] * h2, acc1);
+          acc2 = mfma4(u, geo[G_A + 6] * h0 + geo[G_A + 7] * h1 + geo[G_A + 8] * h2, acc2);
         }
+        Wr[0][N] = acc0;
+        Wr[1][N] = acc1;
+        Wr[2][N] = acc2;
+      }
+#pragma unroll
+      for (int sd = 0; sd < 3; ++sd)
 #pragma unroll
         for (int I = 0; I < T; ++I)
 #pragma unroll
-          for (int N = I; N < T; ++N) Sa[utile(I, N, T)] = mfma4(Wr[I], Wr[N], Sa[utile(I, N, T)]);
+          for (int N = I; N < T; ++N) Sa[utile(I, N, T)] = mfma4(Wr[sd][I], Wr[sd][N], Sa[utile(I, N, T)]);
 #pragma unroll
-        for (int N = 0; N < MT; ++N) {
-          const double zs = nls[N] * s_Z[Kk * MT + N][lane];
+      for (int l = 0; l < 4; ++l) {
+        const double n0 = geo[G_N + 3 * l], n1 = geo[G_N + 3 * l + 1], n2 = geo[G_N + 3 * l + 2];
+        double U[T];
 #pragma unroll
-          for (int I = 0; I < T; ++I) B[I][N] = mfma4(Wr[I], zs, B[I][N]);
+        for (int I = 0; I < T; ++I) U[I] = n0 * Wr[0][I] + n1 * Wr[1][I] + n2 * Wr[2][I];
+#pragma unroll
+        for (int N = (l * D2) / 4; N <= ((l + 1) * D2 - 1) / 4; ++N) {
+          const double z = s_Z[Kk * MT + N][lane];
+          // columns 4N + c of this tile that belong to face l (all four, unless it straddles)
+          const bool mine = (4 * N + c) / D2 == l;
+          const bool whole = 4 * N >= l * D2 && 4 * N + 3 < (l + 1) * D2;
+          const double zl = (whole || mine) ? z : 0.0;
+#pragma unroll
+          for (int I = 0; I < T; ++I) B[I][N] = mfma4(U[I], zl, B[I][N]);
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
+    __builtin_amdgcn_sched_barrier(0);
     // B += T_l DP_l^T
 #pragma unroll
     for (int N = 0; N < MT; ++N) {
