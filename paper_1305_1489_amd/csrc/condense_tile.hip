@@ -239,15 +239,23 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     lds_stage<3 * L3>(tb.ChatT, s_ct, lane);
     // tau PP (eq 4.5) and identity on the padded / unused part
     {
+      // the table reads are all issued first (else the compiler recycles one register pair
+      // and waits after each)
+      constexpr int L4 = D3P4 * D3P4;
+      double pp[NU][4];
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int N = I; N < T; ++N)
+#pragma unroll
+          for (int l = 0; l < 4; ++l) pp[utile(I, N, T)][l] = tb.PPt[l * L4 + (4 * I + r) * D3P4 + 4 * N + c];
       const double T0 = geo[G_T], T1 = geo[G_T + 1], T2 = geo[G_T + 2], T3 = geo[G_T + 3];
 #pragma unroll
       for (int I = 0; I < T; ++I)
 #pragma unroll
         for (int N = I; N < T; ++N) {
-          const int o = (4 * I + r) * D3P4 + 4 * N + c;
-          constexpr int L4 = D3P4 * D3P4;
-          const double sv =
-              Sa[utile(I, N, T)] + (T0 * tb.PPt[o] + T1 * tb.PPt[L4 + o] + T2 * tb.PPt[2 * L4 + o] + T3 * tb.PPt[3 * L4 + o]);
+          const double* q = pp[utile(I, N, T)];
+          const double sv = Sa[utile(I, N, T)] + (T0 * q[0] + T1 * q[1] + T2 * q[2] + T3 * q[3]);
           // selects, not branches (a branch here reshuffles the whole Gram state); the
           // workspace form has no empty slot (its padding repeats a real element)
           const bool empty = !DWS && E < 0;
