@@ -95,6 +95,9 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
   __shared__ double s_w[3][4][NQP + 1];  // +1: the four elements' rows start in different banks
   __shared__ double s_geo[4][G_REC];
   __shared__ int s_slot[4][16];
+  // workspace form: the 16 block base addresses (l, m) of each element of the group, the H
+  // block of slot(l, m) for l != m and the element's own buffer block for l = m
+  __shared__ double* s_base[DWS ? 4 : 1][16];
   __shared__ int s_fbe[4][4];
   __shared__ int s_E[4];
   __shared__ double s_x[64];
@@ -142,6 +145,11 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 #pragma unroll
       for (int j = 0; j < GIT; ++j) (&s_geo[0][0])[lane + 64 * j] = gv[j];
       s_slot[lane >> 4][lane & 15] = sl;
+      {
+        const int l = (lane >> 2) & 3, m = lane & 3;
+        s_base[lane >> 4][lane & 15] = l == m ? dws + (size_t)(4 * elem(lane >> 4) + l) * (D2 * D2 + D2)
+                                              : H + (size_t)sl * D2 * D2;
+      }
       if (lane < 4) s_E[lane] = elem(lane);
     } else {
       if (lane < 4) {
@@ -392,10 +400,9 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
     if constexpr (DWS) {
       // ---- C^K tiles and Cf^K into H (off-diagonal face blocks) and the per-(element, face)
       // buffer (diagonal blocks, F).  Each tile row first runs all of its products, then
-      // stores with addresses chosen by selects: no branch splits a row, so the products of
-      // one row overlap the stores of the previous one.
-      constexpr int W = D2 * D2 + D2;
-      double* dwe = dws + (size_t)(4 * E) * W;
+      // stores whose block addresses come from the table built at set-up: no branch splits
+      // a row, so the products of one row overlap the stores of the previous one.
+      double* const* base = s_base[blk];
 #pragma unroll
       for (int I = 0; I < MT; ++I) {
         const int a = 4 * I + r, la = a / D2, ia = a % D2;
@@ -424,17 +431,12 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
           // lane (r, c) now holds the upper entry (a2, b2) = (4I + c, 4N + r), stored mirrored
           const double tv = tile_transpose(val[N]);
           const int a2 = 4 * I + c, b2 = 4 * N + r, la2 = a2 / D2, lb2 = b2 / D2;
-          // both slots are read whichever array is written, and kept opaque, so the compiler
-          // selects between the two addresses instead of branching around the reads
-          int sl1 = s_slot[blk][4 * la + lb], sl2 = s_slot[blk][4 * lb2 + la2];
-          asm volatile("" : "+v"(sl1), "+v"(sl2));
-          double* p1 = la == lb ? dwe + la * W + ia * D2 + ib : H + ((size_t)sl1 * D2 + ia) * D2 + ib;
-          double* p2 = la2 == lb2 ? dwe + la2 * W + (b2 % D2) * D2 + a2 % D2
-                                  : H + ((size_t)sl2 * D2 + b2 % D2) * D2 + a2 % D2;
+          double* p1 = base[4 * la + lb] + (ia * D2 + ib);
+          double* p2 = base[4 * lb2 + la2] + ((b2 % D2) * D2 + a2 % D2);
           if (I != N || r <= c) *p1 = val[N];
           if (I != N || c < r) *p2 = tv;
         }
-        if (c == 0) dwe[la * W + D2 * D2 + ia] = h;
+        if (c == 0) base[5 * la][D2 * D2 + ia] = h;
       }
     } else {
       // ---- C^K tiles and Cf^K, straight to H and F (or to the export arrays)
