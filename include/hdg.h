@@ -193,8 +193,10 @@ hdg_status hdg_face_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, const 
  *                                    (row-major blocks); exactly symmetric
  *   d_F       double [nfc][d2]       the assembled Cf (eq 6.5's F)
  *   d_factors double [nelt][factor_len]  per-element factors kept for hdg_recover:
- *                                    packed lower Cholesky factors of M_{1/kappa}
- *                                    and of the u-Schur complement, and f^K
+ *                                    the factors of M_{1/kappa} and of the u-Schur
+ *                                    complement, f^K, and (degrees 1..3) the element's
+ *                                    geometry record, so that hdg_recover does not
+ *                                    recompute it; opaque to the caller
  * Every block of H and every entry of F is written; off-diagonal blocks have one
  * contributing element, diagonal blocks and F entries at most two, summed in an
  * order-independent way, so results are bitwise reproducible.

@@ -32,38 +32,9 @@ struct TD {
   static constexpr int D3 = dim3(K), D2 = dim2(K), M = 4 * D2, NQD = (K + 2) * (K + 2) * (K + 2);
   static constexpr int T = (D3 + 3) / 4, MT = D2, QT = (NQD + 3) / 4;
   static constexpr int D3P4 = 4 * T, D2P4 = (D2 + 3) / 4 * 4, NQP = 4 * QT, NU = T * (T + 1) / 2;
-  static constexpr int FACTOR_LEN = (2 * NU + T) * 16;
+  // factor store: U^{-1}, Us^{-1} (packed upper tiles), f, then the geometry record
+  static constexpr int GEO_OFF = (2 * NU + T) * 16, FACTOR_LEN = GEO_OFF + G_REC;
 };
-
-enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_MU = 43, G_REC = kGeoRecord };
-static_assert(G_MU + 4 <= G_REC, "geometry record layout");
-
-// The geometry record of element E (E < 0: a reference element with no data), laid out as
-// above, perm - 1 stored as small integers in doubles.  No FMA contraction here or in
-// load_geometry, so that the records precomputed by k_geo_records and the ones computed
-// inline by the other forms of the condensation are the same bits.
-__device__ inline void tile_geo_record(int E, const hdg_mesh& mesh, const double* __restrict__ tau, double* rec) {
-#pragma clang fp contract(off)
-  ElemGeom g;
-  if (E >= 0) {
-    load_geometry(E, mesh, tau, g);
-  } else {
-    g = ElemGeom{};
-    g.vol = 1.0;
-    g.det = 6.0;
-  }
-  for (int i = 0; i < 9; ++i) rec[G_A + i] = g.a[i / 3][i % 3];
-  rec[G_DET] = g.det;
-  rec[G_VOL] = g.vol;
-  for (int i = 0; i < 12; ++i) rec[G_N + i] = g.n[i / 3][i % 3];
-  for (int l = 0; l < 4; ++l) {
-    rec[G_T + l] = g.T[l];
-    rec[G_MU + l] = (double)g.mu[l];
-    for (int m = 0; m < 4; ++m)
-      rec[G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
-  }
-  for (int i = G_MU + 4; i < G_REC; ++i) rec[i] = 0.0;
-}
 
 // One geometry record per element, for the workspace form of the condensation.
 __global__ void __launch_bounds__(256) k_geo_records(hdg_mesh mesh, const double* __restrict__ tau,
@@ -92,7 +63,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
   using D = TD<K>;
   constexpr int T = D::T, MT = D::MT, QT = D::QT, D3 = D::D3, D2 = D::D2, M = D::M;
   constexpr int NQD = D::NQD, NQP = D::NQP, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
-  __shared__ double s_w[3][4][NQP + 1];  // +1: the four elements' rows start in different banks
+  __shared__ __attribute__((aligned(16))) double s_w[3][4][NQP + 1];  // +1: rows start in different banks
   __shared__ double s_geo[4][G_REC];
   __shared__ int s_slot[4][16];
   // workspace form: the 16 block base addresses (l, m) of each element of the group, the H
@@ -101,7 +72,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
   __shared__ int s_fbe[4][4];
   __shared__ int s_E[4];
   __shared__ double s_x[64];
-  __shared__ double s_Z[T * MT][64];  // Z tiles, lane-contiguous
+  __shared__ __attribute__((aligned(16))) double s_Z[T * MT][64];  // Z tiles, lane-contiguous
   {
     // lane-derived indices are recomputed per group and kept opaque to the compiler, so
     // that the many table addresses derived from them are not hoisted out of this loop
@@ -371,6 +342,10 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       for (int i = 0; i < NU; ++i) fac[i * 16 + ent] = Ui[i];
 #pragma unroll
       for (int i = 0; i < T; ++i) fac[(2 * NU + i) * 16 + ent] = fa[i];
+      // the element's geometry record, for the reconstruction
+      static_assert(G_REC % 16 == 0, "geometry record in whole 16-lane rows");
+#pragma unroll
+      for (int j = 0; j < G_REC / 16; ++j) fac[D::GEO_OFF + 16 * j + ent] = geo[16 * j + ent];
     }
 
     // ---- Cholesky of S, Us^{-1}, and V = Ls^{-1} [B | f] (rows from the bottom, in place)

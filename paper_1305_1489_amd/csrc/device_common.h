@@ -136,4 +136,37 @@ __device__ __forceinline__ int batch_block(int xcd_remap) {
   return (b & 7) * (nb >> 3) + (b >> 3);
 }
 
+// Geometry record of one element, the layout shared by the tile condensation (which
+// precomputes it or keeps it in LDS, and stores it with the element's factors) and the
+// tile reconstruction (which reads it back).
+enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_MU = 43, G_REC = kGeoRecord };
+static_assert(G_MU + 4 <= G_REC, "geometry record layout");
+
+// The geometry record of element E (E < 0: a reference element with no data), laid out as
+// above, perm - 1 stored as small integers in doubles.  No FMA contraction here or in
+// load_geometry, so that the records precomputed by k_geo_records and the ones computed
+// inline by the other forms of the condensation are the same bits.
+__device__ inline void tile_geo_record(int E, const hdg_mesh& mesh, const double* __restrict__ tau, double* rec) {
+#pragma clang fp contract(off)
+  ElemGeom g;
+  if (E >= 0) {
+    load_geometry(E, mesh, tau, g);
+  } else {
+    g = ElemGeom{};
+    g.vol = 1.0;
+    g.det = 6.0;
+  }
+  for (int i = 0; i < 9; ++i) rec[G_A + i] = g.a[i / 3][i % 3];
+  rec[G_DET] = g.det;
+  rec[G_VOL] = g.vol;
+  for (int i = 0; i < 12; ++i) rec[G_N + i] = g.n[i / 3][i % 3];
+  for (int l = 0; l < 4; ++l) {
+    rec[G_T + l] = g.T[l];
+    rec[G_MU + l] = (double)g.mu[l];
+    for (int m = 0; m < 4; ++m)
+      rec[G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
+  }
+  for (int i = G_MU + 4; i < G_REC; ++i) rec[i] = 0.0;
+}
+
 }  // namespace hdg

@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
 }
 
 template <int K>
-__global__ void __launch_bounds__(64 * kSolveWaves) k_pp_solve(hdg_mesh mesh, Tables tb,
+__global__ void __launch_bounds__(64 * kSolveWaves, 2) k_pp_solve(hdg_mesh mesh, Tables tb,
                                                                const double* __restrict__ tau,
                                                                double* __restrict__ us) {
   using D = PD<K>;
@@ -278,7 +278,7 @@ hdg_status run_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const dou
   const int ncu = device_cu_count();
   const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kRhsWaves - 1) / kRhsWaves, ncu));
   k_pp_rhs<K><<<g1, 64 * kRhsWaves, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us);
-  const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kSolveWaves - 1) / kSolveWaves, 2 * ncu));
+  const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kSolveWaves - 1) / kSolveWaves, 3 * ncu));
   k_pp_solve<K><<<g2, 64 * kSolveWaves, 0, s>>>(*mesh, disc->dev, tau, us);
   HDG_CHECK_LAUNCH("k_pp_rhs / k_pp_solve");
   return HDG_OK;

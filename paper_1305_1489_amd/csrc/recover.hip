@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const 
   using Dm = Dims<K>;
   constexpr int D3 = Dm::D3, D2 = Dm::D2, NQD = Dm::NQD, D3P = Dm::D3P;
   constexpr int TT = (D3 + 3) / 4, NU = TT * (TT + 1) / 2;
-  constexpr int FLEN = TILE ? (2 * NU + TT) * 16 : D3 * (D3 + 1) + D3;
+  constexpr int FLEN = TILE ? (2 * NU + TT) * 16 + kGeoRecord : D3 * (D3 + 1) + D3;
   __shared__ RecoverSmem<K> sm;
   const int t = threadIdx.x, nt = blockDim.x;
   for (int E = blockIdx.x; E < mesh.nelt; E += gridDim.x) {
@@ -192,7 +192,8 @@ template <int K>
 struct RD {
   static constexpr int D3 = dim3(K), D2 = dim2(K), T = (D3 + 3) / 4, JT = (D2 + 3) / 4;
   static constexpr int NU = T * (T + 1) / 2, D3P4 = 4 * T, D2P4 = 4 * JT;
-  static constexpr int FLEN = (2 * NU + T) * 16;
+  // factor store of the tile condensation: U^{-1}, Us^{-1}, f, then the geometry record
+  static constexpr int GEO_OFF = (2 * NU + T) * 16, FLEN = GEO_OFF + kGeoRecord;
 };
 
 template <int T>
@@ -220,7 +221,7 @@ __device__ __forceinline__ void apply_U(const double (&UT)[T * (T + 1) / 2], con
 constexpr int kRecWaves = 4;
 
 template <int K>
-__global__ void __launch_bounds__(64 * kRecWaves) k_recover_tile(hdg_mesh mesh, Tables tb,
+__global__ void __launch_bounds__(64 * kRecWaves, 2) k_recover_tile(hdg_mesh mesh, Tables tb,
                                                                  const double* __restrict__ tau,
                                                                  const double* __restrict__ factors,
                                                                  const double* __restrict__ uhat,
@@ -229,42 +230,51 @@ __global__ void __launch_bounds__(64 * kRecWaves) k_recover_tile(hdg_mesh mesh, 
   using D = RD<K>;
   constexpr int D3 = D::D3, D2 = D::D2, T = D::T, JT = D::JT, NU = D::NU, D3P4 = D::D3P4, D2P4 = D::D2P4;
   constexpr int L3 = D3P4 * D3P4, LDP = 24 * D3P4 * D2P4;
-  // the DP and Chat tables, shared by the workgroup's wavefronts
-  __shared__ double s_dpt[LDP], s_cht[3 * L3];
-  for (int i = threadIdx.x; i < LDP; i += blockDim.x) s_dpt[i] = tb.DPT[i];
-  for (int i = threadIdx.x; i < 3 * L3; i += blockDim.x) s_cht[i] = tb.ChatT[i];
+  // the DP and Chat tables, shared by the workgroup's wavefronts, copied global->LDS
+  // asynchronously (1 KB per instruction, spread over the wavefronts)
+  __shared__ __attribute__((aligned(16))) double s_dpt[lds_stage_bytes<LDP>() / 8];
+  __shared__ __attribute__((aligned(16))) double s_cht[lds_stage_bytes<3 * L3>() / 8];
+  lds_stage_wg<LDP, kRecWaves>(tb.DPT, s_dpt, threadIdx.x >> 6, threadIdx.x & 63);
+  lds_stage_wg<3 * L3, kRecWaves>(tb.ChatT, s_cht, threadIdx.x >> 6, threadIdx.x & 63);
+  lds_stage_wait();
   __syncthreads();
-  // per-wavefront geometry (each wavefront runs its own loop, so only the wavefront syncs)
-  __shared__ double s_a_[kRecWaves][4][9], s_n_[kRecWaves][4][12], s_T_[kRecWaves][4][4];
-  __shared__ int s_mu_[kRecWaves][4][4], s_fbe_[kRecWaves][4][4], s_E_[kRecWaves][4];
+  // per-wavefront geometry records and face numbers (each wavefront runs its own loop, so
+  // only the wavefront syncs)
+  __shared__ double s_geo_[kRecWaves][4][kGeoRecord];
+  __shared__ int s_fbe_[kRecWaves][4][4];
   const int wave = threadIdx.x >> 6;
-  auto& s_a = s_a_[wave];
-  auto& s_n = s_n_[wave];
-  auto& s_T = s_T_[wave];
-  auto& s_mu = s_mu_[wave];
+  auto& s_geo = s_geo_[wave];
   auto& s_fbe = s_fbe_[wave];
-  auto& s_E = s_E_[wave];
   const int ngroups = (mesh.nelt + 3) / 4;
   for (int grp = blockIdx.x * kRecWaves + wave; grp < ngroups; grp += gridDim.x * kRecWaves) {
     int lane = threadIdx.x & 63;
     asm volatile("" : "+v"(lane));
-    const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
+    const int r = (lane >> 4) & 3, c = lane & 3, blk = (lane >> 2) & 3;
     wave_lds_sync();
-    if (lane < 4) {
-      const int E = 4 * grp + lane < mesh.nelt ? 4 * grp + lane : -1;
-      s_E[lane] = E;
-      ElemGeom g{};
-      if (E >= 0) load_geometry(E, mesh, tau, g);
-      for (int i = 0; i < 9; ++i) s_a[lane][i] = g.a[i / 3][i % 3];
-      for (int i = 0; i < 12; ++i) s_n[lane][i] = g.n[i / 3][i % 3];
-      for (int l = 0; l < 4; ++l) {
-        s_T[lane][l] = g.T[l];
-        s_mu[lane][l] = E >= 0 ? g.mu[l] : 0;
-        s_fbe[lane][l] = E >= 0 ? mesh.d_facebyele[4 * E + l] : 0;
+    {
+      // the geometry records, kept in the factor store by the condensation, and the face
+      // numbers: every load of the group is issued before any is used (indices clamped;
+      // padding slots of a ragged last group get zeros)
+      constexpr int GIT = 4 * kGeoRecord / 64;
+      static_assert(4 * kGeoRecord % 64 == 0, "geometry records in whole passes");
+      double gv[GIT];
+#pragma unroll
+      for (int j = 0; j < GIT; ++j) {
+        const int idx = lane + 64 * j, Ee = 4 * grp + idx / kGeoRecord;
+        gv[j] = factors[(Ee < mesh.nelt ? (size_t)Ee * D::FLEN : 0) + D::GEO_OFF + idx % kGeoRecord];
       }
+      const int ef = 4 * grp + ((lane >> 2) & 3);
+      const int fb = mesh.d_facebyele[4 * (size_t)(ef < mesh.nelt ? ef : 0) + (lane & 3)];
+#pragma unroll
+      for (int j = 0; j < GIT; ++j) {
+        const int idx = lane + 64 * j;
+        (&s_geo[0][0])[idx] = 4 * grp + idx / kGeoRecord < mesh.nelt ? gv[j] : 0.0;
+      }
+      if (lane < 16) s_fbe[lane >> 2][lane & 3] = ef < mesh.nelt ? fb : 0;
     }
     wave_lds_sync();
-    const int E = s_E[blk];
+    const int E = 4 * grp + blk < mesh.nelt ? 4 * grp + blk : -1;
+    const double* geo = s_geo[blk];
     const double* fa = factors + (size_t)(E >= 0 ? E : 0) * D::FLEN;  // padding lanes read element 0
     double Ui[NU], UiT[NU];
 #pragma unroll
@@ -282,14 +292,14 @@ __global__ void __launch_bounds__(64 * kRecWaves) k_recover_tile(hdg_mesh mesh, 
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int fbe = s_fbe[blk][l];
-      const double* dpt = s_dpt + (s_mu[blk][l] * 4 + l) * D3P4 * D2P4;
+      const double* dpt = s_dpt + ((int)geo[G_MU + l] * 4 + l) * D3P4 * D2P4;
       double uh[JT];
 #pragma unroll
       for (int J = 0; J < JT; ++J) {
         const int i = 4 * J + r;
         uh[J] = (E >= 0 && i < D2) ? uhat[(size_t)fbe * D2 + i] : 0.0;
       }
-      const double n0 = s_n[blk][3 * l], n1 = s_n[blk][3 * l + 1], n2 = s_n[blk][3 * l + 2], Tl = s_T[blk][l];
+      const double n0 = geo[G_N + 3 * l], n1 = geo[G_N + 3 * l + 1], n2 = geo[G_N + 3 * l + 2], Tl = geo[G_T + l];
 #pragma unroll
       for (int Kt = 0; Kt < T; ++Kt) {
         double t = 0.0;
@@ -301,7 +311,7 @@ __global__ void __launch_bounds__(64 * kRecWaves) k_recover_tile(hdg_mesh mesh, 
         ru[Kt] += Tl * t;
       }
     }
-    const double* a = s_a[blk];
+    const double* a = geo + G_A;
     // x_s = M^{-1} r_s, v_h = sum_s a_sh x_s, rhs += sum_h Chat^h v_h
     {
       double xs[3][T];

@@ -49,6 +49,18 @@ __device__ __forceinline__ void lds_stage(const double* __restrict__ src, double
 }
 template <int N>
 constexpr int lds_stage_bytes() { return (N * 8 + 1023) / 1024 * 1024; }
+// The same copy shared by the NW wavefronts of a workgroup (wavefront w issues copies
+// w, w + NW, ...); every wavefront awaits its own copies with lds_stage_wait() and the
+// workgroup then synchronises.
+template <int N, int NW>
+__device__ __forceinline__ void lds_stage_wg(const double* __restrict__ src, double* dst, int wave, int lane) {
+  static_assert(N % 2 == 0, "tables are staged in pairs of doubles");
+  constexpr int NI = (N * 8 + 1023) / 1024;
+  for (int i = wave; i < NI; i += NW) {
+    const int o = min(128 * i + 2 * lane, N - 2);
+    __builtin_amdgcn_global_load_lds(src + o, (__attribute__((address_space(3))) void*)(dst + 128 * i), 16, 0, 0);
+  }
+}
 __device__ __forceinline__ void lds_stage_wait() {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   wave_lds_sync();
