@@ -322,7 +322,7 @@ def main():
         L.hdg_recover(S.disc, S.mesh, S.kappa, S.tau, S.factors, uhat, q, u, postprocess=False)
         if ev is not None:
             ev[3].record(stream)
-        L.hdg_postprocess(S.disc, S.mesh, S.kappa, S.tau, q, u, us)
+        L.hdg_postprocess(S.disc, S.mesh, S.kappa, S.tau, q, u, us, factors=S.factors)
         if ev is not None:
             ev[4].record(stream)
 

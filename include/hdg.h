@@ -285,11 +285,15 @@ hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
  * runs it after the reconstruction; this entry runs it on given fields.
  *   d_kappa  double [nelt][nqd]     d_tau double [nelt][4] (geometry set-up only)
  *   d_q      double [nelt][3][d3]   d_u   double [nelt][d3]   (layouts of hdg_recover)
+ *   d_factors  the factor store of hdg_assemble_condense(_ws) for the same mesh and tau,
+ *            or NULL: for degrees 1..3 the element geometry is then read from it instead
+ *            of recomputed (same values); ignored for degrees 0 and 4
  * Output: d_ustar double [nelt][d3p].  Errors: HDG_ERR_INVALID_ARG (NULL array),
  * HDG_ERR_UNSUPPORTED_DEGREE, HDG_ERR_DEVICE.  Nothing is allocated.
  * ------------------------------------------------------------------------------ */
 hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_tau,
-                           const double* d_q, const double* d_u, double* d_ustar, void* stream);
+                           const double* d_q, const double* d_u, const double* d_factors, double* d_ustar,
+                           void* stream);
 
 /* Same results as hdg_assemble_condense, bit for bit, without atomics.  Each element's
  * contributions to its diagonal face blocks and to F go to the caller's workspace (one

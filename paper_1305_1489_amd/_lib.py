@@ -342,11 +342,12 @@ def hdg_recover(disc: Disc, mesh: Mesh, kappa, tau, factors, uhat, q=None, u=Non
     return q, u, (ustar if postprocess else None)
 
 
-def hdg_postprocess(disc: Disc, mesh: Mesh, kappa, tau, q, u, ustar=None, stream=None):
+def hdg_postprocess(disc: Disc, mesh: Mesh, kappa, tau, q, u, ustar=None, stream=None, factors=None):
+    """factors: the condensation's factor store (optional; the geometry is then read from it)."""
     if ustar is None:
         ustar = torch.empty((mesh.nelt, disc.d3p), dtype=torch.float64, device=mesh.device)
     _check(lib().hdg_postprocess(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(tau), _ptr(q), _ptr(u),
-                                 _ptr(ustar), _stream(stream)))
+                                 _ptr(factors), _ptr(ustar), _stream(stream)))
     return ustar
 
 

@@ -75,9 +75,25 @@ __device__ __forceinline__ PGeo pp_geometry(int E, const hdg_mesh& mesh, const d
   return p;
 }
 
+// Geometry of element E from the record the tile condensation keeps in its factor store
+// (fac: that store, degrees 1..3), else computed; the same bits either way.
+template <int K>
+__device__ __forceinline__ PGeo pp_geometry_any(int E, const hdg_mesh& mesh, const double* tau,
+                                                const double* __restrict__ fac) {
+  if (!fac || E < 0) return pp_geometry(E, mesh, tau);
+  constexpr int T = (dim3(K) + 3) / 4, NU = T * (T + 1) / 2, GEO_OFF = (2 * NU + T) * 16;
+  const double* rec = fac + (size_t)E * (GEO_OFF + kGeoRecord) + GEO_OFF;
+  PGeo p;
+  for (int i = 0; i < 9; ++i) p.a[i] = rec[G_A + i];
+  p.det = rec[G_DET];
+  p.vol = rec[G_VOL];
+  return p;
+}
+
 template <int K>
 __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                            const double* __restrict__ tau,
+                                                           const double* __restrict__ fac,
                                                            const double* __restrict__ qin,
                                                            const double* __restrict__ uin,
                                                            double* __restrict__ rhs_out) {
@@ -103,7 +119,7 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
     const int Em = 4 * grp + (lane & 3);
     const int Eown = Em < mesh.nelt ? Em : -1;
     PGeo gl{};
-    if (lane < 4) gl = pp_geometry(Eown, mesh, tau);
+    if (lane < 4) gl = pp_geometry_any<K>(Eown, mesh, tau, fac);
     // element c's geometry (lane c computed it)
     double a[9];
 #pragma unroll
@@ -190,6 +206,7 @@ __global__ void __launch_bounds__(64 * kRhsWaves) k_pp_rhs(hdg_mesh mesh, Tables
 template <int K>
 __global__ void __launch_bounds__(64 * kSolveWaves, 2) k_pp_solve(hdg_mesh mesh, Tables tb,
                                                                const double* __restrict__ tau,
+                                                               const double* __restrict__ fac,
                                                                double* __restrict__ us) {
   using D = PD<K>;
   constexpr int D3P = D::D3P, TS = D::TS, NUS = D::NUS;
@@ -206,7 +223,7 @@ __global__ void __launch_bounds__(64 * kSolveWaves, 2) k_pp_solve(hdg_mesh mesh,
     const int r = lane >> 4, c = lane & 3, blk = (lane >> 2) & 3;
     const int Em = 4 * grp + (lane & 3);
     PGeo gl{};
-    if (lane < 4) gl = pp_geometry(Em < mesh.nelt ? Em : -1, mesh, tau);
+    if (lane < 4) gl = pp_geometry_any<K>(Em < mesh.nelt ? Em : -1, mesh, tau, fac);
     const int Eb = 4 * grp + blk < mesh.nelt ? 4 * grp + blk : -1;
     // ---- S* = sum_p cf_p Shat_p on the upper tiles, identity on mode 0 and the padding
     double S[NUS];
@@ -273,13 +290,14 @@ __global__ void __launch_bounds__(64 * kSolveWaves, 2) k_pp_solve(hdg_mesh mesh,
 
 template <int K>
 hdg_status run_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
-                           const double* q, const double* u, double* us, hipStream_t s) {
+                           const double* q, const double* u, const double* factors, double* us, hipStream_t s) {
+  const double* fac = (K >= 1 && K <= 3) ? factors : nullptr;  // only the tile layouts carry the record
   const int64_t groups = (mesh->nelt + 3) / 4;
   const int ncu = device_cu_count();
   const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kRhsWaves - 1) / kRhsWaves, ncu));
-  k_pp_rhs<K><<<g1, 64 * kRhsWaves, 0, s>>>(*mesh, disc->dev, kappa, tau, q, u, us);
+  k_pp_rhs<K><<<g1, 64 * kRhsWaves, 0, s>>>(*mesh, disc->dev, kappa, tau, fac, q, u, us);
   const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kSolveWaves - 1) / kSolveWaves, 3 * ncu));
-  k_pp_solve<K><<<g2, 64 * kSolveWaves, 0, s>>>(*mesh, disc->dev, tau, us);
+  k_pp_solve<K><<<g2, 64 * kSolveWaves, 0, s>>>(*mesh, disc->dev, tau, fac, us);
   HDG_CHECK_LAUNCH("k_pp_rhs / k_pp_solve");
   return HDG_OK;
 }
@@ -290,14 +308,14 @@ hdg_status run_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const dou
 // recovered fields (layouts of hdg_recover).  us doubles as the right-hand side between
 // the two kernels.
 hdg_status launch_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
-                              const double* q, const double* u, double* us, hipStream_t s) {
+                              const double* q, const double* u, const double* factors, double* us, hipStream_t s) {
   if (mesh->nelt == 0) return HDG_OK;
   switch (disc->host.k) {
-    case 0: return run_postprocess<0>(disc, mesh, kappa, tau, q, u, us, s);
-    case 1: return run_postprocess<1>(disc, mesh, kappa, tau, q, u, us, s);
-    case 2: return run_postprocess<2>(disc, mesh, kappa, tau, q, u, us, s);
-    case 3: return run_postprocess<3>(disc, mesh, kappa, tau, q, u, us, s);
-    case 4: return run_postprocess<4>(disc, mesh, kappa, tau, q, u, us, s);
+    case 0: return run_postprocess<0>(disc, mesh, kappa, tau, q, u, factors, us, s);
+    case 1: return run_postprocess<1>(disc, mesh, kappa, tau, q, u, factors, us, s);
+    case 2: return run_postprocess<2>(disc, mesh, kappa, tau, q, u, factors, us, s);
+    case 3: return run_postprocess<3>(disc, mesh, kappa, tau, q, u, factors, us, s);
+    case 4: return run_postprocess<4>(disc, mesh, kappa, tau, q, u, factors, us, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover: unsupported degree");
 }
@@ -307,11 +325,11 @@ hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const cha
 }  // namespace hdg
 
 extern "C" hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
-                                      const double* d_tau, const double* d_q, const double* d_u, double* d_ustar,
-                                      void* stream) {
+                                      const double* d_tau, const double* d_q, const double* d_u,
+                                      const double* d_factors, double* d_ustar, void* stream) {
   hdg_status st = hdg::check_disc_mesh(disc, mesh, "hdg_postprocess");
   if (st) return st;
   if (!d_kappa || !d_tau || !d_q || !d_u || !d_ustar)
     return hdg::set_error(HDG_ERR_INVALID_ARG, "hdg_postprocess: NULL array");
-  return hdg::launch_postprocess(disc, mesh, d_kappa, d_tau, d_q, d_u, d_ustar, (hipStream_t)stream);
+  return hdg::launch_postprocess(disc, mesh, d_kappa, d_tau, d_q, d_u, d_factors, d_ustar, (hipStream_t)stream);
 }

@@ -19,7 +19,7 @@
 namespace hdg {
 
 hdg_status launch_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
-                              const double* q, const double* u, double* us, hipStream_t s);
+                              const double* q, const double* u, const double* factors, double* us, hipStream_t s);
 
 namespace {
 
@@ -401,7 +401,7 @@ hdg_status run_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
     k_recover<K, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
   }
   HDG_CHECK_LAUNCH("k_recover");
-  return us ? launch_postprocess(disc, mesh, kappa, tau, q, u, us, s) : HDG_OK;
+  return us ? launch_postprocess(disc, mesh, kappa, tau, q, u, factors, us, s) : HDG_OK;
 }
 
 }  // namespace

@@ -183,6 +183,11 @@ def test_postprocess_entry_on_oracle_fields(k):
     us = L.hdg_postprocess(S.disc, S.mesh, S.kappa, S.tau, q, u)
     torch.cuda.synchronize()
     assert rel(us.cpu().numpy(), out["ustar"]) < TOL
+    # with the factor store the geometry is read, not recomputed: the same bits
+    S.assemble()
+    us2 = L.hdg_postprocess(S.disc, S.mesh, S.kappa, S.tau, q, u, factors=S.factors)
+    torch.cuda.synchronize()
+    assert torch.equal(us2.view(torch.int64), us.view(torch.int64))
 
 
 # ----------------------------------------------------------------------------- whole pipeline
