@@ -296,14 +296,14 @@ hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const dou
                            void* stream);
 
 /* Same results as hdg_assemble_condense, bit for bit, without atomics.  Each element's
- * contributions to its diagonal face blocks and to F go to the caller's workspace (one
- * d2 x d2 block and d2 entries per (element, face)), and a second kernel sums the one or
- * two contributions of each face in a fixed order.  A first kernel writes each element's
- * geometry (48 doubles) into the workspace as well, so that the condensation loads it in
- * one pass.  Workspace: hdg_condense_workspace_size bytes = round_up(4 Nelt (d2^2 + d2) 8,
- * 256) + 384 Nelt, device memory owned by the caller, contents undefined on entry and
- * exit (0 for degrees 0 and 4, which always use the atomic scatter).  Errors: those of
- * hdg_assemble_condense, HDG_ERR_WORKSPACE. */
+ * contributions to its diagonal face blocks and to F go to the caller's workspace (the
+ * upper triangle of a d2 x d2 block and d2 entries per (element, face)), and a second
+ * kernel sums the one or two contributions of each face in a fixed order.  A first kernel
+ * writes each element's geometry (48 doubles) into the workspace as well, so that the
+ * condensation loads it in one pass.  Workspace: hdg_condense_workspace_size bytes =
+ * round_up(4 Nelt (d2 (d2 + 1) / 2 + d2) 8, 256) + 384 Nelt, device memory owned by the
+ * caller, contents undefined on entry and exit (0 for degrees 0 and 4, which always use
+ * the atomic scatter).  Errors: those of hdg_assemble_condense, HDG_ERR_WORKSPACE. */
 hdg_status hdg_condense_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes);
 hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                     const double* d_c, const double* d_f, const double* d_tau, double* d_H, double* d_F,

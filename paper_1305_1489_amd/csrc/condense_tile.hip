@@ -22,8 +22,6 @@
 // The factor store keeps U, Us (packed upper tiles) and f (tiles, column 0) per element.
 #include "tile.h"
 
-#include <type_traits>
-
 namespace hdg {
 namespace {
 
@@ -36,16 +34,18 @@ struct TD {
   static constexpr int GEO_OFF = (2 * NU + T) * 16, FACTOR_LEN = GEO_OFF + G_REC;
 };
 
-// One geometry record per element, for the workspace form of the condensation.
-__global__ void __launch_bounds__(256) k_geo_records(hdg_mesh mesh, const double* __restrict__ tau,
-                                                     double* __restrict__ rec) {
-  const int E = blockIdx.x * blockDim.x + threadIdx.x;
-  if (E >= mesh.nelt) return;
-  double r[G_REC];
-  tile_geo_record(E, mesh, tau, r);
-  double2* out = reinterpret_cast<double2*>(rec + (size_t)E * G_REC);
-#pragma unroll
-  for (int i = 0; i < G_REC / 2; ++i) out[i] = double2{r[2 * i], r[2 * i + 1]};
+// One geometry record per element, for the workspace form of the condensation: each
+// thread computes its element's record into LDS, then the workgroup writes the (contiguous)
+// records of its 64 elements with coalesced stores.
+__global__ void __launch_bounds__(64) k_geo_records(hdg_mesh mesh, const double* __restrict__ tau,
+                                                    double* __restrict__ rec) {
+  __shared__ double s_rec[64 * G_REC];
+  const int E0 = blockIdx.x * 64, E = E0 + threadIdx.x;
+  if (E < mesh.nelt) tile_geo_record(E, mesh, tau, s_rec + threadIdx.x * G_REC);
+  __syncthreads();
+  const int n = min(64, mesh.nelt - E0) * G_REC;
+  double* out = rec + (size_t)E0 * G_REC;
+  for (int i = threadIdx.x; i < n; i += 64) out[i] = s_rec[i];
 }
 
 // One group of four elements (w0 .. w0+3 of the work list) on one wavefront.  With DWS the
@@ -118,7 +118,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
       s_slot[lane >> 4][lane & 15] = sl;
       {
         const int l = (lane >> 2) & 3, m = lane & 3;
-        s_base[lane >> 4][lane & 15] = l == m ? dws + (size_t)(4 * elem(lane >> 4) + l) * (D2 * D2 + D2)
+        s_base[lane >> 4][lane & 15] = l == m ? dws + (size_t)(4 * elem(lane >> 4) + l) * ws_block(D2)
                                               : H + (size_t)sl * D2 * D2;
       }
       if (lane < 4) s_E[lane] = elem(lane);
@@ -406,12 +406,18 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
           // lane (r, c) now holds the upper entry (a2, b2) = (4I + c, 4N + r), stored mirrored
           const double tv = tile_transpose(val[N]);
           const int a2 = 4 * I + c, b2 = 4 * N + r, la2 = a2 / D2, lb2 = b2 / D2;
-          double* p1 = base[4 * la + lb] + (ia * D2 + ib);
-          double* p2 = base[4 * lb2 + la2] + ((b2 % D2) * D2 + a2 % D2);
+          const int ia2 = a2 % D2, ib2 = b2 % D2;
+          // off-diagonal blocks: row-major in H; the element's diagonal blocks: row-packed
+          // upper triangle in the workspace (the mirror of an upper entry lands on that
+          // same entry, written twice with one value)
+          const int o1 = la == lb ? ia * D2 - ia * (ia - 1) / 2 + (ib - ia) : ia * D2 + ib;
+          const int o2 = la2 == lb2 ? ia2 * D2 - ia2 * (ia2 - 1) / 2 + (ib2 - ia2) : ib2 * D2 + ia2;
+          double* p1 = base[4 * la + lb] + o1;
+          double* p2 = base[4 * lb2 + la2] + o2;
           if (I != N || r <= c) *p1 = val[N];
           if (I != N || c < r) *p2 = tv;
         }
-        if (c == 0) base[5 * la][D2 * D2 + ia] = h;
+        if (c == 0) base[5 * la][D2 * (D2 + 1) / 2 + ia] = h;
       }
     } else {
       // ---- C^K tiles and Cf^K, straight to H and F (or to the export arrays)
@@ -511,38 +517,35 @@ __global__ void k_zero_diag_t(const int* __restrict__ diag, int nfc, double* __r
 
 // H_ff (diagonal block) and F_f from the per-(element, face) contributions of the (one or
 // two) elements holding face f, in a fixed order; (0 + a) + b equals the atomic result.
-// P = 2 doubles per thread where d2 d2 is even (then every base is 16-byte aligned), else 1.
+// One packed entry per thread (contiguous reads of both contributions); an off-diagonal
+// entry of the block is written to both of its mirrored places.
 template <int D2>
 __global__ void k_diag_sum(const int* __restrict__ diag, const int* __restrict__ face_elem, int nfc,
                            const double* __restrict__ dws, double* __restrict__ H, double* __restrict__ F) {
-  constexpr int W = D2 * D2 + D2, P = (D2 * D2) % 2 == 0 ? 2 : 1, WP = W / P;
-  using V = typename std::conditional<P == 2, double2, double>::type;
+  constexpr int W = ws_block(D2), TRI = D2 * (D2 + 1) / 2;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nfc * WP) return;
-  const int f = (int)(i / WP);
-  const int e = P * (int)(i - (int64_t)f * WP);
+  if (i >= (int64_t)nfc * W) return;
+  const int f = (int)(i / W);
+  const int p = (int)(i - (int64_t)f * W);
   const int v0 = face_elem[2 * f], v1 = face_elem[2 * f + 1];
-  const V a = *reinterpret_cast<const V*>(dws + (size_t)v0 * W + e);
-  V v = a;
-  if constexpr (P == 2) {
-    v.x = 0.0 + a.x;
-    v.y = 0.0 + a.y;
+  double v = 0.0 + dws[(size_t)v0 * W + p];
+  if (v1 >= 0) v += dws[(size_t)v1 * W + p];
+  if (p < TRI) {
+    // packed (x, y), x <= y: rows x hold D2 - x entries
+    int x = 0, rem = p;
+#pragma unroll
+    for (int r = 0; r < D2 - 1; ++r)
+      if (rem >= D2 - x) {
+        rem -= D2 - x;
+        ++x;
+      }
+    const int y = x + rem;
+    double* blk = H + (size_t)diag[f] * D2 * D2;
+    blk[x * D2 + y] = v;
+    if (y != x) blk[y * D2 + x] = v;
   } else {
-    v = 0.0 + a;
+    F[(size_t)f * D2 + (p - TRI)] = v;
   }
-  if (v1 >= 0) {
-    const V b = *reinterpret_cast<const V*>(dws + (size_t)v1 * W + e);
-    if constexpr (P == 2) {
-      v.x += b.x;
-      v.y += b.y;
-    } else {
-      v += b;
-    }
-  }
-  if (e < D2 * D2)
-    *reinterpret_cast<V*>(H + (size_t)diag[f] * D2 * D2 + e) = v;
-  else
-    *reinterpret_cast<V*>(F + (size_t)f * D2 + (e - D2 * D2)) = v;
 }
 
 template <int K>
@@ -564,10 +567,10 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
                                                         (int)n, Cout, Cfout, lc.xcd_remap, nullptr, nullptr);
   } else if (dws) {
     double* geo_rec = reinterpret_cast<double*>(reinterpret_cast<char*>(dws) + condense_ws_geo_offset(D::D2, mesh->nelt));
-    k_geo_records<<<(unsigned)((mesh->nelt + 255) / 256), 256, 0, s>>>(*mesh, tau, geo_rec);
+    k_geo_records<<<(unsigned)((mesh->nelt + 63) / 64), 64, 0, s>>>(*mesh, tau, geo_rec);
     k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
                                                         (int)n, Cout, Cfout, lc.xcd_remap, dws, geo_rec);
-    const size_t tot = (size_t)mesh->nfc * (D::D2 * D::D2 + D::D2) / ((D::D2 * D::D2) % 2 == 0 ? 2 : 1);
+    const size_t tot = (size_t)mesh->nfc * ws_block(D::D2);
     k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
                                                                      dws, H, F);
   } else {

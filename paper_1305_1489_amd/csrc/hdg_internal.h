@@ -22,10 +22,15 @@ inline constexpr int tri(int n) { return n * (n + 1) / 2; }
 // workspace form): cofactors, det, |K|, normals, T_l, (n_l.n_m), perm, padding.
 constexpr int kGeoRecord = 48;
 
-// Byte layout of the workspace of hdg_assemble_condense_ws: the per-(element, face)
-// diagonal contributions, then the geometry records, each 256-byte aligned.
+// Doubles per (element, face) in the workspace of hdg_assemble_condense_ws: the upper
+// triangle of the element's diagonal block of C^K (row-packed: row x holds columns x..d2-1)
+// and its d2 entries of Cf^K.
+constexpr int ws_block(int d2) { return d2 * (d2 + 1) / 2 + d2; }
+
+// Byte layout of that workspace: the per-(element, face) contributions, then the geometry
+// records, each 256-byte aligned.
 inline size_t condense_ws_geo_offset(int d2, int64_t nelt) {
-  return ((size_t)4 * nelt * (d2 * d2 + d2) * sizeof(double) + 255) / 256 * 256;
+  return ((size_t)4 * nelt * ws_block(d2) * sizeof(double) + 255) / 256 * 256;
 }
 inline size_t condense_ws_bytes(int d2, int64_t nelt) {
   return condense_ws_geo_offset(d2, nelt) + (size_t)nelt * kGeoRecord * sizeof(double);

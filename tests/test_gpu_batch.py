@@ -161,9 +161,9 @@ def test_workspace_condensation_equals_atomic_scatter_bitwise():
             for i, S in enumerate(systems):
                 need = L.hdg_condense_workspace_size(S.disc, S.mesh)
                 d2 = S.disc.d2
-                # per-(element, face) blocks and F entries, 256-byte aligned, then 48-double
-                # geometry records per element
-                per_face = (4 * S.mesh.nelt * (d2 * d2 + d2) * 8 + 255) // 256 * 256
+                # per-(element, face) upper triangles and F entries, 256-byte aligned, then
+                # 48-double geometry records per element
+                per_face = (4 * S.mesh.nelt * (d2 * (d2 + 1) // 2 + d2) * 8 + 255) // 256 * 256
                 assert need == (per_face + 48 * 8 * S.mesh.nelt if 1 <= S.k <= 3 else 0)
                 H0, F0, X0 = L.hdg_assemble_condense(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau)
                 H1 = torch.full_like(H0, float("nan"))
