@@ -21,6 +21,62 @@
 namespace hdg {
 namespace {
 
+// Right-looking Cholesky in place on the lower triangle of the row-major N x N matrix A
+// (leading dimension ld), by the whole workgroup: pass j applies column j (still unscaled,
+// L_ij L_kj = A_ij A_kj / A_jj) to the trailing triangle and scales column j - 1, whose
+// last reader was the pass before, so each column costs one barrier.
+template <int N>
+__device__ inline void wg_cholesky(double* A, int ld) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  double prev = 1.0;  // pivot of column j - 1, read before anyone rescaled it
+  for (int j = 0; j < N; ++j) {
+    const double piv = A[j * ld + j];
+    const double ip = 1.0 / piv;
+    const int m = N - 1 - j;
+    for (int p = t; p < m * m; p += nt) {
+      const int i = j + 1 + p / m, k = j + 1 + p % m;
+      if (k <= i) A[i * ld + k] -= A[i * ld + j] * A[k * ld + j] * ip;
+    }
+    if (j > 0) {
+      const double d = sqrt(prev), id = 1.0 / d;
+      for (int i = j - 1 + t; i < N; i += nt) A[i * ld + j - 1] = i == j - 1 ? d : A[i * ld + j - 1] * id;
+    }
+    prev = piv;
+    __syncthreads();
+  }
+  const double d = sqrt(prev);
+  if (t == 0) A[(N - 1) * ld + N - 1] = d;
+  __syncthreads();
+}
+
+// X <- L^{-1} X for the columns of one or two row-major blocks of N rows (block b: nc[b]
+// columns; row r, column c at X[b] + (c / cs[b]) * ss[b] + r * ld[b] + c % cs[b], which
+// lets three stacked N x N blocks act as one), right-looking: pass k eliminates row k
+// (unscaled) from the rows below and scales row k - 1.  L lower triangular, factor diagonal.
+template <int N>
+__device__ inline void wg_forward(const double* L, int ldl, double* X0, int ld0, int nc0, int cs0, int ss0,
+                                  double* X1, int ld1, int nc1) {
+  const int t = threadIdx.x, nt = blockDim.x, nc = nc0 + nc1;
+  auto at = [&](int r, int c) -> double& {
+    return c < nc0 ? X0[(c / cs0) * ss0 + r * ld0 + c % cs0] : X1[r * ld1 + (c - nc0)];
+  };
+  double iprev = 1.0;
+  for (int k = 0; k < N; ++k) {
+    const double ik = 1.0 / L[k * ldl + k];
+    const int m = N - 1 - k;
+    for (int p = t; p < m * nc; p += nt) {
+      const int r = k + 1 + p / nc, c = p % nc;
+      at(r, c) -= L[r * ldl + k] * at(k, c) * ik;
+    }
+    if (k > 0)
+      for (int c = t; c < nc; c += nt) at(k - 1, c) *= iprev;
+    iprev = ik;
+    __syncthreads();
+  }
+  for (int c = t; c < nc; c += nt) at(N - 1, c) *= iprev;
+  __syncthreads();
+}
+
 template <int K>
 struct CondenseSmem {
   using Dm = Dims<K>;
@@ -58,21 +114,43 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
       sm.wf[q] = wq * fco[(size_t)E * NQD + q];
     }
     __syncthreads();
-    // ---- Gram matrices (upper triangle, mirrored) and the load vector
-    for (int idx = t; idx < D3 * D3; idx += nt) {
-      const int i = idx / D3, j = idx % D3;
-      if (j < i) continue;
-      double sk = 0, sc = 0;
-      for (int q = 0; q < NQD; ++q) {
-        const double pp = tb.P[q * D3 + i] * tb.P[q * D3 + j];
-        sk += sm.wk[q] * pp;
-        sc += sm.wc[q] * pp;
+    // ---- Gram matrices (upper triangle, mirrored) and the load vector.  The basis table
+    // is staged in LDS in chunks of points (in the Z / V / U space, free until the
+    // solves); one thread per upper pair (i, j), pairs numbered from the last row up.
+    {
+      constexpr int QC = (NQD + 1) / 2, NP = D3 * (D3 + 1) / 2;
+      static_assert(QC * D3 <= D3 * M + D3 * (M + 1) + D3 * D3, "basis chunk must fit the solve buffers");
+      double* sP = sm.Z;  // Z, V and U are consecutive
+      for (int q0 = 0; q0 < NQD; q0 += QC) {
+        const int nq = min(QC, NQD - q0);
+        for (int i = t; i < nq * D3; i += nt) sP[i] = tb.P[q0 * D3 + i];
+        __syncthreads();
+        for (int pp = t; pp < NP; pp += nt) {
+          const int kk = NP - 1 - pp;
+          int rr = (int)((sqrtf(8.0f * kk + 1.0f) - 1.0f) * 0.5f);
+          while (rr * (rr + 1) / 2 > kk) --rr;
+          while ((rr + 1) * (rr + 2) / 2 <= kk) ++rr;
+          const int i = D3 - 1 - rr, j = D3 - 1 - (kk - rr * (rr + 1) / 2);
+          double sk = 0, sc = 0;
+#pragma unroll 4
+          for (int q = 0; q < nq; ++q) {
+            const double pq = sP[q * D3 + i] * sP[q * D3 + j];
+            sk += sm.wk[q0 + q] * pq;
+            sc += sm.wc[q0 + q] * pq;
+          }
+          if (q0 == 0) {
+            for (int l = 0; l < 4; ++l) sc += g.T[l] * tb.PP[(l * D3 + i) * D3 + j];
+          } else {
+            sk += sm.L[i * D3 + j];
+            sc += sm.S[i * D3 + j];
+          }
+          sm.L[i * D3 + j] = sk;
+          sm.L[j * D3 + i] = sk;
+          sm.S[i * D3 + j] = sc;
+          sm.S[j * D3 + i] = sc;
+        }
+        __syncthreads();
       }
-      for (int l = 0; l < 4; ++l) sc += g.T[l] * tb.PP[(l * D3 + i) * D3 + j];
-      sm.L[i * D3 + j] = sk;
-      sm.L[j * D3 + i] = sk;
-      sm.S[i * D3 + j] = sc;
-      sm.S[j * D3 + i] = sc;
     }
     for (int i = t; i < D3; i += nt) {
       double s = 0;
@@ -92,18 +170,9 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
       sm.Z[idx] = tb.DP[((g.mu[l] * 4 + l) * D2 + i) * D3 + r];
     }
     __syncthreads();
-    lds_cholesky<D3>(sm.L, D3);
-    // W = L^{-1} C^T (3 D3 columns, viewed as a D3 x 3D3 matrix with column stride)
-    for (int c = t; c < 3 * D3; c += nt) {
-      double* X = sm.W + (c / D3) * D3 * D3 + (c % D3);
-      for (int r = 0; r < D3; ++r) {
-        double s = X[r * D3];
-        for (int k = 0; k < r; ++k) s -= sm.L[r * D3 + k] * X[k * D3];
-        X[r * D3] = s / sm.L[r * D3 + r];
-      }
-    }
-    lds_forward_cols<D3>(sm.L, D3, sm.Z, M, M);
-    __syncthreads();
+    wg_cholesky<D3>(sm.L, D3);
+    // W = L^{-1} C^T (three stacked D3 x D3 blocks) and Z = L^{-1} DP^T, in one sweep
+    wg_forward<D3>(sm.L, D3, sm.W, D3, 3 * D3, D3, D3 * D3, sm.Z, M, M);
     // ---- S += sum_s W_s^T W_s
     for (int idx = t; idx < D3 * D3; idx += nt) {
       const int i = idx / D3, j = idx % D3;
@@ -115,7 +184,7 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
       if (j != i) sm.S[j * D3 + i] += s;
     }
     __syncthreads();
-    lds_cholesky<D3>(sm.S, D3);
+    wg_cholesky<D3>(sm.S, D3);
     // ---- B_l = T_l DP_l^T + U_l^T Z_l with U_l = sum_s n_{l s} W_s
     for (int l = 0; l < 4; ++l) {
       for (int idx = t; idx < D3 * D3; idx += nt)
@@ -130,8 +199,7 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
       __syncthreads();
     }
     // ---- V = Ls^{-1} [B | f]
-    lds_forward_cols<D3>(sm.S, D3, sm.V, MV, MV);
-    __syncthreads();
+    wg_forward<D3>(sm.S, D3, sm.V, MV, MV, MV, 0, nullptr, 0, 0);
     // ---- C^K (upper triangle) and Cf^K; scatter or export
     for (int idx = t; idx < M * M; idx += nt) {
       const int a = idx / M, b = idx % M;
