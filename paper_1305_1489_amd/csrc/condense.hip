@@ -17,245 +17,390 @@
 // blocks have a single writer, diagonal blocks and F at most two (atomic adds onto zeros,
 // which are order-independent for two addends).
 #include "device_common.h"
+#include "tile.h"
 
 namespace hdg {
 namespace {
 
-// Right-looking Cholesky in place on the lower triangle of the row-major N x N matrix A
-// (leading dimension ld), by the whole workgroup: pass j applies column j (still unscaled,
-// L_ij L_kj = A_ij A_kj / A_jj) to the trailing triangle and scales column j - 1, whose
-// last reader was the pass before, so each column costs one barrier.
-template <int N>
-__device__ inline void wg_cholesky(double* A, int ld) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  double prev = 1.0;  // pivot of column j - 1, read before anyone rescaled it
-  for (int j = 0; j < N; ++j) {
-    const double piv = A[j * ld + j];
-    const double ip = 1.0 / piv;
-    const int m = N - 1 - j;
-    for (int p = t; p < m * m; p += nt) {
-      const int i = j + 1 + p / m, k = j + 1 + p % m;
-      if (k <= i) A[i * ld + k] -= A[i * ld + j] * A[k * ld + j] * ip;
-    }
-    if (j > 0) {
-      const double d = sqrt(prev), id = 1.0 / d;
-      for (int i = j - 1 + t; i < N; i += nt) A[i * ld + j - 1] = i == j - 1 ? d : A[i * ld + j - 1] * id;
-    }
-    prev = piv;
-    __syncthreads();
-  }
-  const double d = sqrt(prev);
-  if (t == 0) A[(N - 1) * ld + N - 1] = d;
-  __syncthreads();
+// Value of lane l (uniform) of v, for the whole wavefront.
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __hiloint2double(hi, lo);
 }
 
-// X <- L^{-1} X for the columns of one or two row-major blocks of N rows (block b: nc[b]
-// columns; row r, column c at X[b] + (c / cs[b]) * ss[b] + r * ld[b] + c % cs[b], which
-// lets three stacked N x N blocks act as one), right-looking: pass k eliminates row k
-// (unscaled) from the rows below and scales row k - 1.  L lower triangular, factor diagonal.
-template <int N>
-__device__ inline void wg_forward(const double* L, int ldl, double* X0, int ld0, int nc0, int cs0, int ss0,
-                                  double* X1, int ld1, int nc1) {
-  const int t = threadIdx.x, nt = blockDim.x, nc = nc0 + nc1;
-  auto at = [&](int r, int c) -> double& {
-    return c < nc0 ? X0[(c / cs0) * ss0 + r * ld0 + c % cs0] : X1[r * ld1 + (c - nc0)];
-  };
-  double iprev = 1.0;
-  for (int k = 0; k < N; ++k) {
-    const double ik = 1.0 / L[k * ldl + k];
-    const int m = N - 1 - k;
-    for (int p = t; p < m * nc; p += nt) {
-      const int r = k + 1 + p / nc, c = p % nc;
-      at(r, c) -= L[r * ldl + k] * at(k, c) * ik;
-    }
-    if (k > 0)
-      for (int c = t; c < nc; c += nt) at(k - 1, c) *= iprev;
-    iprev = ik;
-    __syncthreads();
-  }
-  for (int c = t; c < nc; c += nt) at(N - 1, c) *= iprev;
-  __syncthreads();
+// Upper pair (i <= j) of an n x n matrix from its index p in the row-major order of the
+// upper triangle (counted from the end, kk = r (r + 1) / 2 + s with r = n - 1 - i).
+__device__ __forceinline__ void upper_pair(int p, int n, int& i, int& j) {
+  const int kk = n * (n + 1) / 2 - 1 - p;
+  int r = (int)((sqrtf(8.0f * kk + 1.0f) - 1.0f) * 0.5f);
+  while (r * (r + 1) / 2 > kk) --r;
+  while ((r + 1) * (r + 2) / 2 <= kk) ++r;
+  i = n - 1 - r;
+  j = n - 1 - (kk - r * (r + 1) / 2);
 }
+
+// x . y over LD doubles (LD even, both 16-byte aligned; padding entries zero).
+template <int LD>
+__device__ __forceinline__ double lds_dot(const double* x, const double* y) {
+  double s0 = 0, s1 = 0;
+#pragma unroll 3
+  for (int p = 0; p < LD / 2; ++p) {
+    const double2 a = *reinterpret_cast<const double2*>(x + 2 * p);
+    const double2 b = *reinterpret_cast<const double2*>(y + 2 * p);
+    s0 = fma(a.x, b.x, s0);
+    s1 = fma(a.y, b.y, s1);
+  }
+  return s0 + s1;
+}
+
+// Cholesky factor (eq 5.1, eq 5.4) of the N x N SPD matrix whose upper triangle is
+// A[0] + ... + A[NP-1] (row-major, leading dimension LD; entry (i, k) kept at
+// [min(i, k)][max(i, k)]), by one wavefront: lane i holds row i in registers; pass j
+// broadcasts column j lane by lane, updates the trailing rows with the unscaled column
+// and then scales column j.  Writes L^T to Lt (Lt[k][i] = L[i][k] for k <= i) and the
+// reciprocal diagonal to idg.  Lt may alias A[0]: every lane has read its row before
+// any lane writes.
+template <int N, int LD, int NP>
+__device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], double* Lt, double* idg, int lane) {
+  const int i = min(lane, N - 1);
+  double a[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int o = k < i ? k * LD + i : i * LD + k;
+    double s = A[0][o];
+#pragma unroll
+    for (int p = 1; p < NP; ++p) s += A[p][o];
+    a[k] = s;
+    if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+  }
+  double myid = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double piv = lane_bcast(a[j], j);
+    const double id = pivot_rsqrt(piv);
+    const double t = a[j] * (id * id);
+#pragma unroll
+    for (int k = j + 1; k < N; ++k) {
+      a[k] = fma(-t, lane_bcast(a[j], k), a[k]);
+      if ((k - j) % 8 == 0) __builtin_amdgcn_sched_barrier(0);  // bounds the broadcasts in flight
+    }
+    a[j] = lane == j ? piv * id : a[j] * id;
+    if (lane == j) myid = id;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (lane < N) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      if (k <= lane) Lt[k * LD + lane] = a[k];
+    idg[lane] = myid;
+  }
+}
+
+// x <- L^{-1} x for one right-hand side in registers, L given by Lt = L^T (leading
+// dimension LD even, 16-byte aligned rows) and its reciprocal diagonal; column-oriented,
+// so the updates of one pass are independent, and every lane reads the same LDS words.
+template <int N, int LD>
+__device__ __forceinline__ void col_forward(const double* Lt, const double* idg, double (&x)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double xk = x[k] * idg[k];
+    x[k] = xk;
+#pragma unroll
+    for (int p = (k + 1) / 2; 2 * p < N; ++p) {
+      const double2 l = *reinterpret_cast<const double2*>(Lt + k * LD + 2 * p);
+      if (2 * p > k) x[2 * p] = fma(-l.x, xk, x[2 * p]);
+      if (2 * p + 1 < N) x[2 * p + 1] = fma(-l.y, xk, x[2 * p + 1]);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one row of L^T in registers at a time
+  }
+}
+
+template <int K>
+struct ElemLayout {
+  using Dm = Dims<K>;
+  static constexpr int D3 = Dm::D3, D2 = Dm::D2, M = Dm::M, NQD = Dm::NQD;
+  static constexpr int LD = (D3 + 1) & ~1;                       // padded length of every D3-vector
+  static constexpr int PLD = (D3 + 3) / 4 * 4, NQP = (NQD + 3) / 4 * 4;  // padded basis table
+  static constexpr int QS = 3;                                   // point slices of the Gram sums
+  static constexpr int NCOL = 3 * D3 + M;                        // right-hand sides C^T | DP^T
+  static constexpr int NB = LD / 2;                              // 2 x 2 blocks of the Gram matrices
+  // with D3 odd the last diagonal block holds one real entry, which the block beside it takes
+  static constexpr bool MERGE = (D3 % 2 == 1) && NB >= 2;
+  static constexpr int NBLK = NB * (NB + 1) / 2 - (MERGE ? 1 : 0);
+  static constexpr int BIG_SOLVE = (NCOL + M + 1) * LD;
+  static constexpr int BIG_STAGE = lds_stage_bytes<NQP * PLD>() / 8;
+  static constexpr int BIG = BIG_SOLVE > BIG_STAGE ? BIG_SOLVE : BIG_STAGE;
+};
 
 template <int K>
 struct CondenseSmem {
-  using Dm = Dims<K>;
-  double wk[Dm::NQD], wc[Dm::NQD], wf[Dm::NQD];
-  double L[Dm::D3 * Dm::D3];
-  double S[Dm::D3 * Dm::D3];
-  double W[3 * Dm::D3 * Dm::D3];
-  double Z[Dm::D3 * Dm::M];
-  double V[Dm::D3 * (Dm::M + 1)];  // B (then V) with the f column appended
-  double U[Dm::D3 * Dm::D3];
+  using Ly = ElemLayout<K>;
+  // the basis table at the points while the Gram matrices are summed, then one row per
+  // solved column: W_s^T (3 D3 rows), Z^T (M rows), V^T = (Ls^{-1} [B | f])^T (M + 1 rows)
+  double big[Ly::BIG];
+  double wkc[2 * Ly::NQD];  // (|K| w_q / kappa_q, |K| w_q c_q)
+  double wf[Ly::NQD];       // |K| w_q f_q
+  double Lt[Ly::LD * Ly::LD];  // Gram partial of the first slice (upper), then L^T
+  double St[Ly::LD * Ly::LD];  // likewise for S, then Ls^T
+  double Mp[Ly::QS - 1][Ly::LD * Ly::LD], Sp[Ly::QS - 1][Ly::LD * Ly::LD];
+  double fv[Ly::LD];
+  double idl[Ly::LD], ids[Ly::LD];
+  double gn[4][3], gT[4], ga[9];
+  int gmu[4], slot[16], fbe[4];
 };
 
-// Work item w (one element) on one wavefront.
-template <int K>
+// Work item w (one element) on one workgroup of NT threads.
+template <int K, int NT>
 __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tables& tb, const double* __restrict__ kappa,
                                                  const double* __restrict__ cco, const double* __restrict__ fco,
                                                  const double* __restrict__ tau, double* __restrict__ H,
                                                  double* __restrict__ F, double* __restrict__ factors,
                                                  const int* __restrict__ elems, int nwork, double* __restrict__ Cout,
                                                  double* __restrict__ Cfout, int w) {
-  using Dm = Dims<K>;
-  constexpr int D3 = Dm::D3, D2 = Dm::D2, M = Dm::M, NQD = Dm::NQD, MV = M + 1;
-  __shared__ CondenseSmem<K> sm;
-  const int t = threadIdx.x, nt = blockDim.x;
+  using Ly = ElemLayout<K>;
+  constexpr int D3 = Ly::D3, D2 = Ly::D2, M = Ly::M, NQD = Ly::NQD, LD = Ly::LD, PLD = Ly::PLD, QS = Ly::QS;
+  constexpr int NCOL = Ly::NCOL, NB = Ly::NB, NBLK = Ly::NBLK, NW = NT / 64, NTRI = D3 * (D3 + 1) / 2;
+  constexpr int QL = (NQD + QS - 1) / QS;
+  constexpr bool PREFETCH = false;
+  __shared__ __align__(16) CondenseSmem<K> sm;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int E = elems ? elems[w] : w;
+  if (E < 0 || E >= mesh.nelt) return;  // uniform across the block
+  double* Wt = sm.big;
+  double* Zt = sm.big + 3 * D3 * LD;
+  double* Vt = sm.big + NCOL * LD;
+  // ---- the basis table goes to LDS while the coefficients are formed
+  lds_stage_wg<Ly::NQP * PLD, NW>(tb.Pt, sm.big, wave, lane);
   {
-    const int E = elems ? elems[w] : w;
-    if (E < 0 || E >= mesh.nelt) return;  // uniform across the block
-    ElemGeom g;
-    load_geometry(E, mesh, tau, g);
-    // ---- coefficients at the quadrature points
-    for (int q = t; q < NQD; q += nt) {
-      double wq = g.vol * tb.vol_w[q];
-      sm.wk[q] = wq / kappa[(size_t)E * NQD + q];
-      sm.wc[q] = wq * cco[(size_t)E * NQD + q];
-      sm.wf[q] = wq * fco[(size_t)E * NQD + q];
+  ElemGeom g;
+  load_geometry(E, mesh, tau, g);
+  for (int q = t; q < NQD; q += NT) {
+    const double wq = g.vol * tb.vol_w[q];
+    sm.wkc[2 * q] = wq / kappa[(size_t)E * NQD + q];
+    sm.wkc[2 * q + 1] = wq * cco[(size_t)E * NQD + q];
+    sm.wf[q] = wq * fco[(size_t)E * NQD + q];
+  }
+  if (t < 16) sm.slot[t] = mesh.d_slot[16 * E + t];
+  if (t < 4) {
+    sm.fbe[t] = mesh.d_facebyele[4 * E + t];
+    sm.gT[t] = t == 0 ? g.T[0] : t == 1 ? g.T[1] : t == 2 ? g.T[2] : g.T[3];
+    sm.gmu[t] = t == 0 ? g.mu[0] : t == 1 ? g.mu[1] : t == 2 ? g.mu[2] : g.mu[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      sm.gn[t][d] = t == 0 ? g.n[0][d] : t == 1 ? g.n[1][d] : t == 2 ? g.n[2][d] : g.n[3][d];
+  }
+  if (t >= 64 - 9 && t < 64) {
+    const int e = t - (64 - 9);
+    double v = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) v = e == k ? g.a[k / 3][k % 3] : v;
+    sm.ga[e] = v;
+  }
+  }
+  lds_stage_wait();
+  __syncthreads();
+  // ---- right-hand-side columns C_s^T and DP_l^T (eq 5.2), fetched now and solved once L
+  // is known: column c < 3 D3 is (s, i) = (c / D3, c % D3), W_s[r][i] = sum_h a[s][h]
+  // Chat[h][i][r]; the others are (l, i), Z_l[r][i] = DP[mu_l][l][i][r]
+  double x[D3];
+  auto load_col = [&](int c) {
+    if (c < 3 * D3) {
+      const int s = c / D3, i = c % D3;
+      const double a0 = sm.ga[3 * s], a1 = sm.ga[3 * s + 1], a2 = sm.ga[3 * s + 2];
+      const double* c0 = tb.Chat + i * D3;
+#pragma unroll
+      for (int r = 0; r < D3; ++r) x[r] = a0 * c0[r];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < D3; ++r) x[r] = fma(a1, c0[D3 * D3 + r], x[r]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < D3; ++r) x[r] = fma(a2, c0[2 * D3 * D3 + r], x[r]);
+    } else {
+      const int l = (c - 3 * D3) / D2, i = (c - 3 * D3) % D2;
+      const double* dp = tb.DP + ((sm.gmu[l] * 4 + l) * D2 + i) * D3;
+#pragma unroll
+      for (int r = 0; r < D3; ++r) x[r] = dp[r];
     }
-    __syncthreads();
-    // ---- Gram matrices (upper triangle, mirrored) and the load vector.  The basis table
-    // is staged in LDS in chunks of points (in the Z / V / U space, free until the
-    // solves); one thread per upper pair (i, j), pairs numbered from the last row up.
-    {
-      constexpr int QC = (NQD + 1) / 2, NP = D3 * (D3 + 1) / 2;
-      static_assert(QC * D3 <= D3 * M + D3 * (M + 1) + D3 * D3, "basis chunk must fit the solve buffers");
-      double* sP = sm.Z;  // Z, V and U are consecutive
-      for (int q0 = 0; q0 < NQD; q0 += QC) {
-        const int nq = min(QC, NQD - q0);
-        for (int i = t; i < nq * D3; i += nt) sP[i] = tb.P[q0 * D3 + i];
-        __syncthreads();
-        for (int pp = t; pp < NP; pp += nt) {
-          const int kk = NP - 1 - pp;
-          int rr = (int)((sqrtf(8.0f * kk + 1.0f) - 1.0f) * 0.5f);
-          while (rr * (rr + 1) / 2 > kk) --rr;
-          while ((rr + 1) * (rr + 2) / 2 <= kk) ++rr;
-          const int i = D3 - 1 - rr, j = D3 - 1 - (kk - rr * (rr + 1) / 2);
-          double sk = 0, sc = 0;
-#pragma unroll 4
-          for (int q = 0; q < nq; ++q) {
-            const double pq = sP[q * D3 + i] * sP[q * D3 + j];
-            sk += sm.wk[q0 + q] * pq;
-            sc += sm.wc[q0 + q] * pq;
-          }
-          if (q0 == 0) {
-            for (int l = 0; l < 4; ++l) sc += g.T[l] * tb.PP[(l * D3 + i) * D3 + j];
-          } else {
-            sk += sm.L[i * D3 + j];
-            sc += sm.S[i * D3 + j];
-          }
-          sm.L[i * D3 + j] = sk;
-          sm.L[j * D3 + i] = sk;
-          sm.S[i * D3 + j] = sc;
-          sm.S[j * D3 + i] = sc;
-        }
-        __syncthreads();
+  };
+  auto store_col = [&](double* row) {
+#pragma unroll
+    for (int r = 0; r < LD; r += 2)
+      *reinterpret_cast<double2*>(row + r) = make_double2(x[r], r + 1 < D3 ? x[r + 1 < D3 ? r + 1 : 0] : 0.0);
+  };
+  if (PREFETCH && t < NCOL) load_col(t);
+  // ---- Gram matrices M = P^T diag(|K| w / kappa) P and Mc = P^T diag(|K| w c) P (eq 3.5,
+  // eq 4.5): one thread per 2 x 2 block of the upper triangle and slice of the points
+  for (int it = t; it < NBLK * QS; it += NT) {
+    const int blk = it % NBLK, sl = it / NBLK;
+    int bi = 0, rem = blk;
+    while (rem >= NB - bi) {
+      rem -= NB - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    const bool extra = Ly::MERGE && bi == NB - 2 && bj == NB - 1;
+    const int q0 = sl * QL, q1 = min(NQD, q0 + QL);
+    double k00 = 0, k01 = 0, k10 = 0, k11 = 0, c00 = 0, c01 = 0, c10 = 0, c11 = 0, ke = 0, ce = 0;
+    for (int q = q0; q < q1; ++q) {
+      const double2 wq = *reinterpret_cast<const double2*>(sm.wkc + 2 * q);
+      const double2 pi = *reinterpret_cast<const double2*>(sm.big + q * PLD + 2 * bi);
+      const double2 pj = *reinterpret_cast<const double2*>(sm.big + q * PLD + 2 * bj);
+      const double a0 = wq.x * pi.x, a1 = wq.x * pi.y, b0 = wq.y * pi.x, b1 = wq.y * pi.y;
+      k00 = fma(a0, pj.x, k00);
+      k01 = fma(a0, pj.y, k01);
+      k10 = fma(a1, pj.x, k10);
+      k11 = fma(a1, pj.y, k11);
+      c00 = fma(b0, pj.x, c00);
+      c01 = fma(b0, pj.y, c01);
+      c10 = fma(b1, pj.x, c10);
+      c11 = fma(b1, pj.y, c11);
+      if (extra) {
+        const double e2 = pj.x * pj.x;
+        ke = fma(wq.x, e2, ke);
+        ce = fma(wq.y, e2, ce);
       }
     }
-    for (int i = t; i < D3; i += nt) {
+    double* mk = sl == 0 ? sm.Lt : sm.Mp[sl - 1];
+    double* mc = sl == 0 ? sm.St : sm.Sp[sl - 1];
+    const int o = 2 * bi * LD + 2 * bj;
+    mk[o] = k00, mk[o + 1] = k01, mk[o + LD] = k10, mk[o + LD + 1] = k11;
+    mc[o] = c00, mc[o + 1] = c01, mc[o + LD] = c10, mc[o + LD + 1] = c11;
+    if (extra) {
+      mk[(D3 - 1) * LD + D3 - 1] = ke;
+      mc[(D3 - 1) * LD + D3 - 1] = ce;
+    }
+  }
+  __syncthreads();
+  double* fa = factors ? factors + (size_t)E * (D3 * (D3 + 1) + D3) : nullptr;
+  // ---- L (one wavefront) while the columns arrive; the load vector f from the staged table
+  if (wave == NW - 1) {
+    const double* const parts[QS] = {sm.Lt, sm.Mp[0], sm.Mp[1]};
+    wave_cholesky<D3, LD, QS>(parts, sm.Lt, sm.idl, lane);
+  }
+  {
+    const int fi = (NW > 1 ? NT - 65 : NT - 1) - t;
+    if (fi >= 0 && fi < LD) {
       double s = 0;
-      for (int q = 0; q < NQD; ++q) s += sm.wf[q] * tb.P[q * D3 + i];
-      sm.V[i * MV + M] = s;  // f in the last column of V
+      if (fi < D3)
+        for (int q = 0; q < NQD; ++q) s = fma(sm.wf[q], sm.big[q * PLD + fi], s);
+      sm.fv[fi] = s;
+      if (fa && fi < D3) fa[D3 * (D3 + 1) + fi] = s;
     }
-    // ---- W_s = C_s^T (before the solve): W[s][r][i] = sum_h a[s][h] Chat[h][i][r]
-    for (int idx = t; idx < 3 * D3 * D3; idx += nt) {
-      const int s = idx / (D3 * D3), r = (idx / D3) % D3, i = idx % D3;
-      double v = 0;
-      for (int h = 0; h < 3; ++h) v += g.a[s][h] * tb.Chat[(h * D3 + i) * D3 + r];
-      sm.W[idx] = v;
+  }
+  __syncthreads();
+  // ---- W_s = L^{-1} C_s^T, Z = L^{-1} DP^T (eq 5.2), one column per thread
+  if (PREFETCH) {
+    if (t < NCOL) {
+      col_forward<D3, LD>(sm.Lt, sm.idl, x);
+      store_col(sm.big + t * LD);
     }
-    // ---- Z_l = DP_l^T (before the solve)
-    for (int idx = t; idx < D3 * M; idx += nt) {
-      const int r = idx / M, c = idx % M, l = c / D2, i = c % D2;
-      sm.Z[idx] = tb.DP[((g.mu[l] * 4 + l) * D2 + i) * D3 + r];
+  } else {
+    for (int c = t; c < NCOL; c += NT) {
+      load_col(c);
+      col_forward<D3, LD>(sm.Lt, sm.idl, x);
+      store_col(sm.big + c * LD);
     }
-    __syncthreads();
-    wg_cholesky<D3>(sm.L, D3);
-    // W = L^{-1} C^T (three stacked D3 x D3 blocks) and Z = L^{-1} DP^T, in one sweep
-    wg_forward<D3>(sm.L, D3, sm.W, D3, 3 * D3, D3, D3 * D3, sm.Z, M, M);
-    // ---- S += sum_s W_s^T W_s
-    for (int idx = t; idx < D3 * D3; idx += nt) {
-      const int i = idx / D3, j = idx % D3;
-      if (j < i) continue;
-      double s = 0;
-      for (int c = 0; c < 3; ++c)
-        for (int r = 0; r < D3; ++r) s += sm.W[(c * D3 + r) * D3 + i] * sm.W[(c * D3 + r) * D3 + j];
-      sm.S[i * D3 + j] += s;
-      if (j != i) sm.S[j * D3 + i] += s;
+  }
+  if (fa)
+    for (int p = NT - 1 - t; p < NTRI; p += NT) {
+      int i, j;
+      upper_pair(p, D3, i, j);  // (i, j) with i <= j: L[j][i]
+      fa[j * (j + 1) / 2 + i] = sm.Lt[i * LD + j];
     }
-    __syncthreads();
-    wg_cholesky<D3>(sm.S, D3);
-    // ---- B_l = T_l DP_l^T + U_l^T Z_l with U_l = sum_s n_{l s} W_s
-    for (int l = 0; l < 4; ++l) {
-      for (int idx = t; idx < D3 * D3; idx += nt)
-        sm.U[idx] = g.n[l][0] * sm.W[idx] + g.n[l][1] * sm.W[D3 * D3 + idx] + g.n[l][2] * sm.W[2 * D3 * D3 + idx];
-      __syncthreads();
-      for (int idx = t; idx < D3 * D2; idx += nt) {
-        const int i = idx / D2, c = l * D2 + idx % D2;
-        double s = g.T[l] * tb.DP[((g.mu[l] * 4 + l) * D2 + (idx % D2)) * D3 + i];
-        for (int r = 0; r < D3; ++r) s += sm.U[r * D3 + i] * sm.Z[r * M + c];
-        sm.V[i * MV + c] = s;
-      }
-      __syncthreads();
+  __syncthreads();
+  // ---- S = Mc + sum_l tau_l |e_l| PP_l + sum_s W_s^T W_s (eq 5.3), upper triangle
+  for (int p = t; p < NTRI; p += NT) {
+    int i, j;
+    upper_pair(p, D3, i, j);
+    const int o = i * LD + j;
+    double pp[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) pp[l] = tb.PPt[(l * PLD + i) * PLD + j];
+    double s = sm.St[o];
+#pragma unroll
+    for (int k = 0; k < QS - 1; ++k) s += sm.Sp[k][o];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) s = fma(sm.gT[l], pp[l], s);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s += lds_dot<LD>(Wt + (c * D3 + i) * LD, Wt + (c * D3 + j) * LD);
+    sm.St[o] = s;
+  }
+  __syncthreads();
+  // ---- Ls (one wavefront) while the others form B_l = T_l DP_l^T + U_l^T Z_l with
+  // U_l = sum_s n_{l s} W_s (eq 5.5), stored as rows of V^T
+  if (wave == NW - 1) {
+    const double* const parts[1] = {sm.St};
+    wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, lane);
+  }
+  if (NW == 1 || wave < NW - 1) {
+    constexpr int NBT = NW == 1 ? NT : NT - 64;
+    for (int p = t; p < M * D3; p += NBT) {
+      const int c = p / D3, i = p % D3, l = c / D2, ic = c % D2;
+      const double dp = tb.DP[((sm.gmu[l] * 4 + l) * D2 + ic) * D3 + i];
+      double s = sm.gT[l] * dp;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = fma(sm.gn[l][k], lds_dot<LD>(Wt + (k * D3 + i) * LD, Zt + c * LD), s);
+      Vt[c * LD + i] = s;
     }
-    // ---- V = Ls^{-1} [B | f]
-    wg_forward<D3>(sm.S, D3, sm.V, MV, MV, MV, 0, nullptr, 0, 0);
-    // ---- C^K (upper triangle) and Cf^K; scatter or export
-    for (int idx = t; idx < M * M; idx += nt) {
-      const int a = idx / M, b = idx % M;
-      if (b < a) continue;
-      const int la = a / D2, lb = b / D2, ia = a % D2, ib = b % D2;
-      double zz = 0, vv = 0;
-      for (int r = 0; r < D3; ++r) {
-        zz += sm.Z[r * M + a] * sm.Z[r * M + b];
-        vv += sm.V[r * MV + a] * sm.V[r * MV + b];
-      }
-      const double nn = g.n[la][0] * g.n[lb][0] + g.n[la][1] * g.n[lb][1] + g.n[la][2] * g.n[lb][2];
-      double c = nn * zz - vv;
-      if (a == b) c += g.T[la];
-      if (Cout) {
-        Cout[((size_t)w * M + a) * M + b] = c;
-        Cout[((size_t)w * M + b) * M + a] = c;
-      } else {
-        const size_t s1 = mesh.d_slot[16 * E + 4 * la + lb];
-        if (la == lb) {
-          unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], c);
-          if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], c);
-        } else {
-          const size_t s2 = mesh.d_slot[16 * E + 4 * lb + la];
-          H[(s1 * D2 + ia) * D2 + ib] = c;
-          H[(s2 * D2 + ib) * D2 + ia] = c;
-        }
-      }
+  }
+  __syncthreads();
+  // ---- V = Ls^{-1} [B | f] (eq 5.6), one column per thread; the packed factor Ls
+  for (int c = t; c < M + 1; c += NT) {
+    const double* src = c < M ? Vt + c * LD : sm.fv;
+#pragma unroll
+    for (int r = 0; r < D3; ++r) x[r] = src[r];
+    col_forward<D3, LD>(sm.St, sm.ids, x);
+    store_col(Vt + c * LD);
+  }
+  if (fa)
+    for (int p = NT - 1 - t; p < NTRI; p += NT) {
+      int i, j;
+      upper_pair(p, D3, i, j);
+      fa[D3 * (D3 + 1) / 2 + j * (j + 1) / 2 + i] = sm.St[i * LD + j];
     }
-    for (int a = t; a < M; a += nt) {
-      double s = 0;
-      for (int r = 0; r < D3; ++r) s += sm.V[r * MV + a] * sm.V[r * MV + M];
+  __syncthreads();
+  // ---- C^K = tau DD + (n.n) Z^T Z - V^T V (upper triangle) and Cf^K = V^T (Ls^{-1} f)
+  // (eq 5.6); scattered into H and F, or exported
+  constexpr int NPAIR = M * (M + 1) / 2;
+  for (int p = t; p < NPAIR + M; p += NT) {
+    if (p >= NPAIR) {
+      const int a = p - NPAIR;
+      const double s = lds_dot<LD>(Vt + a * LD, Vt + M * LD);
       if (Cfout) {
         Cfout[(size_t)w * M + a] = s;
       } else {
         const int la = a / D2, ia = a % D2;
-        unsafeAtomicAdd(&F[(size_t)mesh.d_facebyele[4 * E + la] * D2 + ia], s);
+        unsafeAtomicAdd(&F[(size_t)sm.fbe[la] * D2 + ia], s);
+      }
+      continue;
+    }
+    int a, b;
+    upper_pair(p, M, a, b);
+    const int la = a / D2, lb = b / D2, ia = a % D2, ib = b % D2;
+    const double zz = lds_dot<LD>(Zt + a * LD, Zt + b * LD);
+    const double vv = lds_dot<LD>(Vt + a * LD, Vt + b * LD);
+    const double nn = sm.gn[la][0] * sm.gn[lb][0] + sm.gn[la][1] * sm.gn[lb][1] + sm.gn[la][2] * sm.gn[lb][2];
+    double c = nn * zz - vv;
+    if (a == b) c += sm.gT[la];
+    if (Cout) {
+      Cout[((size_t)w * M + a) * M + b] = c;
+      Cout[((size_t)w * M + b) * M + a] = c;
+    } else {
+      const size_t s1 = sm.slot[4 * la + lb];
+      if (la == lb) {
+        unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], c);
+        if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], c);
+      } else {
+        const size_t s2 = sm.slot[4 * lb + la];
+        H[(s1 * D2 + ia) * D2 + ib] = c;
+        H[(s2 * D2 + ib) * D2 + ia] = c;
       }
     }
-    // ---- factors kept for the reconstruction: packed L, packed Ls, f
-    if (factors) {
-      double* fa = factors + (size_t)E * (D3 * (D3 + 1) + D3);
-      for (int idx = t; idx < D3 * D3; idx += nt) {
-        const int i = idx / D3, j = idx % D3;
-        if (j > i) continue;
-        fa[i * (i + 1) / 2 + j] = sm.L[idx];
-        fa[D3 * (D3 + 1) / 2 + i * (i + 1) / 2 + j] = sm.S[idx];
-      }
-      // f itself (the solve above overwrote it by Ls^{-1} f): recompute it
-      for (int i = t; i < D3; i += nt) {
-        double s = 0;
-        for (int q = 0; q < NQD; ++q) s += sm.wf[q] * tb.P[q * D3 + i];
-        fa[D3 * (D3 + 1) + i] = s;
-      }
-    }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // EXPORT selects the debugging form (listed elements, C^K and Cf^K written out instead of
@@ -268,7 +413,7 @@ __global__ void __launch_bounds__(NT) k_condense(hdg_mesh mesh, Tables tb, const
                                                  const int* __restrict__ elems, int nwork, double* __restrict__ Cout,
                                                  double* __restrict__ Cfout, int xcd_remap) {
   for (int w = batch_block(xcd_remap); w < nwork; w += gridDim.x)
-    condense_element<K>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
+    condense_element<K, NT>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
                         EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w);
 }
 
@@ -278,7 +423,7 @@ __global__ void __launch_bounds__(NT) k_batch_condense(const BatchItem* __restri
                                                        Tables tb, int xcd_remap) {
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
-    condense_element<K>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
+    condense_element<K, NT>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
                         (int)it->mesh.nelt, nullptr, nullptr, u - it->unit_begin);
   }
 }
