@@ -58,12 +58,14 @@ __device__ __forceinline__ double lds_dot(const double* x, const double* y) {
 // Cholesky factor (eq 5.1, eq 5.4) of the N x N SPD matrix whose upper triangle is
 // A[0] + ... + A[NP-1] (row-major, leading dimension LD; entry (i, k) kept at
 // [min(i, k)][max(i, k)]), by one wavefront: lane i holds row i in registers; pass j
-// broadcasts column j lane by lane, updates the trailing rows with the unscaled column
-// and then scales column j.  Writes L^T to Lt (Lt[k][i] = L[i][k] for k <= i) and the
-// reciprocal diagonal to idg.  Lt may alias A[0]: every lane has read its row before
-// any lane writes.
+// updates the trailing rows with the unscaled column j, which the lanes publish through
+// bc (two buffers of 64 doubles, alternating; column j + 1 is updated and published first,
+// so its round trip through LDS overlaps the rest of pass j), and then scales column j.
+// Writes L^T to Lt (Lt[k][i] = L[i][k] for k <= i) and the reciprocal diagonal to idg.
+// Lt may alias A[0]: every lane has read its row before any lane writes.
 template <int N, int LD, int NP>
-__device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], double* Lt, double* idg, int lane) {
+__device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], double* Lt, double* idg, double* bc,
+                                              int lane) {
   const int i = min(lane, N - 1);
   double a[N];
 #pragma unroll
@@ -147,6 +149,7 @@ struct CondenseSmem {
   double Mp[Ly::QS - 1][Ly::LD * Ly::LD], Sp[Ly::QS - 1][Ly::LD * Ly::LD];
   double fv[Ly::LD];
   double idl[Ly::LD], ids[Ly::LD];
+  double bc[128];  // column broadcast of the one-wavefront Cholesky
   double gn[4][3], gT[4], ga[9];
   int gmu[4], slot[16], fbe[4];
 };
@@ -165,7 +168,12 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   constexpr int QL = (NQD + QS - 1) / QS;
   constexpr bool PREFETCH = false;
   __shared__ __align__(16) CondenseSmem<K> sm;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // the thread index passes through an opaque move, so the per-thread offsets and masks
+  // derived from it are formed where they are used instead of being hoisted out of the
+  // persistent element loop, where they would stay live across every phase
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  const int lane = t & 63, wave = t >> 6;
   const int E = elems ? elems[w] : w;
   if (E < 0 || E >= mesh.nelt) return;  // uniform across the block
   double* Wt = sm.big;
@@ -278,7 +286,7 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   // ---- L (one wavefront) while the columns arrive; the load vector f from the staged table
   if (wave == NW - 1) {
     const double* const parts[QS] = {sm.Lt, sm.Mp[0], sm.Mp[1]};
-    wave_cholesky<D3, LD, QS>(parts, sm.Lt, sm.idl, lane);
+    wave_cholesky<D3, LD, QS>(parts, sm.Lt, sm.idl, sm.bc, lane);
   }
   {
     const int fi = (NW > 1 ? NT - 65 : NT - 1) - t;
@@ -333,7 +341,7 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   // U_l = sum_s n_{l s} W_s (eq 5.5), stored as rows of V^T
   if (wave == NW - 1) {
     const double* const parts[1] = {sm.St};
-    wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, lane);
+    wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, sm.bc, lane);
   }
   if (NW == 1 || wave < NW - 1) {
     constexpr int NBT = NW == 1 ? NT : NT - 64;
