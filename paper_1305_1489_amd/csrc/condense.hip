@@ -78,18 +78,25 @@ __device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], doub
     if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
   }
   double myid = 0;
+  double piv = lane_bcast(a[0], 0), id = pivot_rsqrt(piv);
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const double piv = lane_bcast(a[j], j);
-    const double id = pivot_rsqrt(piv);
     const double t = a[j] * (id * id);
+    double pn = 1.0, idn = 1.0;
+    if (j + 1 < N) {  // column j + 1 first, so the next pivot's square root overlaps this pass
+      a[j + 1] = fma(-t, lane_bcast(a[j], j + 1), a[j + 1]);
+      pn = lane_bcast(a[j + 1], j + 1);
+      idn = pivot_rsqrt(pn);
+    }
 #pragma unroll
-    for (int k = j + 1; k < N; ++k) {
+    for (int k = j + 2; k < N; ++k) {
       a[k] = fma(-t, lane_bcast(a[j], k), a[k]);
       if ((k - j) % 8 == 0) __builtin_amdgcn_sched_barrier(0);  // bounds the broadcasts in flight
     }
     a[j] = lane == j ? piv * id : a[j] * id;
     if (lane == j) myid = id;
+    piv = pn;
+    id = idn;
     __builtin_amdgcn_sched_barrier(0);
   }
   if (lane < N) {
@@ -344,14 +351,35 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
     wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, sm.bc, lane);
   }
   if (NW == 1 || wave < NW - 1) {
-    constexpr int NBT = NW == 1 ? NT : NT - 64;
-    for (int p = t; p < M * D3; p += NBT) {
-      const int c = p / D3, i = p % D3, l = c / D2, ic = c % D2;
-      const double dp = tb.DP[((sm.gmu[l] * 4 + l) * D2 + ic) * D3 + i];
-      double s = sm.gT[l] * dp;
+    // thread item (i, g): row i of B for the BC columns 5 g .. of one face, so the row
+    // U_l[.][i] = sum_s n_{l s} W_s[.][i] is formed once for all of them
+    constexpr int NBT = NW == 1 ? NT : NT - 64, BC = D2 % 5 == 0 ? 5 : 1, NG = M / BC;
+    for (int p = t; p < NG * D3; p += NBT) {
+      const int g = p / D3, i = p % D3, c0 = g * BC, l = c0 / D2;
+      const double n0 = sm.gn[l][0], n1 = sm.gn[l][1], n2 = sm.gn[l][2];
+      double dp[BC];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s = fma(sm.gn[l][k], lds_dot<LD>(Wt + (k * D3 + i) * LD, Zt + c * LD), s);
-      Vt[c * LD + i] = s;
+      for (int b = 0; b < BC; ++b) dp[b] = tb.DP[((sm.gmu[l] * 4 + l) * D2 + (c0 + b) % D2) * D3 + i];
+      double acc[BC][2] = {};
+      const double* w0 = Wt + i * LD;
+      const double* w1 = Wt + (D3 + i) * LD;
+      const double* w2 = Wt + (2 * D3 + i) * LD;
+#pragma unroll 2
+      for (int r = 0; r < LD; r += 2) {
+        const double2 x0 = *reinterpret_cast<const double2*>(w0 + r);
+        const double2 x1 = *reinterpret_cast<const double2*>(w1 + r);
+        const double2 x2 = *reinterpret_cast<const double2*>(w2 + r);
+        const double ux = fma(n2, x2.x, fma(n1, x1.x, n0 * x0.x));
+        const double uy = fma(n2, x2.y, fma(n1, x1.y, n0 * x0.y));
+#pragma unroll
+        for (int b = 0; b < BC; ++b) {
+          const double2 z = *reinterpret_cast<const double2*>(Zt + (c0 + b) * LD + r);
+          acc[b][0] = fma(ux, z.x, acc[b][0]);
+          acc[b][1] = fma(uy, z.y, acc[b][1]);
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < BC; ++b) Vt[(c0 + b) * LD + i] = fma(sm.gT[l], dp[b], acc[b][0] + acc[b][1]);
     }
   }
   __syncthreads();
@@ -372,40 +400,75 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   __syncthreads();
   // ---- C^K = tau DD + (n.n) Z^T Z - V^T V (upper triangle) and Cf^K = V^T (Ls^{-1} f)
   // (eq 5.6); scattered into H and F, or exported
-  constexpr int NPAIR = M * (M + 1) / 2;
-  for (int p = t; p < NPAIR + M; p += NT) {
-    if (p >= NPAIR) {
-      const int a = p - NPAIR;
-      const double s = lds_dot<LD>(Vt + a * LD, Vt + M * LD);
-      if (Cfout) {
-        Cfout[(size_t)w * M + a] = s;
+  {
+    constexpr int NBM = M / 2, NBP = NBM * (NBM + 1) / 2;  // 2 x 2 blocks of the upper triangle
+    static_assert(M % 2 == 0, "face blocks pair up");
+    auto emit = [&](int a, int b, double c) {
+      const int la = a / D2, lb = b / D2, ia = a % D2, ib = b % D2;
+      if (a == b) c += sm.gT[la];
+      if (Cout) {
+        Cout[((size_t)w * M + a) * M + b] = c;
+        Cout[((size_t)w * M + b) * M + a] = c;
       } else {
-        const int la = a / D2, ia = a % D2;
-        unsafeAtomicAdd(&F[(size_t)sm.fbe[la] * D2 + ia], s);
+        const size_t s1 = sm.slot[4 * la + lb];
+        if (la == lb) {
+          unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], c);
+          if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], c);
+        } else {
+          const size_t s2 = sm.slot[4 * lb + la];
+          H[(s1 * D2 + ia) * D2 + ib] = c;
+          H[(s2 * D2 + ib) * D2 + ia] = c;
+        }
       }
-      continue;
-    }
-    int a, b;
-    upper_pair(p, M, a, b);
-    const int la = a / D2, lb = b / D2, ia = a % D2, ib = b % D2;
-    const double zz = lds_dot<LD>(Zt + a * LD, Zt + b * LD);
-    const double vv = lds_dot<LD>(Vt + a * LD, Vt + b * LD);
-    const double nn = sm.gn[la][0] * sm.gn[lb][0] + sm.gn[la][1] * sm.gn[lb][1] + sm.gn[la][2] * sm.gn[lb][2];
-    double c = nn * zz - vv;
-    if (a == b) c += sm.gT[la];
-    if (Cout) {
-      Cout[((size_t)w * M + a) * M + b] = c;
-      Cout[((size_t)w * M + b) * M + a] = c;
-    } else {
-      const size_t s1 = sm.slot[4 * la + lb];
-      if (la == lb) {
-        unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], c);
-        if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], c);
-      } else {
-        const size_t s2 = sm.slot[4 * lb + la];
-        H[(s1 * D2 + ia) * D2 + ib] = c;
-        H[(s2 * D2 + ib) * D2 + ia] = c;
+    };
+    for (int p = t; p < NBP + NBM; p += NT) {
+      if (p >= NBP) {  // Cf for the pair of rows a0, a0 + 1
+        const int a0 = 2 * (p - NBP);
+        const double s0 = lds_dot<LD>(Vt + a0 * LD, Vt + M * LD);
+        const double s1 = lds_dot<LD>(Vt + (a0 + 1) * LD, Vt + M * LD);
+        if (Cfout) {
+          Cfout[(size_t)w * M + a0] = s0;
+          Cfout[(size_t)w * M + a0 + 1] = s1;
+        } else {
+          unsafeAtomicAdd(&F[(size_t)sm.fbe[a0 / D2] * D2 + a0 % D2], s0);
+          unsafeAtomicAdd(&F[(size_t)sm.fbe[(a0 + 1) / D2] * D2 + (a0 + 1) % D2], s1);
+        }
+        continue;
       }
+      int ba, bb;
+      upper_pair(p, NBM, ba, bb);
+      const int a0 = 2 * ba, b0 = 2 * bb;
+      double zz[2][2][2] = {}, vv[2][2][2] = {};
+#pragma unroll 2
+      for (int r = 0; r < LD; r += 2) {
+        double2 za[2], zb[2], va[2], vb[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          za[u] = *reinterpret_cast<const double2*>(Zt + (a0 + u) * LD + r);
+          zb[u] = *reinterpret_cast<const double2*>(Zt + (b0 + u) * LD + r);
+          va[u] = *reinterpret_cast<const double2*>(Vt + (a0 + u) * LD + r);
+          vb[u] = *reinterpret_cast<const double2*>(Vt + (b0 + u) * LD + r);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 2; ++v) {
+            zz[u][v][0] = fma(za[u].x, zb[v].x, zz[u][v][0]);
+            zz[u][v][1] = fma(za[u].y, zb[v].y, zz[u][v][1]);
+            vv[u][v][0] = fma(va[u].x, vb[v].x, vv[u][v][0]);
+            vv[u][v][1] = fma(va[u].y, vb[v].y, vv[u][v][1]);
+          }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const int a = a0 + u, b = b0 + v;
+          if (a > b) continue;
+          const int la = a / D2, lb = b / D2;
+          const double nn = sm.gn[la][0] * sm.gn[lb][0] + sm.gn[la][1] * sm.gn[lb][1] + sm.gn[la][2] * sm.gn[lb][2];
+          emit(a, b, nn * (zz[u][v][0] + zz[u][v][1]) - (vv[u][v][0] + vv[u][v][1]));
+        }
     }
   }
   __syncthreads();
