@@ -112,17 +112,36 @@ __device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], doub
 // so the updates of one pass are independent, and every lane reads the same LDS words.
 template <int N, int LD>
 __device__ __forceinline__ void col_forward(const double* Lt, const double* idg, double (&x)[N]) {
+  // the leading PF pairs of row k + 1 are fetched during pass k (they are the first used
+  // in pass k + 1), the rest of each row at the start of its own pass
+  constexpr int NP = LD / 2, PF = 6;
+  double2 nxt[PF];
+  double dn = idg[0];
+#pragma unroll
+  for (int u = 0; u < PF; ++u) nxt[u] = *reinterpret_cast<const double2*>(Lt + 2 * min(u, NP - 1));
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const double xk = x[k] * idg[k];
+    const int p0 = (k + 1) / 2;
+    double2 cur[NP];
+#pragma unroll
+    for (int p = p0; p < NP; ++p)
+      cur[p] = p < p0 + PF ? nxt[p - p0] : *reinterpret_cast<const double2*>(Lt + k * LD + 2 * p);
+    const double dc = dn;
+    if (k + 1 < N) {
+      const int q0 = (k + 2) / 2;
+      dn = idg[k + 1];
+#pragma unroll
+      for (int u = 0; u < PF; ++u)
+        if (q0 + u < NP) nxt[u] = *reinterpret_cast<const double2*>(Lt + (k + 1) * LD + 2 * (q0 + u));
+    }
+    const double xk = x[k] * dc;
     x[k] = xk;
 #pragma unroll
-    for (int p = (k + 1) / 2; 2 * p < N; ++p) {
-      const double2 l = *reinterpret_cast<const double2*>(Lt + k * LD + 2 * p);
-      if (2 * p > k) x[2 * p] = fma(-l.x, xk, x[2 * p]);
-      if (2 * p + 1 < N) x[2 * p + 1] = fma(-l.y, xk, x[2 * p + 1]);
+    for (int p = p0; 2 * p < N; ++p) {
+      if (2 * p > k) x[2 * p] = fma(-cur[p].x, xk, x[2 * p]);
+      if (2 * p + 1 < N) x[2 * p + 1] = fma(-cur[p].y, xk, x[2 * p + 1]);
     }
-    __builtin_amdgcn_sched_barrier(0);  // one row of L^T in registers at a time
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
