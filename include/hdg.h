@@ -451,8 +451,9 @@ hdg_status hdg_batch_get_config(const hdg_batch* batch, int k, hdg_tile_config* 
 /* Eager form: per degree (highest first) zero the diagonal blocks of H and F of its
  * meshes, then run the persistent kernel; all on `stream`. */
 hdg_status hdg_batch_condense(hdg_batch* batch, void* stream);
-/* (Re)records the same work as one hipGraph whose per-degree parts are parallel branches;
- * called by hdg_batch_launch when no graph exists or the configuration changed. */
+/* (Re)records the same work, in the same order, as one hipGraph (the per-degree parts
+ * are chained, not parallel: each persistent kernel is sized for the whole chip); called
+ * by hdg_batch_launch when no graph exists or the configuration changed. */
 hdg_status hdg_batch_capture(hdg_batch* batch);
 /* One graph launch of the whole batch on `stream`. */
 hdg_status hdg_batch_launch(hdg_batch* batch, void* stream);

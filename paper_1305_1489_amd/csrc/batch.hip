@@ -10,8 +10,10 @@
 //
 // A degree's part is: zero the diagonal blocks and F of its meshes, then the persistent
 // condensation kernel.  The eager form runs the parts one after another (highest degree,
-// i.e. the longest work, first); the captured form records them as parallel branches of
-// one hipGraph (a fork/join over one stream per degree), replayed by one graph launch.
+// i.e. the longest work, first); the captured form records the same chain as one hipGraph,
+// replayed by one graph launch.  The parts are not run as parallel branches: each
+// persistent kernel spreads its units statically over a grid sized for the whole chip,
+// so a kernel sharing the compute units with another finishes with a long tail.
 //
 // The autotuner times, for one degree, every candidate launch shape on the batch itself
 // and keeps the fastest: for the tile kernels the persistent grid size in {1, 2, 4, 8, 16}
@@ -56,13 +58,10 @@ struct hdg_batch {
     int64_t nelt = 0;
     int64_t max_zero = 0;  // largest nfc * d2 * d2 of the degree's meshes
     hdg_tile_config cfg{0, 0, 1};
-    hipStream_t side = nullptr;
-    hipEvent_t join = nullptr;
   };
   Degree deg[kMaxDegree + 1];
   int ncu = 0;
   hipStream_t cap = nullptr;
-  hipEvent_t fork = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -171,11 +170,8 @@ extern "C" hdg_status hdg_batch_create(int n, const hdg_batch_item* items, hdg_b
     e = hipMalloc(&D.d_items, sizeof(BatchItem) * D.items.size());
     if (e == hipSuccess)
       e = hipMemcpy(D.d_items, D.items.data(), sizeof(BatchItem) * D.items.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&D.side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&D.join, hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
   if (e != hipSuccess) {
     hdg_batch_destroy(b);
     return check_hip(e, "hdg_batch_create");
@@ -193,11 +189,8 @@ extern "C" hdg_status hdg_batch_destroy(hdg_batch* b) {
       hipError_t e2 = hipFree(D.d_items);
       if (e == hipSuccess) e = e2;
     }
-    if (D.side) (void)hipStreamDestroy(D.side);
-    if (D.join) (void)hipEventDestroy(D.join);
   }
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
   return check_hip(e, "hdg_batch_destroy");
 }
@@ -240,15 +233,8 @@ extern "C" hdg_status hdg_batch_capture(hdg_batch* b) {
   hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return check_hip(e, "hdg_batch_capture: begin");
   hdg_status st = HDG_OK;
-  e = hipEventRecord(b->fork, b->cap);
-  for (int k = kMaxDegree; k >= 0 && e == hipSuccess && st == HDG_OK; --k) {
-    auto& D = b->deg[k];
-    if (D.items.empty()) continue;
-    e = hipStreamWaitEvent(D.side, b->fork, 0);
-    if (e == hipSuccess) st = run_degree(b, k, D.side);
-    if (e == hipSuccess && st == HDG_OK) e = hipEventRecord(D.join, D.side);
-    if (e == hipSuccess && st == HDG_OK) e = hipStreamWaitEvent(b->cap, D.join, 0);
-  }
+  for (int k = kMaxDegree; k >= 0 && st == HDG_OK; --k)
+    if (!b->deg[k].items.empty()) st = run_degree(b, k, b->cap);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->cap, &g);
   if (st) {
