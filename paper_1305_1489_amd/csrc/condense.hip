@@ -1,7 +1,8 @@
 // Assembly of the element blocks, static condensation onto the four face traces, and
 // scatter into the global trace system (Sections 3-6 of the paper).
 //
-// Per element K (one wavefront, blocks resident in LDS):
+// Per element K (degrees 0 and 4 here; 1..3 run as tiles of four elements elsewhere), on
+// one workgroup with the blocks resident in LDS:
 //   volume terms (eq 3.55, eq 3.56):
 //     M  = sum_q |K| w_q kappa_q^{-1} p_q p_q^T,   Mc = sum_q |K| w_q c_q p_q p_q^T,
 //     f  = sum_q |K| w_q f_q p_q,                  C_s = sum_h a_{s h} Chat^h
