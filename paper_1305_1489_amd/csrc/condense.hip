@@ -59,14 +59,13 @@ __device__ __forceinline__ double lds_dot(const double* x, const double* y) {
 // Cholesky factor (eq 5.1, eq 5.4) of the N x N SPD matrix whose upper triangle is
 // A[0] + ... + A[NP-1] (row-major, leading dimension LD; entry (i, k) kept at
 // [min(i, k)][max(i, k)]), by one wavefront: lane i holds row i in registers; pass j
-// updates the trailing rows with the unscaled column j, which the lanes publish through
-// bc (two buffers of 64 doubles, alternating; column j + 1 is updated and published first,
-// so its round trip through LDS overlaps the rest of pass j), and then scales column j.
+// broadcasts column j lane by lane (v_readlane), updates the trailing rows with it while
+// still unscaled and then scales it; column j + 1 is updated first, so the next pivot's
+// reciprocal square root overlaps the rest of the pass.
 // Writes L^T to Lt (Lt[k][i] = L[i][k] for k <= i) and the reciprocal diagonal to idg.
 // Lt may alias A[0]: every lane has read its row before any lane writes.
 template <int N, int LD, int NP>
-__device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], double* Lt, double* idg, double* bc,
-                                              int lane) {
+__device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], double* Lt, double* idg, int lane) {
   const int i = min(lane, N - 1);
   double a[N];
 #pragma unroll
@@ -150,17 +149,14 @@ template <int K>
 struct ElemLayout {
   using Dm = Dims<K>;
   static constexpr int D3 = Dm::D3, D2 = Dm::D2, M = Dm::M, NQD = Dm::NQD;
-  static constexpr int LD = (D3 + 1) & ~1;                       // padded length of every D3-vector
-  static constexpr int PLD = (D3 + 3) / 4 * 4, NQP = (NQD + 3) / 4 * 4;  // padded basis table
-  static constexpr int QS = 3;                                   // point slices of the Gram sums
-  static constexpr int NCOL = 3 * D3 + M;                        // right-hand sides C^T | DP^T
-  static constexpr int NB = LD / 2;                              // 2 x 2 blocks of the Gram matrices
-  // with D3 odd the last diagonal block holds one real entry, which the block beside it takes
-  static constexpr bool MERGE = (D3 % 2 == 1) && NB >= 2;
-  static constexpr int NBLK = NB * (NB + 1) / 2 - (MERGE ? 1 : 0);
+  static constexpr int LD = (D3 + 3) / 4 * 4;  // padded length of every D3-vector: whole 4x4 tiles
+  static constexpr int PLD = LD, NQP = (NQD + 3) / 4 * 4;  // the padded basis table has rows of LD
+  static constexpr int TT = LD / 4, TM = M / 4;             // tiles along D3 and along the M trace unknowns
+  static constexpr int NCOL = 3 * D3 + M;                    // right-hand sides C^T | DP^T
   static constexpr int BIG_SOLVE = (NCOL + M + 1) * LD;
   static constexpr int BIG_STAGE = lds_stage_bytes<NQP * PLD>() / 8;
   static constexpr int BIG = BIG_SOLVE > BIG_STAGE ? BIG_SOLVE : BIG_STAGE;
+  static_assert(M % 4 == 0 && NQD % 4 == 0, "whole tiles of trace unknowns and of points");
 };
 
 template <int K>
@@ -171,12 +167,10 @@ struct CondenseSmem {
   double big[Ly::BIG];
   double wkc[2 * Ly::NQD];  // (|K| w_q / kappa_q, |K| w_q c_q)
   double wf[Ly::NQD];       // |K| w_q f_q
-  double Lt[Ly::LD * Ly::LD];  // Gram partial of the first slice (upper), then L^T
-  double St[Ly::LD * Ly::LD];  // likewise for S, then Ls^T
-  double Mp[Ly::QS - 1][Ly::LD * Ly::LD], Sp[Ly::QS - 1][Ly::LD * Ly::LD];
+  double Lt[Ly::LD * Ly::LD];  // M (upper tiles), then L^T
+  double St[Ly::LD * Ly::LD];  // Mc, then S, then Ls^T
   double fv[Ly::LD];
   double idl[Ly::LD], ids[Ly::LD];
-  double bc[128];  // column broadcast of the one-wavefront Cholesky
   double gn[4][3], gT[4], ga[9];
   int gmu[4], slot[16], fbe[4];
 };
@@ -190,10 +184,9 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
                                                  const int* __restrict__ elems, int nwork, double* __restrict__ Cout,
                                                  double* __restrict__ Cfout, int w) {
   using Ly = ElemLayout<K>;
-  constexpr int D3 = Ly::D3, D2 = Ly::D2, M = Ly::M, NQD = Ly::NQD, LD = Ly::LD, PLD = Ly::PLD, QS = Ly::QS;
-  constexpr int NCOL = Ly::NCOL, NB = Ly::NB, NBLK = Ly::NBLK, NW = NT / 64, NTRI = D3 * (D3 + 1) / 2;
-  constexpr int QL = (NQD + QS - 1) / QS;
-  constexpr bool PREFETCH = false;
+  constexpr int D3 = Ly::D3, D2 = Ly::D2, M = Ly::M, NQD = Ly::NQD, LD = Ly::LD, PLD = Ly::PLD;
+  constexpr int NCOL = Ly::NCOL, TT = Ly::TT, TM = Ly::TM, NW = NT / 64, NTRI = D3 * (D3 + 1) / 2;
+  constexpr int NUT = TT * (TT + 1) / 2;  // upper tiles of a D3 x D3 matrix
   __shared__ __align__(16) CondenseSmem<K> sm;
   // the thread index passes through an opaque move, so the per-thread offsets and masks
   // derived from it are formed where they are used instead of being hoisted out of the
@@ -201,6 +194,8 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   int t = threadIdx.x;
   asm volatile("" : "+v"(t));
   const int lane = t & 63, wave = t >> 6;
+  // canonical tile coordinates of this lane (block blk, row tr, column tc)
+  const int blk = (lane >> 2) & 3, tr = lane >> 4, tc = lane & 3;
   const int E = elems ? elems[w] : w;
   if (E < 0 || E >= mesh.nelt) return;  // uniform across the block
   double* Wt = sm.big;
@@ -265,55 +260,31 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
     for (int r = 0; r < LD; r += 2)
       *reinterpret_cast<double2*>(row + r) = make_double2(x[r], r + 1 < D3 ? x[r + 1 < D3 ? r + 1 : 0] : 0.0);
   };
-  if (PREFETCH && t < NCOL) load_col(t);
   // ---- Gram matrices M = P^T diag(|K| w / kappa) P and Mc = P^T diag(|K| w c) P (eq 3.5,
-  // eq 4.5): one thread per 2 x 2 block of the upper triangle and slice of the points
-  for (int it = t; it < NBLK * QS; it += NT) {
-    const int blk = it % NBLK, sl = it / NBLK;
-    int bi = 0, rem = blk;
-    while (rem >= NB - bi) {
-      rem -= NB - bi;
-      ++bi;
+  // eq 4.5) on the FP64 matrix cores: job j is upper tile j / 2 of M (j even) or of Mc,
+  // one job per block, four per wavefront instruction, four points per step
+  for (int quad = wave; quad < (2 * NUT + 3) / 4; quad += NW) {
+    const int job = min(4 * quad + blk, 2 * NUT - 1), m = job & 1;
+    int ti, tj;
+    upper_pair(job >> 1, TT, ti, tj);
+    const double* px = sm.big + tr * PLD + 4 * ti + tc;
+    const double* py = sm.big + tr * PLD + 4 * tj + tc;
+    const double* pw = sm.wkc + 2 * tr + m;
+    // three independent accumulation chains over the point steps
+    double acc[3] = {0, 0, 0};
+#pragma unroll 6
+    for (int q0 = 0; q0 < NQD; q0 += 4) {
+      const int ch = (q0 / 4) % 3;
+      acc[ch] = mfma4(px[q0 * PLD], pw[2 * q0] * py[q0 * PLD], acc[ch]);
     }
-    const int bj = bi + rem;
-    const bool extra = Ly::MERGE && bi == NB - 2 && bj == NB - 1;
-    const int q0 = sl * QL, q1 = min(NQD, q0 + QL);
-    double k00 = 0, k01 = 0, k10 = 0, k11 = 0, c00 = 0, c01 = 0, c10 = 0, c11 = 0, ke = 0, ce = 0;
-    for (int q = q0; q < q1; ++q) {
-      const double2 wq = *reinterpret_cast<const double2*>(sm.wkc + 2 * q);
-      const double2 pi = *reinterpret_cast<const double2*>(sm.big + q * PLD + 2 * bi);
-      const double2 pj = *reinterpret_cast<const double2*>(sm.big + q * PLD + 2 * bj);
-      const double a0 = wq.x * pi.x, a1 = wq.x * pi.y, b0 = wq.y * pi.x, b1 = wq.y * pi.y;
-      k00 = fma(a0, pj.x, k00);
-      k01 = fma(a0, pj.y, k01);
-      k10 = fma(a1, pj.x, k10);
-      k11 = fma(a1, pj.y, k11);
-      c00 = fma(b0, pj.x, c00);
-      c01 = fma(b0, pj.y, c01);
-      c10 = fma(b1, pj.x, c10);
-      c11 = fma(b1, pj.y, c11);
-      if (extra) {
-        const double e2 = pj.x * pj.x;
-        ke = fma(wq.x, e2, ke);
-        ce = fma(wq.y, e2, ce);
-      }
-    }
-    double* mk = sl == 0 ? sm.Lt : sm.Mp[sl - 1];
-    double* mc = sl == 0 ? sm.St : sm.Sp[sl - 1];
-    const int o = 2 * bi * LD + 2 * bj;
-    mk[o] = k00, mk[o + 1] = k01, mk[o + LD] = k10, mk[o + LD + 1] = k11;
-    mc[o] = c00, mc[o + 1] = c01, mc[o + LD] = c10, mc[o + LD + 1] = c11;
-    if (extra) {
-      mk[(D3 - 1) * LD + D3 - 1] = ke;
-      mc[(D3 - 1) * LD + D3 - 1] = ce;
-    }
+    if (4 * quad + blk < 2 * NUT) (m ? sm.St : sm.Lt)[(4 * ti + tr) * LD + 4 * tj + tc] = (acc[0] + acc[1]) + acc[2];
   }
   __syncthreads();
   double* fa = factors ? factors + (size_t)E * (D3 * (D3 + 1) + D3) : nullptr;
   // ---- L (one wavefront) while the columns arrive; the load vector f from the staged table
   if (wave == NW - 1) {
-    const double* const parts[QS] = {sm.Lt, sm.Mp[0], sm.Mp[1]};
-    wave_cholesky<D3, LD, QS>(parts, sm.Lt, sm.idl, sm.bc, lane);
+    const double* const parts[1] = {sm.Lt};
+    wave_cholesky<D3, LD, 1>(parts, sm.Lt, sm.idl, lane);
   }
   {
     const int fi = (NW > 1 ? NT - 65 : NT - 1) - t;
@@ -327,17 +298,10 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   }
   __syncthreads();
   // ---- W_s = L^{-1} C_s^T, Z = L^{-1} DP^T (eq 5.2), one column per thread
-  if (PREFETCH) {
-    if (t < NCOL) {
-      col_forward<D3, LD>(sm.Lt, sm.idl, x);
-      store_col(sm.big + t * LD);
-    }
-  } else {
-    for (int c = t; c < NCOL; c += NT) {
-      load_col(c);
-      col_forward<D3, LD>(sm.Lt, sm.idl, x);
-      store_col(sm.big + c * LD);
-    }
+  for (int c = t; c < NCOL; c += NT) {
+    load_col(c);
+    col_forward<D3, LD>(sm.Lt, sm.idl, x);
+    store_col(sm.big + c * LD);
   }
   if (fa)
     for (int p = NT - 1 - t; p < NTRI; p += NT) {
@@ -346,60 +310,56 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
       fa[j * (j + 1) / 2 + i] = sm.Lt[i * LD + j];
     }
   __syncthreads();
-  // ---- S = Mc + sum_l tau_l |e_l| PP_l + sum_s W_s^T W_s (eq 5.3), upper triangle
-  for (int p = t; p < NTRI; p += NT) {
-    int i, j;
-    upper_pair(p, D3, i, j);
-    const int o = i * LD + j;
-    double pp[4];
+  // ---- S = Mc + sum_l tau_l |e_l| PP_l + sum_s W_s^T W_s (eq 5.3), upper tiles on the
+  // matrix cores (rows of W^T past D3 - 1 feed only the padding entries)
+  for (int quad = wave; quad < (NUT + 3) / 4; quad += NW) {
+    const int job = min(4 * quad + blk, NUT - 1);
+    int ti, tj;
+    upper_pair(job, TT, ti, tj);
+    const int i = 4 * ti + tr, j = 4 * tj + tc, o = i * LD + j;
+    double pp[4];  // the table terms are added last, so these loads overlap the products
 #pragma unroll
     for (int l = 0; l < 4; ++l) pp[l] = tb.PPt[(l * PLD + i) * PLD + j];
-    double s = sm.St[o];
+    double acc[3] = {sm.St[o], 0, 0};  // one chain per direction
 #pragma unroll
-    for (int k = 0; k < QS - 1; ++k) s += sm.Sp[k][o];
+    for (int c = 0; c < 3; ++c) {
+      const double* px = Wt + (c * D3 + 4 * ti + tc) * LD + tr;
+      const double* py = Wt + (c * D3 + 4 * tj + tc) * LD + tr;
 #pragma unroll
-    for (int l = 0; l < 4; ++l) s = fma(sm.gT[l], pp[l], s);
+      for (int r0 = 0; r0 < LD; r0 += 4) acc[c] = mfma4(px[r0], py[r0], acc[c]);
+    }
+    double sv = (acc[0] + acc[1]) + acc[2];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s += lds_dot<LD>(Wt + (c * D3 + i) * LD, Wt + (c * D3 + j) * LD);
-    sm.St[o] = s;
+    for (int l = 0; l < 4; ++l) sv = fma(sm.gT[l], pp[l], sv);
+    if (4 * quad + blk < NUT) sm.St[o] = sv;
   }
   __syncthreads();
   // ---- Ls (one wavefront) while the others form B_l = T_l DP_l^T + U_l^T Z_l with
   // U_l = sum_s n_{l s} W_s (eq 5.5), stored as rows of V^T
   if (wave == NW - 1) {
     const double* const parts[1] = {sm.St};
-    wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, sm.bc, lane);
+    wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, lane);
   }
   if (NW == 1 || wave < NW - 1) {
-    // thread item (i, g): row i of B for the BC columns 5 g .. of one face, so the row
-    // U_l[.][i] = sum_s n_{l s} W_s[.][i] is formed once for all of them
-    constexpr int NBT = NW == 1 ? NT : NT - 64, BC = D2 % 5 == 0 ? 5 : 1, NG = M / BC;
-    for (int p = t; p < NG * D3; p += NBT) {
-      const int g = p / D3, i = p % D3, c0 = g * BC, l = c0 / D2;
-      const double n0 = sm.gn[l][0], n1 = sm.gn[l][1], n2 = sm.gn[l][2];
-      double dp[BC];
+    // B^T by tiles on the matrix cores: B[i][c] = T_l DP_l[c][i] + sum_s sum_r W_s[r][i]
+    // (n_{l s} Z[r][c]), l the face of column c; the normal rides on the Z operand, whose
+    // element (r, tc) belongs to column 4 tcb + tc of the tile
+    constexpr int NWB = NW == 1 ? 1 : NW - 1, NJ = TT * TM;
+    for (int quad = wave; quad < (NJ + 3) / 4; quad += NWB) {
+      const int job = min(4 * quad + blk, NJ - 1), ti = job % TT, tcb = job / TT;
+      const int i = 4 * ti + tr, c = 4 * tcb + tc, l = c / D2;
+      // the table term is added last, so its load overlaps the products
+      const double dp = tb.DP[((sm.gmu[l] * 4 + l) * D2 + c % D2) * D3 + min(i, D3 - 1)];
+      double acc[3] = {0, 0, 0};  // one chain per direction
 #pragma unroll
-      for (int b = 0; b < BC; ++b) dp[b] = tb.DP[((sm.gmu[l] * 4 + l) * D2 + (c0 + b) % D2) * D3 + i];
-      double acc[BC][2] = {};
-      const double* w0 = Wt + i * LD;
-      const double* w1 = Wt + (D3 + i) * LD;
-      const double* w2 = Wt + (2 * D3 + i) * LD;
-#pragma unroll 2
-      for (int r = 0; r < LD; r += 2) {
-        const double2 x0 = *reinterpret_cast<const double2*>(w0 + r);
-        const double2 x1 = *reinterpret_cast<const double2*>(w1 + r);
-        const double2 x2 = *reinterpret_cast<const double2*>(w2 + r);
-        const double ux = fma(n2, x2.x, fma(n1, x1.x, n0 * x0.x));
-        const double uy = fma(n2, x2.y, fma(n1, x1.y, n0 * x0.y));
+      for (int sd = 0; sd < 3; ++sd) {
+        const double ns = sm.gn[l][sd];
+        const double* px = Wt + (sd * D3 + 4 * ti + tc) * LD + tr;
+        const double* py = Zt + c * LD + tr;
 #pragma unroll
-        for (int b = 0; b < BC; ++b) {
-          const double2 z = *reinterpret_cast<const double2*>(Zt + (c0 + b) * LD + r);
-          acc[b][0] = fma(ux, z.x, acc[b][0]);
-          acc[b][1] = fma(uy, z.y, acc[b][1]);
-        }
+        for (int r0 = 0; r0 < LD; r0 += 4) acc[sd] = mfma4(px[r0], ns * py[r0], acc[sd]);
       }
-#pragma unroll
-      for (int b = 0; b < BC; ++b) Vt[(c0 + b) * LD + i] = fma(sm.gT[l], dp[b], acc[b][0] + acc[b][1]);
+      if (4 * quad + blk < NJ && i < D3) Vt[c * LD + i] = fma(sm.gT[l], dp, (acc[0] + acc[1]) + acc[2]);
     }
   }
   __syncthreads();
@@ -421,8 +381,6 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   // ---- C^K = tau DD + (n.n) Z^T Z - V^T V (upper triangle) and Cf^K = V^T (Ls^{-1} f)
   // (eq 5.6); scattered into H and F, or exported
   {
-    constexpr int NBM = M / 2, NBP = NBM * (NBM + 1) / 2;  // 2 x 2 blocks of the upper triangle
-    static_assert(M % 2 == 0, "face blocks pair up");
     auto emit = [&](int a, int b, double c) {
       const int la = a / D2, lb = b / D2, ia = a % D2, ib = b % D2;
       if (a == b) c += sm.gT[la];
@@ -441,54 +399,41 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
         }
       }
     };
-    for (int p = t; p < NBP + NBM; p += NT) {
-      if (p >= NBP) {  // Cf for the pair of rows a0, a0 + 1
-        const int a0 = 2 * (p - NBP);
-        const double s0 = lds_dot<LD>(Vt + a0 * LD, Vt + M * LD);
-        const double s1 = lds_dot<LD>(Vt + (a0 + 1) * LD, Vt + M * LD);
-        if (Cfout) {
-          Cfout[(size_t)w * M + a0] = s0;
-          Cfout[(size_t)w * M + a0 + 1] = s1;
-        } else {
-          unsafeAtomicAdd(&F[(size_t)sm.fbe[a0 / D2] * D2 + a0 % D2], s0);
-          unsafeAtomicAdd(&F[(size_t)sm.fbe[(a0 + 1) / D2] * D2 + (a0 + 1) % D2], s1);
+    // job < NPT: upper tile pair (ta, tb) of C^K, the products Z^T Z and V^T V on the
+    // matrix cores; NPT <= job: Cf^K for rows 4 ta .. 4 ta + 3 (the Y operand is the f
+    // column of V^T for every column of the tile)
+    constexpr int NPT = TM * (TM + 1) / 2, NJ = NPT + TM;
+    for (int quad = wave; quad < (NJ + 3) / 4; quad += NW) {
+      const int job = min(4 * quad + blk, NJ - 1);
+      const bool cf = job >= NPT;
+      int ta = job - NPT, tbb = 0;
+      if (!cf) upper_pair(job, TM, ta, tbb);
+      const double* zx = (cf ? Vt : Zt) + (4 * ta + tc) * LD + tr;
+      const double* zy = (cf ? Vt + M * LD : Zt + (4 * tbb + tc) * LD) + tr;
+      const double* vx = Vt + (4 * ta + tc) * LD + tr;
+      const double* vy = Vt + (4 * tbb + tc) * LD + tr;
+      double z2[2] = {0, 0}, v2[2] = {0, 0};  // two chains per product
+#pragma unroll
+      for (int r0 = 0; r0 < LD; r0 += 4) {
+        z2[(r0 / 4) & 1] = mfma4(zx[r0], zy[r0], z2[(r0 / 4) & 1]);
+        v2[(r0 / 4) & 1] = mfma4(vx[r0], vy[r0], v2[(r0 / 4) & 1]);
+      }
+      const double zz = z2[0] + z2[1], vv = v2[0] + v2[1];
+      if (4 * quad + blk >= NJ) continue;
+      const int a = 4 * ta + tr, b = 4 * tbb + tc;
+      if (cf) {
+        if (tc == 0) {
+          if (Cfout)
+            Cfout[(size_t)w * M + a] = zz;
+          else
+            unsafeAtomicAdd(&F[(size_t)sm.fbe[a / D2] * D2 + a % D2], zz);
         }
         continue;
       }
-      int ba, bb;
-      upper_pair(p, NBM, ba, bb);
-      const int a0 = 2 * ba, b0 = 2 * bb;
-      double zz[2][2][2] = {}, vv[2][2][2] = {};
-#pragma unroll 2
-      for (int r = 0; r < LD; r += 2) {
-        double2 za[2], zb[2], va[2], vb[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          za[u] = *reinterpret_cast<const double2*>(Zt + (a0 + u) * LD + r);
-          zb[u] = *reinterpret_cast<const double2*>(Zt + (b0 + u) * LD + r);
-          va[u] = *reinterpret_cast<const double2*>(Vt + (a0 + u) * LD + r);
-          vb[u] = *reinterpret_cast<const double2*>(Vt + (b0 + u) * LD + r);
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int v = 0; v < 2; ++v) {
-            zz[u][v][0] = fma(za[u].x, zb[v].x, zz[u][v][0]);
-            zz[u][v][1] = fma(za[u].y, zb[v].y, zz[u][v][1]);
-            vv[u][v][0] = fma(va[u].x, vb[v].x, vv[u][v][0]);
-            vv[u][v][1] = fma(va[u].y, vb[v].y, vv[u][v][1]);
-          }
-      }
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-          const int a = a0 + u, b = b0 + v;
-          if (a > b) continue;
-          const int la = a / D2, lb = b / D2;
-          const double nn = sm.gn[la][0] * sm.gn[lb][0] + sm.gn[la][1] * sm.gn[lb][1] + sm.gn[la][2] * sm.gn[lb][2];
-          emit(a, b, nn * (zz[u][v][0] + zz[u][v][1]) - (vv[u][v][0] + vv[u][v][1]));
-        }
+      if (a > b) continue;
+      const int la = a / D2, lb = b / D2;
+      const double nn = sm.gn[la][0] * sm.gn[lb][0] + sm.gn[la][1] * sm.gn[lb][1] + sm.gn[la][2] * sm.gn[lb][2];
+      emit(a, b, nn * zz - vv);
     }
   }
   __syncthreads();
