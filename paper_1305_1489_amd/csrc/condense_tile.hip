@@ -556,7 +556,6 @@ __global__ void k_diag_sum(const int* __restrict__ diag, const int* __restrict__
     for (int y = 0; y < D2; ++y) out[y] = v[y];
   }
 }
-}
 
 template <int K>
 hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
