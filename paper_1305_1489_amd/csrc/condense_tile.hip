@@ -518,42 +518,34 @@ __global__ void k_zero_diag_t(const int* __restrict__ diag, int nfc, double* __r
 
 // H_ff (diagonal block) and F_f from the per-(element, face) contributions of the (one or
 // two) elements holding face f, in a fixed order; (0 + a) + b equals the atomic result.
-// One thread per row x of the block (row D2: the F entries): its 2 D2 reads of packed
-// entries (min(x, y), max(x, y)) are all in flight together, and the row goes out as
-// 16-byte stores when D2 is even (rows then start on 16-byte boundaries).
+// One packed entry per thread (contiguous reads of both contributions); an off-diagonal
+// entry of the block is written to both of its mirrored places.
 template <int D2>
 __global__ void k_diag_sum(const int* __restrict__ diag, const int* __restrict__ face_elem, int nfc,
                            const double* __restrict__ dws, double* __restrict__ H, double* __restrict__ F) {
-  constexpr int W = ws_block(D2), TRI = D2 * (D2 + 1) / 2, PER = D2 + 1;
+  constexpr int W = ws_block(D2), TRI = D2 * (D2 + 1) / 2;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)nfc * PER) return;
-  const int f = (int)(i / PER);
-  const int x = (int)(i - (int64_t)f * PER);
+  if (i >= (int64_t)nfc * W) return;
+  const int f = (int)(i / W);
+  const int p = (int)(i - (int64_t)f * W);
   const int v0 = face_elem[2 * f], v1 = face_elem[2 * f + 1];
-  const double* d0 = dws + (size_t)v0 * W;
-  const double* d1 = dws + (size_t)(v1 >= 0 ? v1 : v0) * W;
-  double a[D2], b[D2];
+  double v = 0.0 + dws[(size_t)v0 * W + p];
+  if (v1 >= 0) v += dws[(size_t)v1 * W + p];
+  if (p < TRI) {
+    // packed (x, y), x <= y: rows x hold D2 - x entries
+    int x = 0, rem = p;
 #pragma unroll
-  for (int y = 0; y < D2; ++y) {
-    const int lo = min(x, y), hi = max(x, y);
-    // rows lo of the packed upper triangle hold D2 - lo entries; row D2 is F
-    const int pk = x < D2 ? lo * D2 - lo * (lo - 1) / 2 + (hi - lo) : TRI + y;
-    a[y] = d0[pk];
-    b[y] = d1[pk];
-  }
-  double* out = x < D2 ? H + (size_t)diag[f] * D2 * D2 + x * D2 : F + (size_t)f * D2;
-  double v[D2];
-#pragma unroll
-  for (int y = 0; y < D2; ++y) {
-    v[y] = 0.0 + a[y];
-    if (v1 >= 0) v[y] += b[y];
-  }
-  if constexpr (D2 % 2 == 0) {
-#pragma unroll
-    for (int y = 0; y < D2; y += 2) *reinterpret_cast<double2*>(out + y) = make_double2(v[y], v[y + 1]);
+    for (int r = 0; r < D2 - 1; ++r)
+      if (rem >= D2 - x) {
+        rem -= D2 - x;
+        ++x;
+      }
+    const int y = x + rem;
+    double* blk = H + (size_t)diag[f] * D2 * D2;
+    blk[x * D2 + y] = v;
+    if (y != x) blk[y * D2 + x] = v;
   } else {
-#pragma unroll
-    for (int y = 0; y < D2; ++y) out[y] = v[y];
+    F[(size_t)f * D2 + (p - TRI)] = v;
   }
 }
 
@@ -579,7 +571,7 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
     k_geo_records<<<(unsigned)((mesh->nelt + 63) / 64), 64, 0, s>>>(*mesh, tau, geo_rec);
     k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
                                                         (int)n, Cout, Cfout, lc.xcd_remap, dws, geo_rec);
-    const size_t tot = (size_t)mesh->nfc * (D::D2 + 1);
+    const size_t tot = (size_t)mesh->nfc * ws_block(D::D2);
     k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
                                                                      dws, H, F);
   } else {
