@@ -8,6 +8,8 @@
 //   elimination    (end of Section 6) Dirichlet rows become identity rows with right-hand
 //                  side uD, and the Dirichlet columns of the free rows are moved to the
 //                  right-hand side and zeroed, which keeps H symmetric positive definite.
+#include <climits>
+
 #include "device_common.h"
 
 namespace hdg {
@@ -84,33 +86,51 @@ __global__ void k_neumann(hdg_mesh mesh, Tables tb, const double* __restrict__ g
   F[(size_t)f * D2 + c] += s;
 }
 
-// One thread per (row face f, row component i).
+// Dirichlet elimination (eq 6.5 with the Dirichlet traces known): a Dirichlet row becomes
+// the identity with right-hand side uhat; every other row subtracts H_fg uhat_g for its
+// Dirichlet columns g (ascending block order) and clears those blocks.  Only rows that
+// hold a Dirichlet column need work, and every such row is reached from the Dirichlet
+// faces: thread (Dirichlet face g, local face l of g's element, row component c) takes row
+// f = face l of that element, a Dirichlet row itself when l is g's own slot.  A row with
+// several Dirichlet columns is processed by the thread of the smallest of them only, so
+// each row is updated once and in the same order as a scan over all rows.
 template <int D2>
 __global__ void k_mask(hdg_mesh mesh, double* __restrict__ H, double* __restrict__ b, const double* __restrict__ uhat) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= mesh.nfc * D2) return;
-  const int f = i / D2, c = i % D2;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= mesh.ndir * 4 * D2) return;
+  const int c = (int)(t % D2), l = (int)(t / D2 % 4), g = mesh.d_dirfaces[t / (4 * D2)];
+  const int em = mesh.d_face_elem[2 * g];  // 4 E + m: the one element of a boundary face
+  const int f = mesh.d_facebyele[(em & ~3) + l];
+  const bool own = f == g;
+  if (!own && mesh.d_ftype[f] == 1) return;  // another Dirichlet row: its own thread clears it
   const int p0 = mesh.d_row_ptr[f], p1 = mesh.d_row_ptr[f + 1];
-  if (mesh.d_ftype[f] == 1) {
+  const size_t i = (size_t)f * D2 + c;
+  if (own) {
     for (int p = p0; p < p1; ++p) {
       double* blk = H + ((size_t)p * D2 + c) * D2;
       const bool dg = mesh.d_col_idx[p] == f;
       for (int j = 0; j < D2; ++j) blk[j] = (dg && j == c) ? 1.0 : 0.0;
     }
     b[i] = uhat[i];
-  } else {
-    double s = b[i];
-    for (int p = p0; p < p1; ++p) {
-      const int g = mesh.d_col_idx[p];
-      if (mesh.d_ftype[g] != 1) continue;
-      double* blk = H + ((size_t)p * D2 + c) * D2;
-      for (int j = 0; j < D2; ++j) {
-        s -= blk[j] * uhat[(size_t)g * D2 + j];
-        blk[j] = 0.0;
-      }
-    }
-    b[i] = s;
+    return;
   }
+  int gmin = INT_MAX;
+  for (int p = p0; p < p1; ++p) {
+    const int col = mesh.d_col_idx[p];
+    if (mesh.d_ftype[col] == 1) gmin = min(gmin, col);
+  }
+  if (gmin != g) return;  // the row belongs to the thread of its smallest Dirichlet column
+  double s = b[i];
+  for (int p = p0; p < p1; ++p) {
+    const int col = mesh.d_col_idx[p];
+    if (mesh.d_ftype[col] != 1) continue;
+    double* blk = H + ((size_t)p * D2 + c) * D2;
+    for (int j = 0; j < D2; ++j) {
+      s -= blk[j] * uhat[(size_t)col * D2 + j];
+      blk[j] = 0.0;
+    }
+  }
+  b[i] = s;
 }
 
 template <int K>
@@ -124,7 +144,10 @@ hdg_status run_boundary(const hdg_disc* disc, const hdg_mesh* mesh, const double
     k_dirichlet<Dm::D2, Dm::NQD2><<<(unsigned)((mesh->ndir * Dm::D2 + T - 1) / T), T, 0, s>>>(*mesh, disc->dev, uD, uhat);
   if (mesh->nneu)
     k_neumann<Dm::D2, Dm::NQD2><<<(unsigned)((mesh->nneu * Dm::D2 + T - 1) / T), T, 0, s>>>(*mesh, disc->dev, gN, F);
-  k_mask<Dm::D2><<<(unsigned)((nu + T - 1) / T), T, 0, s>>>(*mesh, H, F, uhat);
+  if (mesh->ndir) {
+    const size_t nm = (size_t)mesh->ndir * 4 * Dm::D2;
+    k_mask<Dm::D2><<<(unsigned)((nm + T - 1) / T), T, 0, s>>>(*mesh, H, F, uhat);
+  }
   HDG_CHECK_LAUNCH("hdg_boundary");
   return HDG_OK;
 }
