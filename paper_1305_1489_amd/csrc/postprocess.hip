@@ -52,7 +52,7 @@ struct PD {
   static constexpr bool RHS_LDS = (P1_LDS_LEN + PT_LDS_LEN) * 8 <= 144 * 1024;
 };
 
-constexpr int kRhsWaves = 8, kSolveWaves = 4;
+constexpr int kRhsWaves = 16, kSolveWaves = 4;
 
 // Geometry of element E (lanes 0..3; E < 0: the reference element, data zero).
 struct PGeo {
