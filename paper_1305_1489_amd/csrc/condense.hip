@@ -42,20 +42,6 @@ __device__ __forceinline__ void upper_pair(int p, int n, int& i, int& j) {
   j = n - 1 - (kk - r * (r + 1) / 2);
 }
 
-// x . y over LD doubles (LD even, both 16-byte aligned; padding entries zero).
-template <int LD>
-__device__ __forceinline__ double lds_dot(const double* x, const double* y) {
-  double s0 = 0, s1 = 0;
-#pragma unroll 3
-  for (int p = 0; p < LD / 2; ++p) {
-    const double2 a = *reinterpret_cast<const double2*>(x + 2 * p);
-    const double2 b = *reinterpret_cast<const double2*>(y + 2 * p);
-    s0 = fma(a.x, b.x, s0);
-    s1 = fma(a.y, b.y, s1);
-  }
-  return s0 + s1;
-}
-
 // Cholesky factor (eq 5.1, eq 5.4) of the N x N SPD matrix whose upper triangle is
 // A[0] + ... + A[NP-1] (row-major, leading dimension LD; entry (i, k) kept at
 // [min(i, k)][max(i, k)]), by one wavefront: lane i holds row i in registers; pass j
