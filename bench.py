@@ -178,8 +178,8 @@ def batch_metric(args):
     setup_s = time.perf_counter() - t0
     nelt = sum(S.mesh.nelt for S in systems)
     b = L.hdg_batch_create([S.batch_item() for S in systems])
-    cache = os.path.join(ROOT, "gpurun_out", "hdg_autotune.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) \
-        else AT.DEFAULT_CACHE
+    out_dir = os.environ.get("HDG_RESULTS_DIR")  # where run artefacts go, when set
+    cache = os.path.join(out_dir, "hdg_autotune.json") if out_dir and os.path.isdir(out_dir) else AT.DEFAULT_CACHE
     t0 = time.perf_counter()
     tuned = AT.tune_batch(b, sorted(discs), cache_path=cache, reps=3, force=True)
     tune_s = time.perf_counter() - t0
@@ -282,8 +282,8 @@ def main():
                     help="also run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is documented "
-              f"in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
+              f"note, not built", file=sys.stderr)
         sys.exit(2)
     import torch
     from hdg_inputs import config, kuhn_mesh

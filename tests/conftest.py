@@ -14,7 +14,7 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # gpu tests are skipped where no GPU is visible (selecting -m gpu on a GPU machine runs them)
+    # gpu tests are skipped where no GPU is visible (selecting -m gpu on a machine with one runs them)
     try:
         import torch
         has_gpu = torch.cuda.is_available()

@@ -7,7 +7,7 @@ Against the FP64 oracle on 256 sampled elements:
     vector, shared by both sides.
 The FP64 path is listed beside it.  On the whole mesh, against the library's FP64 path:
 H, F, the solved traces uhat (both solves to the same true residual), and q, u, u*.
-The table is printed and, when gpurun_out/ exists, written there as JSON.
+The table is printed and, when HDG_RESULTS_DIR names a directory, written there as JSON.
 """
 import json
 import os
@@ -92,8 +92,8 @@ def test_precision_table_jitter_k3():
              "sweeps": {"min": int(sw.min()), "max": int(sw.max()), "mean": float(sw.mean())},
              "solve_iterations": {"fp64": i64["iterations"], "fp32_refined": iir["iterations"]}}
     print(json.dumps(table, indent=1), flush=True)
-    out = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("HDG_RESULTS_DIR")
+    if out and os.path.isdir(out):
         json.dump(table, open(os.path.join(out, "precision_table.json"), "w"), indent=1)
     for form in oracle.values():
         for v in form.values():
