@@ -53,6 +53,8 @@ __global__ void __launch_bounds__(64) k_geo_records(hdg_mesh mesh, const double*
 // ([4 nelt][d2 (d2 + 1) / 2 + d2]: the row-packed upper triangle of the block, then the F
 // entries) with plain stores, to be summed per face by k_diag_sum; without it
 // they are atomic adds onto zeros.
+using gdouble = __attribute__((address_space(1))) double;
+
 template <int K, bool DWS>
 __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const Tables& tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
@@ -413,12 +415,15 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
           // same entry, written twice with one value)
           const int o1 = la == lb ? ia * D2 - ia * (ia - 1) / 2 + (ib - ia) : ia * D2 + ib;
           const int o2 = la2 == lb2 ? ia2 * D2 - ia2 * (ia2 - 1) / 2 + (ib2 - ia2) : ib2 * D2 + ia2;
-          double* p1 = base[4 * la + lb] + o1;
-          double* p2 = base[4 * lb2 + la2] + o2;
+          // the table holds generic pointers; stored through as global ones, so these are
+          // global stores (a flat store also counts against the LDS wait counter, and every
+          // later LDS wait of the loop would then wait for the store to reach memory)
+          gdouble* p1 = (gdouble*)(base[4 * la + lb]) + o1;
+          gdouble* p2 = (gdouble*)(base[4 * lb2 + la2]) + o2;
           if (I != N || r <= c) *p1 = val[N];
           if (I != N || c < r) *p2 = tv;
         }
-        if (c == 0) base[5 * la][D2 * (D2 + 1) / 2 + ia] = h;
+        if (c == 0) ((gdouble*)(base[5 * la]))[D2 * (D2 + 1) / 2 + ia] = h;
       }
     } else {
       // ---- C^K tiles and Cf^K, straight to H and F (or to the export arrays)
