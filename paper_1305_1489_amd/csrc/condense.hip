@@ -445,8 +445,9 @@ __global__ void __launch_bounds__(NT) k_batch_condense(const BatchItem* __restri
                                                        Tables tb, int xcd_remap) {
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
-    condense_element<K, NT>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
-                        (int)it->mesh.nelt, nullptr, nullptr, u - it->unit_begin);
+    condense_element<K, NT>(as_global(it->mesh), tb, as_global(it->kappa), as_global(it->c), as_global(it->f),
+                            as_global(it->tau), as_global(it->H), as_global(it->F), as_global(it->factors), nullptr,
+                            (int)it->mesh.nelt, nullptr, nullptr, u - it->unit_begin);
   }
 }
 

@@ -507,8 +507,10 @@ __global__ void __launch_bounds__(64) k_batch_condense_tile(const BatchItem* __r
                                                             int total_units, Tables tb, int xcd_remap) {
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
-    condense_tile_group<K, false>(it->mesh, tb, it->kappa, it->c, it->f, it->tau, it->H, it->F, it->factors, nullptr,
-                                  (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin), nullptr, nullptr);
+    condense_tile_group<K, false>(as_global(it->mesh), tb, as_global(it->kappa), as_global(it->c), as_global(it->f),
+                                  as_global(it->tau), as_global(it->H), as_global(it->F), as_global(it->factors),
+                                  nullptr, (int)it->mesh.nelt, nullptr, nullptr, 4 * (u - it->unit_begin), nullptr,
+                                  nullptr);
   }
 }
 

@@ -19,6 +19,38 @@ struct Dims {
 // Geometry of one element (eq 2.0, eq 3.8, Section 2): a = det(B) B^{-T} (the cofactor
 // matrix, a[s][h] = a_{s h}), |K|, outward normals n_l with |n_l| = |e_l|, T_l = tau_l |e_l|,
 // and mu_l = perm(K, l) - 1.
+// A pointer read from device memory (a batch work item) is a generic pointer, and the
+// compiler then emits flat memory instructions for it; a flat access also counts against
+// the LDS wait counter, so every later LDS wait waits for it to reach memory.  as_global
+// states that the pointer addresses global memory (it always does here), after which its
+// accesses are compiled as global ones.
+template <class T>
+__device__ __forceinline__ T* as_global(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+__device__ __forceinline__ hdg_mesh as_global(const hdg_mesh& m) {
+  hdg_mesh g = m;
+  g.d_coords = as_global(g.d_coords);
+  g.d_elements = as_global(g.d_elements);
+  g.d_dirichlet = as_global(g.d_dirichlet);
+  g.d_neumann = as_global(g.d_neumann);
+  g.d_faces = as_global(g.d_faces);
+  g.d_ftype = as_global(g.d_ftype);
+  g.d_dirfaces = as_global(g.d_dirfaces);
+  g.d_neufaces = as_global(g.d_neufaces);
+  g.d_facebyele = as_global(g.d_facebyele);
+  g.d_perm = as_global(g.d_perm);
+  g.d_volume = as_global(g.d_volume);
+  g.d_area = as_global(g.d_area);
+  g.d_normals = as_global(g.d_normals);
+  g.d_face_elem = as_global(g.d_face_elem);
+  g.d_row_ptr = as_global(g.d_row_ptr);
+  g.d_col_idx = as_global(g.d_col_idx);
+  g.d_diag = as_global(g.d_diag);
+  g.d_slot = as_global(g.d_slot);
+  return g;
+}
+
 struct ElemGeom {
   double v0[3];
   double a[3][3];
