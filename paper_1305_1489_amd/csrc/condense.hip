@@ -247,23 +247,30 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
       *reinterpret_cast<double2*>(row + r) = make_double2(x[r], r + 1 < D3 ? x[r + 1 < D3 ? r + 1 : 0] : 0.0);
   };
   // ---- Gram matrices M = P^T diag(|K| w / kappa) P and Mc = P^T diag(|K| w c) P (eq 3.5,
-  // eq 4.5) on the FP64 matrix cores: job j is upper tile j / 2 of M (j even) or of Mc,
-  // one job per block, four per wavefront instruction, four points per step
-  for (int quad = wave; quad < (2 * NUT + 3) / 4; quad += NW) {
-    const int job = min(4 * quad + blk, 2 * NUT - 1), m = job & 1;
+  // eq 4.5) on the FP64 matrix cores: job j is upper tile j of both, one job per block,
+  // four per wavefront instruction, four points per step; both weights come in one 16-byte
+  // read and the basis operands serve both products
+  for (int quad = wave; quad < (NUT + 3) / 4; quad += NW) {
+    const int job = min(4 * quad + blk, NUT - 1);
     int ti, tj;
-    upper_pair(job >> 1, TT, ti, tj);
+    upper_pair(job, TT, ti, tj);
     const double* px = sm.big + tr * PLD + 4 * ti + tc;
     const double* py = sm.big + tr * PLD + 4 * tj + tc;
-    const double* pw = sm.wkc + 2 * tr + m;
-    // three independent accumulation chains over the point steps
-    double acc[3] = {0, 0, 0};
+    const double* pw = sm.wkc + 2 * tr;
+    double am[2] = {0, 0}, ac[2] = {0, 0};  // two chains per product
 #pragma unroll 6
     for (int q0 = 0; q0 < NQD; q0 += 4) {
-      const int ch = (q0 / 4) % 3;
-      acc[ch] = mfma4(px[q0 * PLD], pw[2 * q0] * py[q0 * PLD], acc[ch]);
+      const int ch = (q0 / 4) & 1;
+      const double2 wq = *reinterpret_cast<const double2*>(pw + 2 * q0);
+      const double x = px[q0 * PLD], y = py[q0 * PLD];
+      am[ch] = mfma4(x, wq.x * y, am[ch]);
+      ac[ch] = mfma4(x, wq.y * y, ac[ch]);
     }
-    if (4 * quad + blk < 2 * NUT) (m ? sm.St : sm.Lt)[(4 * ti + tr) * LD + 4 * tj + tc] = (acc[0] + acc[1]) + acc[2];
+    if (4 * quad + blk < NUT) {
+      const int o = (4 * ti + tr) * LD + 4 * tj + tc;
+      sm.Lt[o] = am[0] + am[1];
+      sm.St[o] = ac[0] + ac[1];
+    }
   }
   __syncthreads();
   double* fa = factors ? factors + (size_t)E * (D3 * (D3 + 1) + D3) : nullptr;
