@@ -7,11 +7,11 @@ workload configurations.  It holds none of the HDG method's arithmetic (no
 quadrature, no basis, no local matrices).  Both the CPU oracle and the HIP
 library's tests draw their inputs from here.
 """
-from .mesh import kuhn_mesh, KuhnMesh
+from .mesh import kuhn_mesh, KuhnMesh, permute_element_vertices
 from .fields import Problem, manufactured_sin_xyz, manufactured_sin_pi, polynomial_problem, rff_field, constant_rhs_problem
 from .configs import config, CONFIGS
 
 __all__ = [
-    "kuhn_mesh", "KuhnMesh", "Problem", "manufactured_sin_xyz", "manufactured_sin_pi",
+    "kuhn_mesh", "KuhnMesh", "permute_element_vertices", "Problem", "manufactured_sin_xyz", "manufactured_sin_pi",
     "polynomial_problem", "rff_field", "constant_rhs_problem", "config", "CONFIGS",
 ]

@@ -142,3 +142,22 @@ def single_tet_mesh(vertices=None) -> KuhnMesh:
             rows.append([a, b, c])
     return KuhnMesh(n=0, coordinates=coords, elements=el,
                     dirichlet=np.array(rows, dtype=np.int32), neumann=np.zeros((0, 3), dtype=np.int32))
+
+
+# The twelve even permutations of four vertex slots: reordering an element's vertices by
+# one of them keeps det B_K > 0 (Section 2 requires positively oriented elements).
+EVEN_PERMUTATIONS = tuple(p for p in itertools.permutations(range(4))
+                          if sum(p[i] > p[j] for i in range(4) for j in range(i + 1, 4)) % 2 == 0)
+
+
+def permute_element_vertices(mesh: KuhnMesh, seed: int = 0) -> KuhnMesh:
+    """The same mesh with each element's vertex list reordered by a seeded even permutation
+    (numpy PCG64(seed), one of the twelve per element).  The boundary lists are untouched.
+    A Kuhn mesh alone meets only a few (local face, face permutation) pairs; reordered this
+    way, interior faces are seen from their two elements under every relative orientation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pick = rng.integers(0, len(EVEN_PERMUTATIONS), size=mesh.nelt)
+    perms = np.array(EVEN_PERMUTATIONS, dtype=np.int64)[pick]            # (nelt, 4)
+    el = np.take_along_axis(mesh.elements, perms, axis=1).astype(np.int32)
+    return KuhnMesh(n=mesh.n, coordinates=mesh.coordinates, elements=el,
+                    dirichlet=mesh.dirichlet, neumann=mesh.neumann)

@@ -200,8 +200,11 @@ hdg_status hdg_face_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, const 
  * Every block of H and every entry of F is written; off-diagonal blocks have one
  * contributing element, diagonal blocks and F entries at most two, summed in an
  * order-independent way, so results are bitwise reproducible.
- * Errors: HDG_ERR_INVALID_ARG.  Tau validity is the caller's contract (not checked
- * on the device; hdg_check_tau checks it). */
+ * Errors: HDG_ERR_INVALID_ARG; HDG_ERR_SINGULAR when the mesh has no Dirichlet face and
+ * c == 0 at every volume point (Section 1: constants then solve the homogeneous system).
+ * That check runs only for meshes without Dirichlet faces; it reads one flag back and so
+ * synchronises the stream (such a call is not graph-capturable).  Tau validity is the
+ * caller's contract (not checked on the device; hdg_check_tau checks it). */
 hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                  const double* d_c, const double* d_f, const double* d_tau, double* d_H,
                                  double* d_F, double* d_factors, void* stream);
@@ -322,7 +325,8 @@ hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, 
  *   d_X       double [nelt][4 d3][4 d2 + 1]  X, kept for hdg_recover_ir (may be NULL);
  *             hdg_ir_store_len gives 4 d3 (4 d2 + 1)
  *   d_sweeps  int32 [nelt]  sweeps used per element (may be NULL)
- * Errors: HDG_ERR_UNSUPPORTED_DEGREE (k = 0 or 4), HDG_ERR_INVALID_ARG.
+ * Errors: HDG_ERR_UNSUPPORTED_DEGREE (k = 0 or 4), HDG_ERR_INVALID_ARG, HDG_ERR_SINGULAR (as
+ * for hdg_assemble_condense).
  * ------------------------------------------------------------------------------ */
 hdg_status hdg_ir_store_len(const hdg_disc* disc, int64_t* n);
 hdg_status hdg_assemble_condense_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
@@ -407,7 +411,8 @@ hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* 
  * batch.  Two items must not share an output array (their writes would race).  It
  * allocates the device work lists, one stream per degree and the capture objects
  * (set-up, not a compute call).  Errors: HDG_ERR_INVALID_ARG (n < 1, NULL arrays, an
- * unexpanded mesh, nq != k + 2), HDG_ERR_DEVICE.
+ * unexpanded mesh, nq != k + 2), HDG_ERR_SINGULAR (an item as in hdg_assemble_condense;
+ * checked here, on the null stream), HDG_ERR_DEVICE.
  * ------------------------------------------------------------------------------ */
 typedef struct {
   const hdg_disc* disc;      /* degree and tables (nq = k + 2) */

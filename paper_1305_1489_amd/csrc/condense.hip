@@ -556,6 +556,38 @@ hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_ite
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "batched condensation: unsupported degree");
 }
 
+// ---- the one singular configuration of the method (Section 1: the system has a unique
+// solution when kappa > 0, c >= 0 and tau_K is not identically zero on any K, unless there is
+// no Dirichlet face and c vanishes everywhere: then every constant trace with u = const,
+// q = 0 solves the homogeneous system).  The flag is a file-scope device variable, so the
+// check allocates nothing; it is cleared by a kernel, not a memset.
+__device__ int g_reaction_positive;
+
+__global__ void k_flag_clear() { g_reaction_positive = 0; }
+
+__global__ void k_any_positive(const double* __restrict__ c, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (c[i] > 0.0) g_reaction_positive = 1;  // every writer stores the same value
+}
+
+hdg_status check_not_singular(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_c, hipStream_t s,
+                              const char* who) {
+  if (mesh->ndir > 0) return HDG_OK;
+  const int64_t n = mesh->nelt * (int64_t)disc->host.nqd;
+  k_flag_clear<<<1, 1, 0, s>>>();
+  k_any_positive<<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, s>>>(d_c, n);
+  HDG_CHECK_LAUNCH("k_any_positive");
+  int flag = 0;
+  hipError_t e = hipMemcpyFromSymbolAsync(&flag, HIP_SYMBOL(g_reaction_positive), sizeof(int), 0,
+                                          hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return check_hip(e, who);
+  if (!flag)
+    return set_error(HDG_ERR_SINGULAR, std::string(who) +
+                                           ": no Dirichlet face and c == 0 at every point: constants span the kernel");
+  return HDG_OK;
+}
+
 hdg_status check_disc_mesh(const hdg_disc* disc, const hdg_mesh* mesh, const char* who) {
   if (!disc || !mesh) return set_error(HDG_ERR_INVALID_ARG, std::string(who) + ": NULL handle");
   if (disc->host.nq != disc->host.k + 2)
@@ -577,6 +609,8 @@ extern "C" hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh
   if (st) return st;
   if (!d_kappa || !d_c || !d_f || !d_tau || !d_H || !d_F)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense: NULL array");
+  st = check_not_singular(disc, mesh, d_c, (hipStream_t)stream, "hdg_assemble_condense");
+  if (st) return st;
   return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
                            nullptr, (hipStream_t)stream);
 }
@@ -599,6 +633,8 @@ extern "C" hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_m
   hdg_condense_workspace_size(disc, mesh, &need);
   if (need && (!d_ws || ws_bytes < need))
     return set_error(HDG_ERR_WORKSPACE, "hdg_assemble_condense_ws: workspace too small");
+  st = check_not_singular(disc, mesh, d_c, (hipStream_t)stream, "hdg_assemble_condense_ws");
+  if (st) return st;
   return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
                            nullptr, (hipStream_t)stream, need ? (double*)d_ws : nullptr);
 }

@@ -387,6 +387,8 @@ extern "C" hdg_status hdg_assemble_condense_ir(const hdg_disc* disc, const hdg_m
   if (!d_kappa || !d_c || !d_f || !d_tau || !d_H || !d_F || max_sweeps < 1 || max_sweeps > 20)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense_ir: NULL array or max_sweeps outside 1..20");
   hipStream_t s = (hipStream_t)stream;
+  st = check_not_singular(disc, mesh, d_c, s, "hdg_assemble_condense_ir");
+  if (st) return st;
   const int64_t n = mesh->nelt;
   switch (disc->host.k) {
     case 1: return run_ir<1>(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_X, max_sweeps, d_sweeps, nullptr, n, nullptr, nullptr, s);

@@ -32,6 +32,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The copy's LDS writes arrive through the vector-memory return path, not the LDS queue of
+// the wavefront, so nothing orders them after LDS reads and writes that the wavefront issued
+// earlier and that are still in flight; the compiler inserts no wait for that hazard (a
+// wavefront-scope fence emits none, and it may leave loads of the destination outstanding
+// when it schedules their consumers later).  Every copy therefore first drains the
+// wavefront's LDS traffic, so that a buffer read just before it (the Gram weights before
+// the divergence tables land in the same space) is read before it is overwritten.
+__device__ __forceinline__ void lds_drain() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // Asynchronous copy of an element-independent table (N doubles, N even, 16-byte aligned)
 // from global memory straight into LDS, 1 KB per wavefront instruction and no registers:
 // lane t of copy i moves doubles 128 i + 2t, +1 (clamped to the table, so the source is
@@ -41,6 +50,7 @@ template <int N>
 __device__ __forceinline__ void lds_stage(const double* __restrict__ src, double* dst, int lane) {
   static_assert(N % 2 == 0, "tables are staged in pairs of doubles");
   constexpr int NI = (N * 8 + 1023) / 1024;
+  lds_drain();
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int o = min(128 * i + 2 * lane, N - 2);
@@ -51,11 +61,13 @@ template <int N>
 constexpr int lds_stage_bytes() { return (N * 8 + 1023) / 1024 * 1024; }
 // The same copy shared by the NW wavefronts of a workgroup (wavefront w issues copies
 // w, w + NW, ...); every wavefront awaits its own copies with lds_stage_wait() and the
-// workgroup then synchronises.
+// workgroup then synchronises.  The other wavefronts' reads of the destination must be
+// ordered before the copy by a workgroup barrier, as for any LDS write.
 template <int N, int NW>
 __device__ __forceinline__ void lds_stage_wg(const double* __restrict__ src, double* dst, int wave, int lane) {
   static_assert(N % 2 == 0, "tables are staged in pairs of doubles");
   constexpr int NI = (N * 8 + 1023) / 1024;
+  lds_drain();
   for (int i = wave; i < NI; i += NW) {
     const int o = min(128 * i + 2 * lane, N - 2);
     __builtin_amdgcn_global_load_lds(src + o, (__attribute__((address_space(3))) void*)(dst + 128 * i), 16, 0, 0);

@@ -370,3 +370,67 @@ def test_paper_rates_recompute():
         e = t[a]
         got = [math.log(e[i] / e[i + 1]) / math.log(e[i + 1] / e[i + 2]) for i in range(2)]
         assert np.allclose(got, printed, atol=0.011), (a, got, printed)
+
+
+# ----------------------------------------------------------------------------- all face permutations, tau edge cases
+def _permuted(n=3, seed=5):
+    from hdg_inputs import permute_element_vertices
+    base = kuhn_mesh(n, jitter=0.15, seed=seed, dirichlet_sides=("x0", "x1", "z0"), neumann_sides=("y0", "y1", "z1"))
+    return permute_element_vertices(base, seed=seed)
+
+
+def test_permuted_mesh_all_pairs_and_face_maps():
+    """With elements listed in seeded even vertex orders every (local face l, perm mu) pair
+    of eq 2.2-2.3 occurs, and eq 2.3 holds at the reference vertices for each of them."""
+    ex = _ex(_permuted())
+    assert np.all(ex.volume > 0)
+    assert len({(l, int(ex.perm[K, l])) for K in range(ex.nelt) for l in range(4)}) == 24
+    Fmu = [lambda s, t: (s, t), lambda s, t: (t, s), lambda s, t: (t, 1 - s - t),
+           lambda s, t: (s, 1 - s - t), lambda s, t: (1 - s - t, s), lambda s, t: (1 - s - t, t)]
+    phiK = [lambda s, t: (s, t, 0), lambda s, t: (s, 0, t), lambda s, t: (0, s, t), lambda s, t: (s, t, 1 - s - t)]
+    for K in range(ex.nelt):
+        v = ex.coordinates[ex.elements[K]]
+        B = np.stack([v[1] - v[0], v[2] - v[0], v[3] - v[0]], axis=1)
+        for l in range(4):
+            w = ex.coordinates[ex.faces[ex.facebyele[K, l]]]
+            for (s, t) in ((0, 0), (1, 0), (0, 1), (0.2, 0.3)):
+                ss, tt = Fmu[ex.perm[K, l] - 1](s, t)
+                assert np.allclose(w[0] + ss * (w[1] - w[0]) + tt * (w[2] - w[0]),
+                                   v[0] + B @ np.array(phiK[l](s, t), dtype=float), atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_polynomial_reproduction_permuted_mesh(k):
+    """Exact reproduction (Section 8, last paragraph) on the permuted-vertex mesh: the face
+    integrals see every relative face orientation."""
+    ex = _ex(_permuted(seed=11))
+    pb = polynomial_problem(k, seed=k, kappa=2.0, c=1.0, c_linear=True)
+    out = G.solve_problem(ex, pb, k)
+    err = G.errors(ex, pb, k, out["q"], out["u"], out["uhat"], out["ustar"])
+    assert err["e_u"] < 1e-11 and err["e_uhat"] < 1e-11 and err["e_star"] < 1e-11, err
+    if k:
+        assert err["e_q"] < 1e-11, err
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_tau_zero_on_three_faces(k):
+    """Section 1 allows tau_K to vanish on all faces of K but one.  With c = 0 the local
+    problem then rests on that one face: the system stays uniquely solvable (H_II SPD),
+    polynomial solutions are still reproduced, and the constant trace still lies in the
+    kernel of every C^K (tau only enters through T_l)."""
+    m = kuhn_mesh(3, jitter=0.1, seed=4, dirichlet_sides=("x0", "x1"), neumann_sides=("y0", "y1", "z0", "z1"))
+    ex = _ex(m)
+    rng = np.random.default_rng(7)
+    tau = np.zeros((ex.nelt, 4))
+    tau[np.arange(ex.nelt), rng.integers(0, 4, size=ex.nelt)] = rng.uniform(0.5, 2.0, size=ex.nelt)
+    pb = polynomial_problem(k, seed=k, kappa=2.0, c=0.0)
+    pb.tau = tau
+    out = G.solve_problem(ex, pb, k)
+    err = G.errors(ex, pb, k, out["q"], out["u"], out["uhat"], out["ustar"])
+    assert err["e_u"] < 1e-11 and err["e_uhat"] < 1e-11, err
+    d2 = basis.dim2(k)
+    one = np.zeros(4 * d2)
+    one[::d2] = 1.0  # coefficient 1 on the constant mode of every face (orthonormal D, D_1 = 1)
+    z = _const_problem(kappa=1.5, c=0.0, f=0.0, tau=tau)
+    C, _ = L.condense(L.local_blocks(ex, z, L.rules(k)))
+    assert np.abs(C @ one).max() < 1e-12 * np.abs(C).max()
