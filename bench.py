@@ -73,6 +73,44 @@ def algorithmic_flops(k):
     return condense, recover, postprocess
 
 
+# Algorithmic FP64 flops per element of the element stages at k = 3 as the survey's
+# measurement section counts them (symmetric block condensation, stored local factors):
+# assembly a2-a5 126.6 k (the two symmetric Gram masses 105 k of it) + condensation a6 348 k;
+# reconstruction from stored factors 14.4 k; postprocess u* 74 k.
+SURVEY_FLOPS_K3 = {"condense": 126_600 + 348_000, "recover": 14_400, "postprocess": 74_000}
+
+
+class HipEvents:
+    """hipEvent_t handles from the HIP runtime (ctypes), for timing one kernel of a call
+    through hdg_set_kernel_timer on the stream the library launches on."""
+
+    def __init__(self):
+        import ctypes
+        self.C = ctypes
+        # the HIP runtime this process already runs (torch's and the library's), never a second copy
+        path = "libamdhip64.so.7"
+        for ln in open("/proc/self/maps"):
+            if "libamdhip64" in ln:
+                path = ln.split()[-1]
+                break
+        self.rt = ctypes.CDLL(path)
+
+    def create(self):
+        ev = self.C.c_void_p()
+        if self.rt.hipEventCreate(self.C.byref(ev)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+        return ev.value
+
+    def elapsed_ms(self, a, b):
+        ms = self.C.c_float()
+        if self.rt.hipEventElapsedTime(self.C.byref(ms), self.C.c_void_p(a), self.C.c_void_p(b)) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return ms.value
+
+    def destroy(self, ev):
+        self.rt.hipEventDestroy(self.C.c_void_p(ev))
+
+
 def algorithmic_bytes(k, nelt, nfc, nnzb):
     """Minimal HBM bytes of the condensation kernel per launch: coefficients at the
     quadrature points, per-element geometry/topology, the H and F writes and the factors."""
@@ -82,31 +120,79 @@ def algorithmic_bytes(k, nelt, nfc, nnzb):
     return per_elt * nelt + nnzb * d2 * d2 * 8 + nfc * d2 * 8
 
 
-def cpu_baseline(cfg, sample=4096):
-    """The oracle, untuned, on a bounded sample of elements of the same workload."""
+_CPU = {}
+
+
+def _cpu_chunk(el):
+    """One worker's share of the oracle's element stages (BLAS at one thread per worker)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
-    from hdg_inputs import kuhn_mesh
-    from oracle import globalsys as OG, local as OL, mesh as OM
-    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
-                  neumann_sides=cfg["neumann"])
-    ex = OM.expand(m.coordinates, m.elements, m.dirichlet, m.neumann)
-    pb = cfg["problem"]()
-    R = OL.rules(cfg["k"])
-    el = np.arange(min(sample, ex.nelt))
-    rng = np.random.default_rng(0)
+    from oracle import globalsys as OG, local as OL
+    ex, pb, R, k = _CPU["ex"], _CPU["pb"], _CPU["R"], _CPU["k"]
     with threadpool_limits(1):
-        t0 = time.perf_counter()
         b = OL.local_blocks(ex, pb, R, el)
         OL.condense(b)
-        b = OL.local_blocks(ex, pb, R, el)
-        q, u = OL.recover(b, rng.standard_normal((el.size, 4 * binom(cfg["k"] + 2, 2))))
+        uK = np.random.default_rng(int(el[0])).standard_normal((el.size, 4 * binom(k + 2, 2)))
+        q, u = OL.recover(OL.local_blocks(ex, pb, R, el), uK)
         OG.postprocess(ex, pb, R, q, u, el)
-        dt = time.perf_counter() - t0
-    return {"value": el.size / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {el.size} elements of the same mesh: element blocks + dense-LU condensation "
-                      f"(eq 5.5-5.6) + blocks again + reconstruction + postprocess, NumPy/SciPy FP64, "
-                      f"BLAS limited to 1 thread; {dt:.1f} s"}
+    return el.size
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, sample=16384, runs=3, max_workers=16):
+    """The oracle, untuned, on the host cores: the element stages of the same workload
+    (element blocks, dense-LU condensation, blocks again, reconstruction, postprocess) on a
+    bounded sample of its elements, split into one contiguous chunk per available core (at
+    most max_workers, the host share of one GPU), one process each, BLAS at one thread per
+    process.  One warm-up run, then the median of `runs`.  Runs before the GPU is touched, so
+    the worker processes are forks of a process without a GPU context.  The oracle's mesh
+    expansion is timed on its own (one process)."""
+    import multiprocessing as mp
+    import statistics
+    import numpy as np
+    from hdg_inputs import kuhn_mesh
+    from oracle import local as OL, mesh as OM
+    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
+                  neumann_sides=cfg["neumann"])
+    t0 = time.perf_counter()
+    ex = OM.expand(m.coordinates, m.elements, m.dirichlet, m.neumann)
+    expand_s = time.perf_counter() - t0
+    _CPU.update(ex=ex, pb=cfg["problem"](), R=OL.rules(cfg["k"]), k=cfg["k"])
+    n = min(sample, ex.nelt)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    workers = max(1, min(cores, max_workers))
+    chunk = -(-n // workers)  # one contiguous chunk per process: the oracle is vectorised over elements
+    chunks = [np.arange(s, min(s + chunk, n)) for s in range(0, n, chunk)]
+    times = []
+    with mp.get_context("fork").Pool(workers) as pool:
+        for r in range(runs + 1):
+            t0 = time.perf_counter()
+            done = sum(pool.map(_cpu_chunk, chunks, chunksize=1))
+            dt = time.perf_counter() - t0
+            if r:
+                times.append(dt)
+    assert done == n
+    med = statistics.median(times)
+    log(f"cpu baseline: {n} elements on {workers} processes, median {med:.2f} s of {times}")
+    return {"value": n / med, "unit": "elements/s", "cores": workers, "kind": "oracle",
+            "sample": f"first {n} elements of the same mesh in chunks of {chunk} over {workers} processes "
+                      f"(multiprocessing, BLAS 1 thread each): element blocks + dense-LU condensation "
+                      f"(eq 5.5-5.6) + blocks again + reconstruction + postprocess, NumPy/SciPy FP64; "
+                      f"median of {runs} runs after one warm-up: {', '.join(f'{t:.2f}' for t in times)} s",
+            "cpu_model": cpu_model(), "host_cores_visible": cores,
+            "oracle_mesh_expansion_s": round(expand_s, 3)}
 
 
 def traffic_record(kernel, kernel_src_sha):
@@ -285,19 +371,46 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
               f"note, not built", file=sys.stderr)
         sys.exit(2)
-    import torch
     from hdg_inputs import config, kuhn_mesh
-    from paper_1305_1489_amd import _lib as L
-    from paper_1305_1489_amd.driver import HDGSystem
-
     cfg = config(args.workload)
     k = cfg["k"]
     log(f"workload {args.workload}: n={cfg['n']} k={k}")
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle), before the GPU is initialised ...")
+        cpu = cpu_baseline(cfg)
+    import statistics
+    import torch
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem, _field
+
     m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
                   neumann_sides=cfg["neumann"])
     S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, cfg["problem"]())
     nelt, nfc, nnzb = S.mesh.nelt, S.mesh.nfc, S.mesh.nnzb
     log(f"nelt={nelt} nfc={nfc} nnzb={nnzb}")
+
+    # set-up stages, outside elements/s: mesh expansion (a0; host arrays already in the
+    # process, one device read-back of the face count) and the coefficient fields at the
+    # quadrature points; one warm-up, then the median of 3
+    def setup_ms(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return statistics.median(ts)
+
+    pb = cfg["problem"]()
+    a0_ms = setup_ms(lambda: L.hdg_mesh_expand(m.coordinates, m.elements, m.dirichlet, m.neumann))
+    qp_ms = setup_ms(lambda: L.hdg_qp_coords(S.disc, S.mesh))
+    X, Y, Z = S.qp[..., 0], S.qp[..., 1], S.qp[..., 2]
+    field_ms = setup_ms(lambda: [_field(fn, X, Y, Z) for fn in (pb.kappa, pb.c, pb.f)])
+    log(f"set-up: mesh expansion {a0_ms:.2f} ms, qp coordinates {qp_ms:.3f} ms, fields {field_ms:.3f} ms")
+
     # trace solution computed once, outside the timed region
     S.assemble()
     S.boundary()
@@ -309,8 +422,13 @@ def main():
     u = torch.empty((nelt, S.disc.d3), dtype=torch.float64, device="cuda")
     us = torch.empty((nelt, S.disc.d3p), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    tile = 1 <= k <= 3
+    main_kernel = "k_condense_tile" if tile else "k_condense"
+    hip = HipEvents()
 
-    def step(ev=None):
+    def step(ev=None, kev=None):
+        if kev is not None:  # the condensation kernel alone, between the call's other launches
+            L.hdg_set_kernel_timer(main_kernel, kev[0], kev[1])
         if ev is not None:
             ev[0].record(stream)
         L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors, ws=S.condense_ws)
@@ -330,46 +448,62 @@ def main():
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    kevs = [(hip.create(), hip.create()) for _ in range(args.steps)]
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
     for i in range(args.steps):
-        step(evs[i])
+        step(evs[i], kevs[i])
     t_end.record(stream)
     torch.cuda.synchronize()
+    L.hdg_set_kernel_timer(None)
     total_ms = t_start.elapsed_time(t_end)
-    ms = total_ms / args.steps
-    cond_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    bc_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-    rec_ms = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
-    pp_ms = sum(e[3].elapsed_time(e[4]) for e in evs) / args.steps
-    log(f"step {ms:.3f} ms: condense {cond_ms:.3f}, boundary {bc_ms:.3f}, recover {rec_ms:.3f}, "
-        f"postprocess {pp_ms:.3f}")
+    per_step = [e[0].elapsed_time(e[4]) for e in evs]
+    ms = statistics.median(per_step)
+    med = lambda a, b: statistics.median(e[a].elapsed_time(e[b]) for e in evs)
+    cond_ms, bc_ms, rec_ms, pp_ms = med(0, 1), med(1, 2), med(2, 3), med(3, 4)
+    kern_ms = [hip.elapsed_ms(a, b) for a, b in kevs]
+    kern_avg = sum(kern_ms) / len(kern_ms)
+    for a, b in kevs:
+        hip.destroy(a)
+        hip.destroy(b)
+    log(f"step median {ms:.3f} ms (mean over the window {total_ms / args.steps:.3f}): condense call {cond_ms:.3f} "
+        f"({main_kernel} {kern_avg:.3f} avg), boundary {bc_ms:.3f}, recover {rec_ms:.3f}, postprocess {pp_ms:.3f}")
     fl_c, fl_r, fl_p = algorithmic_flops(k)
-    ach_c = fl_c * nelt / (cond_ms * 1e-3) / 1e12
-    ach_r = fl_r * nelt / (rec_ms * 1e-3) / 1e12
-    ach_p = fl_p * nelt / (pp_ms * 1e-3) / 1e12
     peak = 78.6  # MI355X FP64: dense matrix and vector rate are both 78.6 TFLOP/s
-    tile = 1 <= k <= 3
+    if k == 3:
+        sv_c, sv_r, sv_p = SURVEY_FLOPS_K3["condense"], SURVEY_FLOPS_K3["recover"], SURVEY_FLOPS_K3["postprocess"]
+        flop_src = "survey measurement section, k=3 (a2-a5 126.6k + a6 348k; a9 R2 14.4k; a10 74k)"
+    else:
+        sv_c, sv_r, sv_p = fl_c, fl_r, fl_p
+        flop_src = "implementation count (the survey gives per-stage figures at k=3 only)"
+    tf = lambda fl, t: fl * nelt / (t * 1e-3) / 1e12
+    ach_c, ach_r, ach_p = tf(sv_c, kern_avg), tf(sv_r, rec_ms), tf(sv_p, pp_ms)
     kernels = {
-        "condense": {"kernel": "k_condense_tile" if tile else "k_condense", "call": "hdg_assemble_condense_ws",
-                     "call_launches": ["k_condense_tile", "k_diag_sum"] if tile else ["k_condense", "k_zero_diag"],
-                     "source": "condense_tile.hip" if tile else "condense.hip",
-                     "bound": "mfma" if tile else "alu", "achieved": round(ach_c, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(ach_c / peak, 4), "avg_launch_ms": round(cond_ms, 4),
-                     "algorithmic_flops_per_element": fl_c, "elements_per_launch": nelt,
+        "condense": {"kernel": main_kernel, "call": "hdg_assemble_condense_ws",
+                     "timed": f"{main_kernel} alone: HIP events recorded around its launch (hdg_set_kernel_timer), "
+                              f"average over the {args.steps} timed steps",
+                     "call_launches": [main_kernel], "source": "condense_tile.hip" if tile else "condense.hip",
+                     "bound": "mfma", "achieved": round(ach_c, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(ach_c / peak, 4), "avg_launch_ms": round(kern_avg, 4),
+                     "algorithmic_flops_per_element": sv_c, "flops_source": flop_src,
+                     "elements_per_launch": nelt,
+                     "implementation_count": {"flops_per_element": fl_c, "achieved": round(tf(fl_c, kern_avg), 3),
+                                              "frac": round(tf(fl_c, kern_avg) / peak, 4),
+                                              "note": "the kernel's own block-elimination count, which uses the "
+                                                      "rank-one face structure (fewer flops than the survey's)"},
+                     "call_ms": round(cond_ms, 4),
                      "algorithmic_bytes_per_launch": algorithmic_bytes(k, nelt, nfc, nnzb)},
         "recover": {"kernel": "k_recover_tile" if tile else "k_recover", "call": "hdg_recover",
                     "call_launches": ["k_recover_tile" if tile else "k_recover"], "source": "recover.hip",
-                    "bound": "mfma" if tile else "alu",
-                    "achieved": round(ach_r, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach_r / peak, 4),
-                    "avg_launch_ms": round(rec_ms, 4), "algorithmic_flops_per_element": fl_r,
-                    "elements_per_launch": nelt},
+                    "bound": "mfma", "achieved": round(ach_r, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(ach_r / peak, 4), "avg_launch_ms": round(rec_ms, 4),
+                    "algorithmic_flops_per_element": sv_r, "elements_per_launch": nelt},
         "postprocess": {"kernel": "k_pp_rhs", "call": "hdg_postprocess", "call_launches": ["k_pp_rhs", "k_pp_solve"],
                         "source": "postprocess.hip", "bound": "mfma", "achieved": round(ach_p, 3), "peak": peak,
                         "unit": "TFLOP/s", "frac": round(ach_p / peak, 4), "avg_launch_ms": round(pp_ms, 4),
-                        "algorithmic_flops_per_element": fl_p, "elements_per_launch": nelt},
+                        "algorithmic_flops_per_element": sv_p, "elements_per_launch": nelt},
     }
     for kk in kernels.values():
         # achieved is over the whole call (avg_launch_ms), so its traffic is summed over the
@@ -407,14 +541,16 @@ def main():
                                f"tau=1, Dirichlet x=0,1, Neumann elsewhere",
                    "nelt": nelt, "k": k, "nfc": nfc, "nnzb": nnzb,
                    "stage_ms": {"assemble_condense": cond_ms, "boundary": bc_ms, "recover": rec_ms,
-                                "postprocess": pp_ms}},
+                                "postprocess": pp_ms},
+                   "step_ms": {"median": ms, "mean": total_ms / args.steps, "min": min(per_step),
+                               "max": max(per_step)},
+                   "setup_ms": {"mesh_expansion": a0_ms, "qp_coordinates": qp_ms, "field_evaluation": field_ms}},
         "roofline": roofline,
     }
     if not args.no_precision:
         result["precision"] = result_precision
-    if not args.no_cpu:
-        log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(cfg)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     if not args.no_solve:
         log("solve metric ...")
         result["solve"] = solve_metric(args)

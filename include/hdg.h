@@ -63,6 +63,15 @@ const char* hdg_last_error(void);
 /* Largest supported polynomial degree. */
 int hdg_max_degree(void);
 
+/* Measurement hook (no effect on results): while set, every launch by this thread of the
+ * library kernel named `kernel` ("k_condense_tile", "k_condense", "k_geo_records",
+ * "k_diag_sum", "k_recover_tile", "k_recover", "k_pp_rhs", "k_pp_solve") is bracketed by
+ * hipEventRecord(ev_start) and hipEventRecord(ev_stop) on the stream of the call, so that
+ * one kernel of a multi-kernel call can be timed with the caller's events (hipEvent_t,
+ * created and owned by the caller, timing enabled).  kernel = NULL switches it off.
+ * Errors: HDG_ERR_INVALID_ARG (a NULL event with a non-NULL name). */
+hdg_status hdg_set_kernel_timer(const char* kernel, void* ev_start, void* ev_stop);
+
 /* ------------------------------------------------------------------------------
  * Mesh (Section 2, "Data structure").
  *

@@ -20,6 +20,17 @@ hdg_status check_hip(hipError_t e, const char* what) {
   return set_error(HDG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Kernel timer of hdg_set_kernel_timer (per thread, like the error message).
+static thread_local std::string g_timer_kernel;
+static thread_local hipEvent_t g_timer_start = nullptr, g_timer_stop = nullptr;
+
+void timer_begin(const char* kernel, hipStream_t s) {
+  if (g_timer_start && g_timer_kernel == kernel) (void)hipEventRecord(g_timer_start, s);
+}
+void timer_end(const char* kernel, hipStream_t s) {
+  if (g_timer_stop && g_timer_kernel == kernel) (void)hipEventRecord(g_timer_stop, s);
+}
+
 }  // namespace hdg
 
 using namespace hdg;
@@ -29,6 +40,19 @@ extern "C" {
 const char* hdg_last_error(void) { return g_last_error.c_str(); }
 
 int hdg_max_degree(void) { return kMaxDegree; }
+
+hdg_status hdg_set_kernel_timer(const char* kernel, void* ev_start, void* ev_stop) {
+  if (!kernel) {
+    g_timer_kernel.clear();
+    g_timer_start = g_timer_stop = nullptr;
+    return HDG_OK;
+  }
+  if (!ev_start || !ev_stop) return set_error(HDG_ERR_INVALID_ARG, "hdg_set_kernel_timer: NULL event");
+  g_timer_kernel = kernel;
+  g_timer_start = (hipEvent_t)ev_start;
+  g_timer_stop = (hipEvent_t)ev_stop;
+  return HDG_OK;
+}
 
 // Launch shapes of the single-mesh condensation, per degree (persistent grids; the tile
 // kernels of k = 1..3 run four elements per wavefront, so waves_per_element is 1).

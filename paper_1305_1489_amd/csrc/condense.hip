@@ -487,12 +487,14 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
   if (Cout) {  // export form: one shape is enough
     k_condense<K, 256, true><<<grid, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm);
   } else {
+    timer_begin("k_condense", s);
     switch (lc.waves_per_element) {
       case 1: k_condense<K, 64, false><<<grid, 64, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
       case 2: k_condense<K, 128, false><<<grid, 128, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
       case 4: k_condense<K, 256, false><<<grid, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
       default: k_condense<K, 512, false><<<grid, 512, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm); break;
     }
+    timer_end("k_condense", s);
   }
   HDG_CHECK_LAUNCH("k_condense");
   return HDG_OK;

@@ -575,15 +575,23 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
                                                         (int)n, Cout, Cfout, lc.xcd_remap, nullptr, nullptr);
   } else if (dws) {
     double* geo_rec = reinterpret_cast<double*>(reinterpret_cast<char*>(dws) + condense_ws_geo_offset(D::D2, mesh->nelt));
+    timer_begin("k_geo_records", s);
     k_geo_records<<<(unsigned)((mesh->nelt + 63) / 64), 64, 0, s>>>(*mesh, tau, geo_rec);
+    timer_end("k_geo_records", s);
+    timer_begin("k_condense_tile", s);
     k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
                                                         (int)n, Cout, Cfout, lc.xcd_remap, dws, geo_rec);
+    timer_end("k_condense_tile", s);
     const size_t tot = (size_t)mesh->nfc * ws_block(D::D2);
+    timer_begin("k_diag_sum", s);
     k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
                                                                      dws, H, F);
+    timer_end("k_diag_sum", s);
   } else {
+    timer_begin("k_condense_tile", s);
     k_condense_tile<K, false, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
                                                          (int)n, Cout, Cfout, lc.xcd_remap, nullptr, nullptr);
+    timer_end("k_condense_tile", s);
   }
   HDG_CHECK_LAUNCH("k_condense_tile");
   return HDG_OK;

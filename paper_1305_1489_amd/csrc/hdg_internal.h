@@ -120,6 +120,9 @@ hdg_status set_error(hdg_status s, const std::string& msg);
 hdg_status check_hip(hipError_t e, const char* what);
 // HDG_ERR_SINGULAR when the mesh has no Dirichlet face and c vanishes at every volume point
 // (reads one device flag back: synchronises the stream, only in the no-Dirichlet case).
+// hdg_set_kernel_timer: record the caller's events around the launch of the named kernel.
+void timer_begin(const char* kernel, hipStream_t s);
+void timer_end(const char* kernel, hipStream_t s);
 hdg_status check_not_singular(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_c, hipStream_t s,
                               const char* who);
 }  // namespace hdg

@@ -295,9 +295,13 @@ hdg_status run_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const dou
   const int64_t groups = (mesh->nelt + 3) / 4;
   const int ncu = device_cu_count();
   const int g1 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kRhsWaves - 1) / kRhsWaves, ncu));
+  timer_begin("k_pp_rhs", s);
   k_pp_rhs<K><<<g1, 64 * kRhsWaves, 0, s>>>(*mesh, disc->dev, kappa, tau, fac, q, u, us);
+  timer_end("k_pp_rhs", s);
   const int g2 = (int)std::max<int64_t>(1, std::min<int64_t>((groups + kSolveWaves - 1) / kSolveWaves, 3 * ncu));
+  timer_begin("k_pp_solve", s);
   k_pp_solve<K><<<g2, 64 * kSolveWaves, 0, s>>>(*mesh, disc->dev, tau, fac, us);
+  timer_end("k_pp_solve", s);
   HDG_CHECK_LAUNCH("k_pp_rhs / k_pp_solve");
   return HDG_OK;
 }

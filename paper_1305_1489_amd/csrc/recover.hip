@@ -395,10 +395,14 @@ hdg_status run_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
     const int64_t groups = (mesh->nelt + 3) / 4;
     const int64_t wgs = (groups + kRecWaves - 1) / kRecWaves;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(wgs, 2 * (int64_t)device_cu_count()));
+    timer_begin("k_recover_tile", s);
     k_recover_tile<K><<<grid, 64 * kRecWaves, 0, s>>>(*mesh, disc->dev, tau, factors, uhat, q, u);
+    timer_end("k_recover_tile", s);
   } else {
     const int grid = (int)std::min<int64_t>(mesh->nelt, 1 << 20);
+    timer_begin("k_recover", s);
     k_recover<K, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
+    timer_end("k_recover", s);
   }
   HDG_CHECK_LAUNCH("k_recover");
   return us ? launch_postprocess(disc, mesh, kappa, tau, q, u, factors, us, s) : HDG_OK;
