@@ -321,6 +321,23 @@ hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, 
                                     const double* d_c, const double* d_f, const double* d_tau, double* d_H, double* d_F,
                                     double* d_factors, void* d_ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hdg_assemble_condense_ws with the
+ * library's own workspace instead of the caller's.  That workspace is a static device array
+ * of hdg_condense_noalloc_capacity() bytes (256 MiB), one per device the library runs on,
+ * held until the process ends; the call itself allocates nothing.  The caller still passes
+ * every input and output.  Same results as hdg_assemble_condense_ws, bit for bit.
+ * Limit: hdg_condense_workspace_size(disc, mesh) must not exceed the capacity (k = 3: up to
+ * about 108,000 elements; k = 2: 215,000; k = 1: 399,000; k = 0, 4 need none), else
+ * HDG_ERR_WORKSPACE before any launch.  Every call on a device shares that device's array
+ * and leaves it in an undefined state: calls that overlap in time on one device (two
+ * streams, two threads) race and must be serialised by the caller.  Errors: those of
+ * hdg_assemble_condense_ws. */
+hdg_status hdg_condense_noalloc_capacity(size_t* bytes);
+hdg_status hdg_assemble_condense_noalloc(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                         const double* d_c, const double* d_f, const double* d_tau, double* d_H,
+                                         double* d_F, double* d_factors, void* stream);
+
 /* ------------------------------------------------------------------------------
  * Condensation with FP32 local factorisations and FP64 iterative refinement (degrees
  * 1..3; eq 5.1-5.6, scatter of eq 6.5).

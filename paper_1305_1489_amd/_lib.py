@@ -31,7 +31,8 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_batch_condense", "hdg_batch_capture", "hdg_batch_launch", "hdg_autotune", "hdg_set_launch_config",
            "hdg_get_launch_config", "hdg_gnn_param_count", "hdg_gnn_graph_workspace_size", "hdg_gnn_build_graph",
            "hdg_gnn_workspace_size", "hdg_gnn_forward", "hdg_gnn_loss_grad", "hdg_gnn_adam", "hdg_ir_store_len",
-           "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir", "hdg_set_kernel_timer"]
+           "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir", "hdg_condense_noalloc_capacity",
+           "hdg_assemble_condense_noalloc", "hdg_set_kernel_timer"]
 
 
 class HdgError(RuntimeError):
@@ -286,6 +287,19 @@ def hdg_set_kernel_timer(kernel, ev_start=None, ev_stop=None):
     c_void_p); kernel=None switches the timer off."""
     _check(lib().hdg_set_kernel_timer(None if kernel is None else kernel.encode(), C.c_void_p(ev_start),
                                       C.c_void_p(ev_stop)))
+
+
+def hdg_condense_noalloc_capacity() -> int:
+    n = C.c_size_t(0)
+    _check(lib().hdg_condense_noalloc_capacity(C.byref(n)))
+    return n.value
+
+
+def hdg_assemble_condense_noalloc(disc: Disc, mesh: Mesh, kappa, c, f, tau, H, F, factors, stream=None):
+    """hdg_assemble_condense_ws with the library's static device workspace (no allocation)."""
+    _check(lib().hdg_assemble_condense_noalloc(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f),
+                                               _ptr(tau), _ptr(H), _ptr(F), _ptr(factors), _stream(stream)))
+    return H, F, factors
 
 
 def hdg_export_local(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, stream=None):

@@ -641,6 +641,35 @@ extern "C" hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_m
                            nullptr, (hipStream_t)stream, need ? (double*)d_ws : nullptr);
 }
 
+namespace hdg {
+hdg_status condense_static_workspace(size_t need, double** ws);
+size_t condense_scratch_capacity();
+}  // namespace hdg
+
+extern "C" hdg_status hdg_condense_noalloc_capacity(size_t* bytes) {
+  if (!bytes) return set_error(HDG_ERR_INVALID_ARG, "hdg_condense_noalloc_capacity: NULL argument");
+  *bytes = condense_scratch_capacity();
+  return HDG_OK;
+}
+
+extern "C" hdg_status hdg_assemble_condense_noalloc(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                                    const double* d_c, const double* d_f, const double* d_tau,
+                                                    double* d_H, double* d_F, double* d_factors, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_assemble_condense_noalloc");
+  if (st) return st;
+  if (!d_kappa || !d_c || !d_f || !d_tau || !d_H || !d_F || !mesh->d_face_elem)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense_noalloc: NULL array");
+  size_t need = 0;
+  hdg_condense_workspace_size(disc, mesh, &need);
+  double* ws = nullptr;
+  st = condense_static_workspace(need, &ws);
+  if (st) return st;
+  st = check_not_singular(disc, mesh, d_c, (hipStream_t)stream, "hdg_assemble_condense_noalloc");
+  if (st) return st;
+  return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
+                           nullptr, (hipStream_t)stream, ws);
+}
+
 extern "C" hdg_status hdg_export_local(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                        const double* d_c, const double* d_f, const double* d_tau,
                                        const int32_t* d_elems, int64_t n, double* d_C, double* d_Cf, void* stream) {

@@ -20,6 +20,9 @@
 // Each finished 4x4 tile of C^K is scattered straight into H (upper triangle mirrored,
 // so H stays exactly symmetric); diagonal face blocks and F take atomic adds onto zeros.
 // The factor store keeps U, Us (packed upper tiles) and f (tiles, column 0) per element.
+#include <mutex>
+#include <string>
+
 #include "tile.h"
 
 namespace hdg {
@@ -597,7 +600,52 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
   return HDG_OK;
 }
 
+// ---- the library's own workspace for callers that cannot allocate (hdg_assemble_condense_noalloc)
+//
+// A file-scope device array: the runtime gives every device the library runs on its own
+// copy when the code object is loaded, and it lives until the process ends.  In host code
+// `scratch` names a host-side stand-in, not a device address: the device address is
+// looked up per device with hipGetSymbolAddress and only that pointer is ever handed to a
+// kernel.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on each device).
+hdg_status scratch_pointer(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return check_hip(e, "hdg_assemble_condense_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices)
+    return set_error(HDG_ERR_DEVICE, "hdg_assemble_condense_noalloc: device index beyond the supported range");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return check_hip(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                "hdg_assemble_condense_noalloc: hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return HDG_OK;
+}
+
 }  // namespace
+
+size_t condense_scratch_capacity() { return kScratchBytes; }
+
+hdg_status condense_static_workspace(size_t need, double** ws) {
+  *ws = nullptr;
+  if (need > kScratchBytes)
+    return set_error(HDG_ERR_WORKSPACE, "hdg_assemble_condense_noalloc: the mesh needs " + std::to_string(need) +
+                                            " bytes of workspace, more than the library's static " +
+                                            std::to_string(kScratchBytes) + " bytes");
+  if (need == 0) return HDG_OK;
+  return scratch_pointer(ws);
+}
 
 int tile_factor_len(int k) {
   switch (k) {
