@@ -303,6 +303,60 @@ def batch_metric(args):
             "per_degree": per_k, "tuning_s": tune_s}
 
 
+def projection_metric(S, pb, hip, reps=20):
+    """The HDG projection (eq 9.13) and the L2 trace projection (eq 9.12) of the exact (q, u)
+    on the same mesh: the fields at the quadrature points are evaluated once (outside the
+    timing), then hdg_project_hdg (face moments of all faces + the element kernel) is timed.
+    Both kernels are HBM-bound; achieved bytes are the algorithmic ones (each input and
+    output moved once)."""
+    import statistics
+    import torch
+    from paper_1305_1489_amd import _lib as L
+    m, d = S.mesh, S.disc
+    faces = torch.arange(m.nfc, dtype=torch.int32, device="cuda")
+    out = []
+    for x in (S.qp, L.hdg_face_qp_coords(d, m, faces)):
+        X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+        out.append(torch.stack([c * torch.ones_like(X) for c in pb.q(X, Y, Z)] + [pb.u(X, Y, Z) * torch.ones_like(X)],
+                               dim=-1).contiguous())
+    quv, quf = out
+    Pq = torch.empty((m.nelt, 3, d.d3), dtype=torch.float64, device="cuda")
+    Pu = torch.empty((m.nelt, d.d3), dtype=torch.float64, device="cuda")
+    L.hdg_project_hdg(d, m, S.tau, quv, quf, Pq, Pu)  # warm-up
+    ws = torch.empty(m.nfc * 4 * d.d2 * 8, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    call, kern = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0, k1 = hip.create(), hip.create()
+        L.hdg_set_kernel_timer("k_hdg_projection", k0, k1)
+        e0.record(stream)
+        L.hdg_project_hdg(d, m, S.tau, quv, quf, Pq, Pu, ws=ws)
+        e1.record(stream)
+        call.append((e0, e1))
+        kern.append((k0, k1))
+    torch.cuda.synchronize()
+    L.hdg_set_kernel_timer(None)
+    call_ms = statistics.median(a.elapsed_time(b) for a, b in call)
+    kern_ms = statistics.median(hip.elapsed_ms(a, b) for a, b in kern)
+    for a, b in kern:
+        hip.destroy(a)
+        hip.destroy(b)
+    nqd, nqd2, d3, d2 = d.nqd, d.nqd2, d.d3, d.d2
+    face_bytes = m.nfc * (nqd2 * 4 + 4 * d2) * 8             # k_face_moments: data in, moments out
+    elem_bytes = m.nelt * ((nqd * 4 + 4 * d3) * 8 + 4 * 8 + 12 * 8 + 2 * 4 * 4) + m.nfc * 4 * d2 * 8
+    gbs = elem_bytes / (kern_ms * 1e-3) / 1e9
+    log(f"projection: hdg_project_hdg {call_ms:.3f} ms (k_hdg_projection {kern_ms:.3f} ms, {gbs:.0f} GB/s)")
+    return {"call": "hdg_project_hdg (k_face_moments over all faces + k_hdg_projection)",
+            "call_ms": call_ms, "elements_per_s": m.nelt / (call_ms * 1e-3),
+            "kernel": {"kernel": "k_hdg_projection", "bound": "hbm", "avg_launch_ms": kern_ms,
+                       "algorithmic_bytes_per_launch": elem_bytes, "achieved": round(gbs, 1), "peak": 8000.0,
+                       "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                       "bytes_note": "(q, u) at the volume points read once, the face moments of every face "
+                                     "read once, tau / normals / faces / perm, Pi q and Pi u written once"},
+            "face_moments_bytes_per_launch": face_bytes}
+
+
 GNN_CHECKPOINT = os.path.join(ROOT, "paper_1305_1489_amd", "checkpoints", "gnn_k2.safetensors")
 
 
@@ -364,6 +418,7 @@ def main():
     ap.add_argument("--gnn", default=None, help="checkpoint of the learned preconditioner (default: the packaged one)")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-refined condensation timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-condensation workload")
+    ap.add_argument("--no-projection", action="store_true", help="skip the HDG / trace projection timing")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -516,6 +571,9 @@ def main():
     roofline["other_kernels"] = {n: v for n, v in kernels.items() if n != dom}
     if not args.no_precision:
         result_precision = precision_metric(S, stream, cond_ms)
+    result_projection = None
+    if not args.no_projection and getattr(cfg["problem"](), "q", None) is not None:
+        result_projection = projection_metric(S, cfg["problem"](), hip)
     if args.calibrate_copy:
         x = torch.empty(args.calibrate_copy // 8, dtype=torch.float64, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
@@ -549,6 +607,8 @@ def main():
     }
     if not args.no_precision:
         result["precision"] = result_precision
+    if result_projection is not None:
+        result["projection"] = result_projection
     if cpu is not None:
         result["cpu_baseline"] = cpu
     if not args.no_solve:

@@ -65,7 +65,8 @@ int hdg_max_degree(void);
 
 /* Measurement hook (no effect on results): while set, every launch by this thread of the
  * library kernel named `kernel` ("k_condense_tile", "k_condense", "k_geo_records",
- * "k_diag_sum", "k_recover_tile", "k_recover", "k_pp_rhs", "k_pp_solve") is bracketed by
+ * "k_diag_sum", "k_recover_tile", "k_recover", "k_pp_rhs", "k_pp_solve", "k_face_moments",
+ * "k_hdg_projection") is bracketed by
  * hipEventRecord(ev_start) and hipEventRecord(ev_stop) on the stream of the call, so that
  * one kernel of a multi-kernel call can be timed with the caller's events (hipEvent_t,
  * created and owned by the caller, timing enabled).  kernel = NULL switches it off.
@@ -169,7 +170,8 @@ hdg_status hdg_disc_get_info(const hdg_disc* disc, hdg_disc_info* info);
  * "vol_w" [nqd], "tri_pts" [nqd2][2], "tri_w" [nqd2], "P" [nqd][d3], "Pgrad"
  * [3][nqd][d3], "D" [nqd2][d2], "Pface" [4][nqd2][d3], "Chat" [3][d3][d3],
  * "PP" [4][d3][d3], "DP" [6][4][d2][d3], "P1grad" [3][nqd][d3p], "Shat"
- * [6][d3p][d3p] (xx, yy, zz, xy+yx, xz+zx, yz+zy), and the zero-padded layouts of the
+ * [6][d3p][d3p] (xx, yy, zz, xy+yx, xz+zx, yz+zy), "DPtopinv" [6][4][d2][d2] (the inverse of
+ * the last d2 columns of each DP_{mu,l}, used by the HDG projection), and the zero-padded layouts of the
  * postprocess kernel: "P1grad_pad" [3][nqp][d3pp4] and "Shat_tiles" [6][ts(ts+1)/2][4][4]
  * (upper 4x4 tiles (I, N), I <= N, row by row), where nqp and d3pp4 are nqd and d3p
  * rounded up to multiples of 4 and ts = d3pp4 / 4.  *count receives the number of
@@ -337,6 +339,50 @@ hdg_status hdg_condense_noalloc_capacity(size_t* bytes);
 hdg_status hdg_assemble_condense_noalloc(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                          const double* d_c, const double* d_f, const double* d_tau, double* d_H,
                                          double* d_F, double* d_factors, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Local projections and the superconvergence diagnostics (Section 9, "Local L2
+ * projections" and "HDG projection"; eq 9.12, 9.13, 10.2).  The caller evaluates the
+ * fields at the library's quadrature points (hdg_qp_coords, hdg_face_qp_coords), as for the
+ * coefficients.
+ * ------------------------------------------------------------------------------ */
+/* L2 projection onto M_h (eq 9.12) of ncomp fields on n faces: d_vals double
+ * [n][nqd2][ncomp] holds the fields at the points of hdg_face_qp_coords of those faces (in
+ * each face's own parametrisation); d_out double [n][ncomp][d2] receives the coefficients in
+ * the orthonormal face basis (whose face mass matrix is the identity, so this is
+ * (w . D)^T v, the formula of eq 6.3).  One thread per output, nothing allocated.
+ * Errors: HDG_ERR_INVALID_ARG (NULL array, n < 0, ncomp outside 1..8). */
+hdg_status hdg_project_trace(const hdg_disc* disc, const hdg_mesh* mesh, int64_t n, int ncomp, const double* d_vals,
+                             double* d_out, void* stream);
+/* HDG projection (eq 9.13): (Pi q, Pi u) in P_k(K)^3 x P_k(K) with the moments of q and u
+ * against P_{k-1}(K) and, on every face, the moments of q.nu + tau u against P_k(e).
+ *   d_tau      double [nelt][4]       as for the condensation (not zero on all four faces)
+ *   d_qu_vol   double [nelt][nqd][4]  (q_x, q_y, q_z, u) at the points of hdg_qp_coords
+ *                                     (32-byte aligned, as every hipMalloc'd buffer is)
+ *   d_qu_face  double [nfc][nqd2][4]  the same at the points of hdg_face_qp_coords of faces
+ *                                     0..nfc-1
+ *   d_Pq       double [nelt][3][d3], d_Pu double [nelt][d3]  (layouts of hdg_recover)
+ * Workspace: hdg_project_hdg_workspace_size bytes (the face moments, [nfc][4][d2]).
+ * Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE, HDG_ERR_UNSUPPORTED_DEGREE. */
+hdg_status hdg_project_hdg_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes);
+hdg_status hdg_project_hdg(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_tau, const double* d_qu_vol,
+                           const double* d_qu_face, double* d_Pq, double* d_Pu, void* d_ws, size_t ws_bytes,
+                           void* stream);
+/* Squared norms behind eq 10.2, into d_out double[4] (device): ||Pi u - u_h||^2_Omega,
+ * ||u||^2_Omega, ||P u - uhat_h||_h^2 and ||u||_h^2 with ||v||_h^2 = sum_e |e| ||v||_e^2, so
+ * that eps_u = sqrt(out[0] / out[1]) and eps_uhat = sqrt(out[2] / out[3]).
+ *   d_Pu, d_uh  double [nelt][d3]   (hdg_project_hdg's Pi u, hdg_recover's u)
+ *   d_Puhat, d_uhat double [nfc][d2] (hdg_project_trace of u over all faces, the solution)
+ *   d_u_vol   double [nelt][nqd], d_u_face double [nfc][nqd2]: u at the quadrature points
+ *             (either may be NULL: its norm is then 0)
+ * The norms of the discrete differences use the orthonormal bases (|K| sum_i d_i^2 and
+ * |e| sum_i d_i^2); those of u use the quadrature rules of disc.  Fixed-order reductions
+ * (bitwise reproducible).  Workspace: hdg_superconvergence_norms_workspace_size bytes. */
+hdg_status hdg_superconvergence_norms_workspace_size(const hdg_mesh* mesh, size_t* bytes);
+hdg_status hdg_superconvergence_norms(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_Pu,
+                                      const double* d_uh, const double* d_u_vol, const double* d_Puhat,
+                                      const double* d_uhat, const double* d_u_face, double* d_out, void* d_ws,
+                                      size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------
  * Condensation with FP32 local factorisations and FP64 iterative refinement (degrees

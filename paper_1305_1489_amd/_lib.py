@@ -32,7 +32,9 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_get_launch_config", "hdg_gnn_param_count", "hdg_gnn_graph_workspace_size", "hdg_gnn_build_graph",
            "hdg_gnn_workspace_size", "hdg_gnn_forward", "hdg_gnn_loss_grad", "hdg_gnn_adam", "hdg_ir_store_len",
            "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir", "hdg_condense_noalloc_capacity",
-           "hdg_assemble_condense_noalloc", "hdg_set_kernel_timer"]
+           "hdg_assemble_condense_noalloc", "hdg_set_kernel_timer", "hdg_project_trace",
+           "hdg_project_hdg_workspace_size", "hdg_project_hdg", "hdg_superconvergence_norms_workspace_size",
+           "hdg_superconvergence_norms"]
 
 
 class HdgError(RuntimeError):
@@ -300,6 +302,50 @@ def hdg_assemble_condense_noalloc(disc: Disc, mesh: Mesh, kappa, c, f, tau, H, F
     _check(lib().hdg_assemble_condense_noalloc(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f),
                                                _ptr(tau), _ptr(H), _ptr(F), _ptr(factors), _stream(stream)))
     return H, F, factors
+
+
+def hdg_project_trace(disc: Disc, mesh: Mesh, vals, out=None, stream=None):
+    """eq 9.12 for the fields vals [n][nqd2][ncomp] at the face points of n faces ->
+    [n][ncomp][d2]."""
+    if vals.dim() == 2:
+        vals = vals.unsqueeze(-1)
+    n, _, ncomp = vals.shape
+    if out is None:
+        out = torch.empty((n, ncomp, disc.d2), dtype=torch.float64, device=vals.device)
+    _check(lib().hdg_project_trace(disc.handle, C.byref(mesh.struct), C.c_int64(n), C.c_int(ncomp), _ptr(vals),
+                                   _ptr(out), _stream(stream)))
+    return out
+
+
+def hdg_project_hdg(disc: Disc, mesh: Mesh, tau, qu_vol, qu_face, Pq=None, Pu=None, ws=None, stream=None):
+    """eq 9.13: (Pi q, Pi u) from (q, u) at the volume points [nelt][nqd][4] and the face
+    points of every face [nfc][nqd2][4]."""
+    n = C.c_size_t(0)
+    _check(lib().hdg_project_hdg_workspace_size(disc.handle, C.byref(mesh.struct), C.byref(n)))
+    if ws is None:
+        ws = torch.empty(max(n.value, 8), dtype=torch.uint8, device=qu_vol.device)
+    if Pq is None:
+        Pq = torch.empty((mesh.nelt, 3, disc.d3), dtype=torch.float64, device=qu_vol.device)
+    if Pu is None:
+        Pu = torch.empty((mesh.nelt, disc.d3), dtype=torch.float64, device=qu_vol.device)
+    _check(lib().hdg_project_hdg(disc.handle, C.byref(mesh.struct), _ptr(tau), _ptr(qu_vol), _ptr(qu_face),
+                                 _ptr(Pq), _ptr(Pu), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return Pq, Pu
+
+
+def hdg_superconvergence_norms(disc: Disc, mesh: Mesh, Pu, uh, Puhat, uhat, u_vol=None, u_face=None, out=None,
+                               ws=None, stream=None):
+    """The four squared norms behind eq 10.2 as a device tensor of 4 doubles."""
+    n = C.c_size_t(0)
+    _check(lib().hdg_superconvergence_norms_workspace_size(C.byref(mesh.struct), C.byref(n)))
+    if ws is None:
+        ws = torch.empty(max(n.value, 8), dtype=torch.uint8, device=Pu.device)
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=Pu.device)
+    _check(lib().hdg_superconvergence_norms(disc.handle, C.byref(mesh.struct), _ptr(Pu), _ptr(uh), _ptr(u_vol),
+                                            _ptr(Puhat), _ptr(uhat), _ptr(u_face), _ptr(out), _ptr(ws),
+                                            C.c_size_t(ws.numel()), _stream(stream)))
+    return out
 
 
 def hdg_export_local(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, stream=None):

@@ -235,6 +235,36 @@ HostTables build_tables(int k, int nq) {
           for (int r = 0; r < nqd2; ++r) s += tw[r] * Dmu[(mu * nqd2 + r) * d2 + i] * Pface[(l * nqd2 + r) * d3 + j];
           DP[(((mu * 4) + l) * d2 + i) * d3 + j] = s;
         }
+  // Inverse of the last d2 columns of each DP_{mu,l}: the face moments of the degree-k modes
+  // that are orthogonal to P_{k-1}(K).  A polynomial of P_k(K) orthogonal to P_{k-1}(K) that
+  // vanishes on a face is zero, so this d2 x d2 block is invertible (HDG projection, eq 9.13).
+  // Gauss-Jordan with partial pivoting in long double.
+  std::vector<ld> DPtopinv(24 * d2 * d2, 0);
+  for (int ml = 0; ml < 24; ++ml) {
+    std::vector<ld> a(d2 * 2 * d2, 0);
+    for (int i = 0; i < d2; ++i) {
+      for (int j = 0; j < d2; ++j) a[i * 2 * d2 + j] = DP[(ml * d2 + i) * d3 + (d3 - d2) + j];
+      a[i * 2 * d2 + d2 + i] = 1;
+    }
+    for (int c = 0; c < d2; ++c) {
+      int piv = c;
+      for (int r = c + 1; r < d2; ++r)
+        if (std::fabs(a[r * 2 * d2 + c]) > std::fabs(a[piv * 2 * d2 + c])) piv = r;
+      if (std::fabs(a[piv * 2 * d2 + c]) < 1e-12L) throw std::runtime_error("singular top-mode face block");
+      if (piv != c)
+        for (int j = 0; j < 2 * d2; ++j) std::swap(a[c * 2 * d2 + j], a[piv * 2 * d2 + j]);
+      const ld inv = 1 / a[c * 2 * d2 + c];
+      for (int j = 0; j < 2 * d2; ++j) a[c * 2 * d2 + j] *= inv;
+      for (int r = 0; r < d2; ++r)
+        if (r != c) {
+          const ld f = a[r * 2 * d2 + c];
+          if (f != 0)
+            for (int j = 0; j < 2 * d2; ++j) a[r * 2 * d2 + j] -= f * a[c * 2 * d2 + j];
+        }
+    }
+    for (int i = 0; i < d2; ++i)
+      for (int j = 0; j < d2; ++j) DPtopinv[(ml * d2 + i) * d2 + j] = a[i * 2 * d2 + d2 + j];
+  }
   const int pairs[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
   for (int pidx = 0; pidx < 6; ++pidx) {
     int h = pairs[pidx][0], g = pairs[pidx][1];
@@ -273,6 +303,7 @@ HostTables build_tables(int k, int nq) {
   o.DP = take(24 * d2 * d3);
   o.P1g = take(3 * nqd * d3p);
   o.Shat = take(6 * d3p * d3p);
+  o.DPtopinv = take(24 * d2 * d2);
   const int D3P4 = (d3 + 3) / 4 * 4, D2P4 = (d2 + 3) / 4 * 4, NQP = (nqd + 3) / 4 * 4;
   t.d3p4 = D3P4;
   t.d2p4 = D2P4;
@@ -316,6 +347,7 @@ HostTables build_tables(int k, int nq) {
   put(o.DP, DP);
   put(o.P1g, P1g);
   put(o.Shat, Shat);
+  put(o.DPtopinv, DPtopinv);
   for (int q = 0; q < nqd; ++q)
     for (int j = 0; j < d3; ++j) t.data[o.Pt + q * D3P4 + j] = (double)P[q * d3 + j];
   for (int h = 0; h < 3; ++h)

@@ -74,6 +74,10 @@ def test_tables_match_oracle(L, k):
     Dmu = np.stack([OB.eval2(k, p) for p in Fm])
     DP = np.einsum("r,mri,lrj->mlij", tw, Dmu, Pf)
     assert np.abs(T("DP").reshape(6, 4, d2, d3) - DP).max() < 1e-12
+    # the HDG projection's inverses of the top-mode columns of each DP_{mu,l} (eq 9.13)
+    Ainv = T("DPtopinv").reshape(6, 4, d2, d2)
+    prod = np.einsum("mlij,mljk->mlik", Ainv, DP[:, :, :, d3 - d2:])
+    assert np.abs(prod - np.eye(d2)).max() < 1e-10
     # postprocess tables
     G1 = OB.grad3(k + 1, vp)
     assert np.abs(T("P1grad").reshape(3, -1, d3p) - G1).max() < 1e-10
