@@ -357,6 +357,45 @@ def projection_metric(S, pb, hip, reps=20):
             "face_moments_bytes_per_launch": face_bytes}
 
 
+def bdm_metric(S, hip, flops_per_element, reps=20):
+    """The hybridized BDM element (Section 9, "BDM": tau = 0, u in P_{k-1}) on the same mesh:
+    hdg_assemble_condense_bdm, with its condensation kernel timed alone."""
+    import statistics
+    import torch
+    from paper_1305_1489_amd import _lib as L
+    if not 1 <= S.k <= 3:
+        return None
+    run = lambda: L.hdg_assemble_condense_bdm(S.disc, S.mesh, S.kappa, S.c, S.f, S.H, S.F, S.factors, ws=S.condense_ws)
+    run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    call, kern = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0, k1 = hip.create(), hip.create()
+        L.hdg_set_kernel_timer("k_condense_tile", k0, k1)
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        call.append((e0, e1))
+        kern.append((k0, k1))
+    torch.cuda.synchronize()
+    L.hdg_set_kernel_timer(None)
+    call_ms = statistics.median(a.elapsed_time(b) for a, b in call)
+    kern_ms = statistics.median(hip.elapsed_ms(a, b) for a, b in kern)
+    for a, b in kern:
+        hip.destroy(a)
+        hip.destroy(b)
+    tf = flops_per_element * S.mesh.nelt / (kern_ms * 1e-3) / 1e12
+    log(f"bdm: hdg_assemble_condense_bdm {call_ms:.3f} ms (k_condense_tile {kern_ms:.3f} ms)")
+    return {"call": "hdg_assemble_condense_bdm", "call_ms": call_ms, "elements_per_s": S.mesh.nelt / (call_ms * 1e-3),
+            "kernel": {"kernel": "k_condense_tile<k, false, true, BDM>", "bound": "mfma", "avg_launch_ms": kern_ms,
+                       "achieved": round(tf, 3), "peak": 78.6, "unit": "TFLOP/s", "frac": round(tf / 78.6, 4),
+                       "flops_per_element": flops_per_element,
+                       "flops_note": "the HDG kernel's implementation count: the BDM element runs the same "
+                                     "products with the degree-k u modes masked"}}
+
+
 GNN_CHECKPOINT = os.path.join(ROOT, "paper_1305_1489_amd", "checkpoints", "gnn_k2.safetensors")
 
 
@@ -419,6 +458,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-refined condensation timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-condensation workload")
     ap.add_argument("--no-projection", action="store_true", help="skip the HDG / trace projection timing")
+    ap.add_argument("--no-bdm", action="store_true", help="skip the hybridized BDM condensation timing")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -571,6 +611,9 @@ def main():
     roofline["other_kernels"] = {n: v for n, v in kernels.items() if n != dom}
     if not args.no_precision:
         result_precision = precision_metric(S, stream, cond_ms)
+    result_bdm = None
+    if not args.no_bdm:
+        result_bdm = bdm_metric(S, hip, fl_c)
     result_projection = None
     if not args.no_projection and getattr(cfg["problem"](), "q", None) is not None:
         result_projection = projection_metric(S, cfg["problem"](), hip)
@@ -609,6 +652,8 @@ def main():
         result["precision"] = result_precision
     if result_projection is not None:
         result["projection"] = result_projection
+    if result_bdm is not None:
+        result["bdm"] = result_bdm
     if cpu is not None:
         result["cpu_baseline"] = cpu
     if not args.no_solve:

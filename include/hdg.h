@@ -341,6 +341,21 @@ hdg_status hdg_assemble_condense_noalloc(const hdg_disc* disc, const hdg_mesh* m
                                          double* d_F, double* d_factors, void* stream);
 
 /* ------------------------------------------------------------------------------
+ * Hybridized BDM element (Section 9, "BDM"), degrees 1..3: V_h = P_k(K)^3, W_h = P_{k-1}(K),
+ * M_h as for HDG, tau = 0.  The local matrices are those of hdg_assemble_condense with tau = 0
+ * and the last d2 rows and columns of A1 (the degree-k modes of u and of its test space), the
+ * last d2 rows of A2 and Af and the last d2 columns of A3 deleted; C^K = A3 A1^{-1} A2 and
+ * Cf^K = A3 A1^{-1} Af are scattered into H and F exactly as by hdg_assemble_condense_ws
+ * (same workspace, same layouts).  The factor store records the element as BDM, so that
+ * hdg_recover returns u in P_{k-1}(K) (its degree-k coefficients zero) and q in P_k(K)^3;
+ * hdg_boundary and hdg_solve apply unchanged.  Errors: HDG_ERR_UNSUPPORTED_DEGREE (k = 0 or
+ * 4), HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE, HDG_ERR_SINGULAR (as for hdg_assemble_condense).
+ * ------------------------------------------------------------------------------ */
+hdg_status hdg_assemble_condense_bdm(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                     const double* d_c, const double* d_f, double* d_H, double* d_F,
+                                     double* d_factors, void* d_ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------------
  * Local projections and the superconvergence diagnostics (Section 9, "Local L2
  * projections" and "HDG projection"; eq 9.12, 9.13, 10.2).  The caller evaluates the
  * fields at the library's quadrature points (hdg_qp_coords, hdg_face_qp_coords), as for the

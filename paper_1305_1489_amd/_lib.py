@@ -34,7 +34,7 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir", "hdg_condense_noalloc_capacity",
            "hdg_assemble_condense_noalloc", "hdg_set_kernel_timer", "hdg_project_trace",
            "hdg_project_hdg_workspace_size", "hdg_project_hdg", "hdg_superconvergence_norms_workspace_size",
-           "hdg_superconvergence_norms"]
+           "hdg_superconvergence_norms", "hdg_assemble_condense_bdm"]
 
 
 class HdgError(RuntimeError):
@@ -346,6 +346,16 @@ def hdg_superconvergence_norms(disc: Disc, mesh: Mesh, Pu, uh, Puhat, uhat, u_vo
                                             _ptr(Puhat), _ptr(uhat), _ptr(u_face), _ptr(out), _ptr(ws),
                                             C.c_size_t(ws.numel()), _stream(stream)))
     return out
+
+
+def hdg_assemble_condense_bdm(disc: Disc, mesh: Mesh, kappa, c, f, H, F, factors, ws=None, stream=None):
+    """The hybridized BDM element (tau = 0, u in P_{k-1}) into H, F and the factor store."""
+    need = hdg_condense_workspace_size(disc, mesh)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=mesh.device)
+    _check(lib().hdg_assemble_condense_bdm(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(H),
+                                           _ptr(F), _ptr(factors), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return H, F, factors
 
 
 def hdg_export_local(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, stream=None):

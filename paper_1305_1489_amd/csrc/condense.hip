@@ -670,6 +670,30 @@ extern "C" hdg_status hdg_assemble_condense_noalloc(const hdg_disc* disc, const 
                            nullptr, (hipStream_t)stream, ws);
 }
 
+namespace hdg {
+hdg_status dispatch_condense_tile_bdm(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                                      const double* f, double* H, double* F, double* factors, double* dws,
+                                      hipStream_t s);
+}  // namespace hdg
+
+extern "C" hdg_status hdg_assemble_condense_bdm(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                                const double* d_c, const double* d_f, double* d_H, double* d_F,
+                                                double* d_factors, void* d_ws, size_t ws_bytes, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_assemble_condense_bdm");
+  if (st) return st;
+  if (disc->host.k < 1 || disc->host.k > 3)
+    return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_assemble_condense_bdm: degrees 1..3");
+  if (!d_kappa || !d_c || !d_f || !d_H || !d_F || !d_factors || !mesh->d_face_elem)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_assemble_condense_bdm: NULL array");
+  size_t need = 0;
+  hdg_condense_workspace_size(disc, mesh, &need);
+  if (!d_ws || ws_bytes < need) return set_error(HDG_ERR_WORKSPACE, "hdg_assemble_condense_bdm: workspace too small");
+  st = check_not_singular(disc, mesh, d_c, (hipStream_t)stream, "hdg_assemble_condense_bdm");
+  if (st) return st;
+  return dispatch_condense_tile_bdm(disc, mesh, d_kappa, d_c, d_f, d_H, d_F, d_factors, (double*)d_ws,
+                                    (hipStream_t)stream);
+}
+
 extern "C" hdg_status hdg_export_local(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                        const double* d_c, const double* d_f, const double* d_tau,
                                        const int32_t* d_elems, int64_t n, double* d_C, double* d_Cf, void* stream) {

@@ -41,10 +41,10 @@ struct TD {
 // thread computes its element's record into LDS, then the workgroup writes the (contiguous)
 // records of its 64 elements with coalesced stores.
 __global__ void __launch_bounds__(64) k_geo_records(hdg_mesh mesh, const double* __restrict__ tau,
-                                                    double* __restrict__ rec) {
+                                                    double* __restrict__ rec, int du_removed) {
   __shared__ double s_rec[64 * G_REC];
   const int E0 = blockIdx.x * 64, E = E0 + threadIdx.x;
-  if (E < mesh.nelt) tile_geo_record(E, mesh, tau, s_rec + threadIdx.x * G_REC);
+  if (E < mesh.nelt) tile_geo_record(E, mesh, tau, s_rec + threadIdx.x * G_REC, du_removed);
   __syncthreads();
   const int n = min(64, mesh.nelt - E0) * G_REC;
   double* out = rec + (size_t)E0 * G_REC;
@@ -58,7 +58,13 @@ __global__ void __launch_bounds__(64) k_geo_records(hdg_mesh mesh, const double*
 // they are atomic adds onto zeros.
 using gdouble = __attribute__((address_space(1))) double;
 
-template <int K, bool DWS>
+//
+// BDM selects the hybridized BDM element (Section 9, "BDM"): tau = 0 (the geometry records
+// carry T_l = 0) and u in P_{k-1}(K).  Deleting the last d2 rows and columns of A1 (the
+// degree-k modes of u and of its test space) is done by masking: those rows and columns of
+// Mc and of C_s^T (so of W and S) and those entries of f are zero, with a unit diagonal in S,
+// which decouples the removed modes (their rows of B and V vanish).
+template <int K, bool DWS, bool BDM = false>
 __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const Tables& tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
                                                       const double* __restrict__ tau, double* __restrict__ H,
@@ -215,6 +221,12 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 #pragma unroll
       for (int I = 0; I < T; ++I) fa[I] = mfma4(pv[I], yf, fa[I]);
     }
+    // BDM: u lives in the first D3U modes
+    constexpr int D3U = BDM ? D3 - D2 : D3;
+    if constexpr (BDM) {
+#pragma unroll
+      for (int I = 0; I < T; ++I) fa[I] = 4 * I + r < D3U ? fa[I] : 0.0;
+    }
     // the transposed Chat tables (element-independent) go to the weight buffer, dead from
     // here on, while the factorisations and the Z phase run
     constexpr int L3 = D3P4 * D3P4;
@@ -246,7 +258,10 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
           const bool empty = !DWS && E < 0;
           const bool unit = I == N && r == c && (4 * I + r >= D3 || empty);
           Ma[utile(I, N, T)] = unit ? 1.0 : (empty ? 0.0 : Ma[utile(I, N, T)]);
-          Sa[utile(I, N, T)] = unit ? 1.0 : (empty ? 0.0 : sv);
+          // BDM: the removed u modes get a unit diagonal and no coupling
+          const bool cut = BDM && (4 * I + r >= D3U || 4 * N + c >= D3U);
+          const bool sunit = unit || (cut && I == N && r == c);
+          Sa[utile(I, N, T)] = sunit ? 1.0 : ((empty || cut) ? 0.0 : sv);
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -296,9 +311,18 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
           const int o = (4 * J + r) * D3P4 + 4 * N + c;
           const double h0 = s_ct[o], h1 = s_ct[L3 + o], h2 = s_ct[2 * L3 + o];
           const double u = Ui[utile(J, Kk, T)];
-          acc0 = mfma4(u, geo[G_A + 0] * h0 + geo[G_A + 1] * h1 + geo[G_A + 2] * h2, acc0);
-          acc1 = mfma4(u, geo[G_A + 3] * h0 + geo[G_A + 4] * h1 + geo[G_A + 5] * h2, acc1);
-          acc2 = mfma4(u, geo[G_A + 6] * h0 + geo[G_A + 7] * h1 + geo[G_A + 8] * h2, acc2);
+          double c0 = geo[G_A + 0] * h0 + geo[G_A + 1] * h1 + geo[G_A + 2] * h2;
+          double c1 = geo[G_A + 3] * h0 + geo[G_A + 4] * h1 + geo[G_A + 5] * h2;
+          double c2 = geo[G_A + 6] * h0 + geo[G_A + 7] * h1 + geo[G_A + 8] * h2;
+          if constexpr (BDM) {  // columns of C_s^T beyond the u space of P_{k-1}
+            const bool keep = 4 * N + c < D3U;
+            c0 = keep ? c0 : 0.0;
+            c1 = keep ? c1 : 0.0;
+            c2 = keep ? c2 : 0.0;
+          }
+          acc0 = mfma4(u, c0, acc0);
+          acc1 = mfma4(u, c1, acc1);
+          acc2 = mfma4(u, c2, acc2);
         }
         Wr[0][N] = acc0;
         Wr[1][N] = acc1;
@@ -490,7 +514,7 @@ __device__ __forceinline__ void condense_tile_group(const hdg_mesh& mesh, const 
 
 // EXPORT selects the debugging form (listed elements, C^K and Cf^K written out instead of
 // scattered); the scatter form is compiled with those pointers known to be null.
-template <int K, bool EXPORT, bool DWS>
+template <int K, bool EXPORT, bool DWS, bool BDM = false>
 __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                       const double* __restrict__ cco, const double* __restrict__ fco,
                                                       const double* __restrict__ tau, double* __restrict__ H,
@@ -500,7 +524,7 @@ __global__ void __launch_bounds__(64) k_condense_tile(hdg_mesh mesh, Tables tb, 
                                                       int xcd_remap, double* __restrict__ dws,
                                                       const double* __restrict__ geo_rec) {
   for (int w0 = batch_block(xcd_remap) * 4; w0 < nwork; w0 += gridDim.x * 4)
-    condense_tile_group<K, DWS>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
+    condense_tile_group<K, DWS, BDM>(mesh, tb, kappa, cco, fco, tau, H, F, factors, EXPORT ? elems : nullptr, nwork,
                                 EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w0, dws, DWS ? geo_rec : nullptr);
 }
 
@@ -579,7 +603,7 @@ hdg_status run_condense_tile(const hdg_disc* disc, const hdg_mesh* mesh, const d
   } else if (dws) {
     double* geo_rec = reinterpret_cast<double*>(reinterpret_cast<char*>(dws) + condense_ws_geo_offset(D::D2, mesh->nelt));
     timer_begin("k_geo_records", s);
-    k_geo_records<<<(unsigned)((mesh->nelt + 63) / 64), 64, 0, s>>>(*mesh, tau, geo_rec);
+    k_geo_records<<<(unsigned)((mesh->nelt + 63) / 64), 64, 0, s>>>(*mesh, tau, geo_rec, 0);
     timer_end("k_geo_records", s);
     timer_begin("k_condense_tile", s);
     k_condense_tile<K, false, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors, elems,
@@ -633,7 +657,41 @@ hdg_status scratch_pointer(double** out) {
   return HDG_OK;
 }
 
+// The hybridized BDM element (workspace form only): records with T_l = 0 and d2 removed u
+// modes, the masked group kernel, the per-face sums.
+template <int K>
+hdg_status run_condense_tile_bdm(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                                 const double* f, double* H, double* F, double* factors, double* dws, hipStream_t s) {
+  using D = TD<K>;
+  const int64_t n = mesh->nelt, groups = (n + 3) / 4;
+  const hdg_tile_config lc = launch_config(K);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(groups, (int64_t)lc.workgroups_per_cu * device_cu_count()));
+  double* geo_rec = reinterpret_cast<double*>(reinterpret_cast<char*>(dws) + condense_ws_geo_offset(D::D2, mesh->nelt));
+  k_geo_records<<<(unsigned)((mesh->nelt + 63) / 64), 64, 0, s>>>(*mesh, nullptr, geo_rec, D::D2);
+  timer_begin("k_condense_tile", s);
+  k_condense_tile<K, false, true, true><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, c, f, nullptr, H, F, factors,
+                                                            nullptr, (int)n, nullptr, nullptr, lc.xcd_remap, dws,
+                                                            geo_rec);
+  timer_end("k_condense_tile", s);
+  const size_t tot = (size_t)mesh->nfc * ws_block(D::D2);
+  k_diag_sum<D::D2><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(mesh->d_diag, mesh->d_face_elem, (int)mesh->nfc,
+                                                                   dws, H, F);
+  HDG_CHECK_LAUNCH("k_condense_tile (BDM)");
+  return HDG_OK;
+}
+
 }  // namespace
+
+hdg_status dispatch_condense_tile_bdm(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                                      const double* f, double* H, double* F, double* factors, double* dws,
+                                      hipStream_t s) {
+  switch (disc->host.k) {
+    case 1: return run_condense_tile_bdm<1>(disc, mesh, kappa, c, f, H, F, factors, dws, s);
+    case 2: return run_condense_tile_bdm<2>(disc, mesh, kappa, c, f, H, F, factors, dws, s);
+    case 3: return run_condense_tile_bdm<3>(disc, mesh, kappa, c, f, H, F, factors, dws, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_assemble_condense_bdm: degrees 1..3");
+}
 
 size_t condense_scratch_capacity() { return kScratchBytes; }
 

@@ -94,7 +94,7 @@ __device__ inline void load_geometry(int K, const hdg_mesh& mesh, const double* 
       g.n[l][d] = nn[3 * l + d];
       s2 += g.n[l][d] * g.n[l][d];
     }
-    g.T[l] = tau[4 * K + l] * sqrt(s2);
+    g.T[l] = tau ? tau[4 * K + l] * sqrt(s2) : 0.0;  // no tau: the mixed (BDM) element
     g.mu[l] = mesh.d_perm[4 * K + l] - 1;
   }
 }
@@ -171,14 +171,18 @@ __device__ __forceinline__ int batch_block(int xcd_remap) {
 // Geometry record of one element, the layout shared by the tile condensation (which
 // precomputes it or keeps it in LDS, and stores it with the element's factors) and the
 // tile reconstruction (which reads it back).
-enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_MU = 43, G_REC = kGeoRecord };
-static_assert(G_MU + 4 <= G_REC, "geometry record layout");
+// G_DU holds the number of degree-k modes removed from the scalar space (0 for HDG, d2 for
+// the hybridized BDM element, whose u lives in P_{k-1}); the reconstruction reads it.
+enum { G_A = 0, G_DET = 9, G_VOL = 10, G_N = 11, G_T = 23, G_NN = 27, G_MU = 43, G_DU = 47, G_REC = kGeoRecord };
+static_assert(G_DU < G_REC, "geometry record layout");
 
 // The geometry record of element E (E < 0: a reference element with no data), laid out as
-// above, perm - 1 stored as small integers in doubles.  No FMA contraction here or in
+// above, perm - 1 and the removed-mode count stored as small integers in doubles; tau may be
+// NULL (T_l = 0).  No FMA contraction here or in
 // load_geometry, so that the records precomputed by k_geo_records and the ones computed
 // inline by the other forms of the condensation are the same bits.
-__device__ inline void tile_geo_record(int E, const hdg_mesh& mesh, const double* __restrict__ tau, double* rec) {
+__device__ inline void tile_geo_record(int E, const hdg_mesh& mesh, const double* __restrict__ tau, double* rec,
+                                       int du_removed = 0) {
 #pragma clang fp contract(off)
   ElemGeom g;
   if (E >= 0) {
@@ -199,6 +203,7 @@ __device__ inline void tile_geo_record(int E, const hdg_mesh& mesh, const double
       rec[G_NN + 4 * l + m] = g.n[l][0] * g.n[m][0] + g.n[l][1] * g.n[m][1] + g.n[l][2] * g.n[m][2];
   }
   for (int i = G_MU + 4; i < G_REC; ++i) rec[i] = 0.0;
+  rec[G_DU] = (double)du_removed;
 }
 
 }  // namespace hdg

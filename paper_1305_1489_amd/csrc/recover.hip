@@ -335,7 +335,14 @@ __global__ void __launch_bounds__(64 * kRecWaves, 2) k_recover_tile(hdg_mesh mes
         }
       }
     }
-    // u = S^{-1} rhs with the factors of S
+    // u = S^{-1} rhs with the factors of S.  The hybridized BDM element (record slot G_DU:
+    // d2 removed modes) has u in P_{k-1}: the removed rows of the right-hand side are dropped,
+    // and S^{-1} is the identity there, so those modes of u come out zero.
+    {
+      const int d3u = D3 - (int)geo[G_DU];
+#pragma unroll
+      for (int Kt = 0; Kt < T; ++Kt) ru[Kt] = 4 * Kt + r < d3u ? ru[Kt] : 0.0;
+    }
     double uu[T];
     {
 #pragma unroll

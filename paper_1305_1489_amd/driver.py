@@ -68,9 +68,13 @@ class HDGSystem:
                                        device=self.device)
 
     # ---- stages
-    def assemble(self, atomic=False):
-        """Condensation into H, F, factors; atomic=True selects the atomic scatter (same bits)."""
-        if atomic:
+    def assemble(self, atomic=False, method="hdg"):
+        """Condensation into H, F, factors; atomic=True selects the atomic scatter (same bits);
+        method="bdm" the hybridized BDM element (tau = 0, u in P_{k-1})."""
+        if method == "bdm":
+            L.hdg_assemble_condense_bdm(self.disc, self.mesh, self.kappa, self.c, self.f, self.H, self.F,
+                                        self.factors, ws=self.condense_ws, stream=self.stream)
+        elif atomic:
             L.hdg_assemble_condense(self.disc, self.mesh, self.kappa, self.c, self.f, self.tau, self.H, self.F,
                                     self.factors, stream=self.stream)
         else:
@@ -88,8 +92,8 @@ class HDGSystem:
         return L.hdg_recover(self.disc, self.mesh, self.kappa, self.tau, self.factors, self.uhat,
                              postprocess=postprocess, stream=self.stream)
 
-    def run(self, rtol=1e-10, precision=0):
-        self.assemble()
+    def run(self, rtol=1e-10, precision=0, method="hdg"):
+        self.assemble(method=method)
         self.boundary()
         info = self.solve(rtol=rtol, precision=precision)
         q, u, us = self.recover()
