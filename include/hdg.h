@@ -406,12 +406,16 @@ hdg_status hdg_superconvergence_norms(const hdg_disc* disc, const hdg_mesh* mesh
  * X = A1^{-1} [A2 | Af] (eq 5.2-5.4) is computed by refinement X += P(B - A1 X).  The
  * residual uses A1's block structure and runs in FP64; P is the block elimination of A1
  * (M, and the Schur complement S = Mc + tauPP + sum_s C_s M^{-1} C_s^T) with FP32
- * Cholesky factors, applied on the FP32 matrix cores.  Sweeps stop once the correction
- * is at most 1e-15 of X, or at max_sweeps (1..20).  Then C^K = A3 X_2 + tauDD and
+ * Cholesky factors, applied on the FP32 matrix cores.  Sweeps stop once every column of
+ * the right-hand side [A2 | Af] has settled (its correction at most 1e-15 of that column of
+ * X, or no longer shrinking by half while below 1e-12 of it: the FP64 rounding floor), or
+ * at max_sweeps (1..20).  Then C^K = A3 X_2 + tauDD and
  * Cf^K = A3 X_f (FP64) are scattered into H and F exactly as by hdg_assemble_condense.
  *   d_X       double [nelt][4 d3][4 d2 + 1]  X, kept for hdg_recover_ir (may be NULL);
  *             hdg_ir_store_len gives 4 d3 (4 d2 + 1)
- *   d_sweeps  int32 [nelt]  sweeps used per element (may be NULL)
+ *   d_sweeps  int32 [nelt]  sweeps used per element (may be NULL); max_sweeps + 1 marks an
+ *             element whose refinement had not met the bound after max_sweeps sweeps (its
+ *             outputs are written all the same, at the accuracy reached)
  * Errors: HDG_ERR_UNSUPPORTED_DEGREE (k = 0 or 4), HDG_ERR_INVALID_ARG, HDG_ERR_SINGULAR (as
  * for hdg_assemble_condense).
  * ------------------------------------------------------------------------------ */
@@ -481,6 +485,14 @@ hdg_status hdg_gnn_forward(const hdg_gnn_shape* shape, const float* d_params, co
 hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
                              const hdg_gnn_graph* graph, const float* d_probes, int nprobe, float* d_N,
                              double* d_loss, float* d_grad, void* d_ws, size_t ws_bytes, void* stream);
+/* z = M^{-1} r = L^{-T} G^T G L^{-1} r with G = I + N: the learned preconditioner as hdg_solve
+ * applies it (precond = 1), FP64 vectors with FP32 factors and FP64 accumulation.
+ *   d_N [nnzb][d2][d2] (hdg_gnn_forward), d_Linv [nfc][d2][d2] and d_mirror [nnzb] (the
+ *   graph), d_r and d_z double [nfc][d2] (distinct arrays).
+ * Workspace: nfc d2 doubles.  Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE. */
+hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N, const float* d_Linv,
+                                 const int32_t* d_mirror, const double* d_r, double* d_z, void* d_ws, size_t ws_bytes,
+                                 void* stream);
 /* One Adam step (step = 1, 2, ...) on n parameters. */
 hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr,
                         float beta1, float beta2, float eps, void* stream);

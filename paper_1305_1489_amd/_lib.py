@@ -34,7 +34,7 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir", "hdg_condense_noalloc_capacity",
            "hdg_assemble_condense_noalloc", "hdg_set_kernel_timer", "hdg_project_trace",
            "hdg_project_hdg_workspace_size", "hdg_project_hdg", "hdg_superconvergence_norms_workspace_size",
-           "hdg_superconvergence_norms", "hdg_assemble_condense_bdm"]
+           "hdg_superconvergence_norms", "hdg_assemble_condense_bdm", "hdg_gnn_precond_apply"]
 
 
 class HdgError(RuntimeError):
@@ -356,6 +356,17 @@ def hdg_assemble_condense_bdm(disc: Disc, mesh: Mesh, kappa, c, f, H, F, factors
     _check(lib().hdg_assemble_condense_bdm(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f), _ptr(H),
                                            _ptr(F), _ptr(factors), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
     return H, F, factors
+
+
+def hdg_gnn_precond_apply(disc: Disc, mesh: Mesh, N, Linv, mirror, r, z=None, ws=None, stream=None):
+    """z = L^{-T} G^T G L^{-1} r (G = I + N), as the learned-preconditioner PCG applies it."""
+    if z is None:
+        z = torch.empty_like(r)
+    if ws is None:
+        ws = torch.empty(mesh.nfc * disc.d2 * 8, dtype=torch.uint8, device=r.device)
+    _check(lib().hdg_gnn_precond_apply(disc.handle, C.byref(mesh.struct), _ptr(N), _ptr(Linv), _ptr(mirror), _ptr(r),
+                                       _ptr(z), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return z
 
 
 def hdg_export_local(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, stream=None):

@@ -7,7 +7,9 @@
 //     B  = [A2 | Af]  (A2 = [n_x DP^T; n_y DP^T; n_z DP^T; -tauDP^T], Af = [0; 0; 0; f])
 // X = A1^{-1} B is computed by iterative refinement:
 //     X = 0;  repeat  R = B - A1 X (FP64),  X += P(R)
-// until the correction is below 1e-15 of X (or a sweep limit).  P is the block
+// until every right-hand-side column has settled: its correction is below 1e-15 of that
+// column of X, or has stopped shrinking below 1e-12 of it (the rounding floor); a sweep
+// limit marks the element as not converged.  P is the block
 // elimination of A1 with FP32 factors:
 //     Y_s = M^{-1} R_s,   U = S^{-1} (R_u - sum_s C_s Y_s),   Q_s = Y_s + M^{-1} C_s^T U,
 //     S = Mc + tauPP + sum_s C_s M^{-1} C_s^T.
@@ -105,7 +107,8 @@ struct IrSmem {
   double wk[NQD], wc[NQD], wf[NQD];
   double M[D3 * D3], Sd[D3 * D3], Cs[3][D3 * D3], f[D3];
   double X[N4 * NR];
-  double red[2][kIrThreads / 64];
+  int flag;
+  double dprev[D::NR];  // each column's previous correction size
   // FP32, padded
   float Minv[PD * PD], Sinv[PD * PD], Wk[PD * PR], C32[3][PD * PD], G[3][PD * PD];
   float R[3][PD * PR], Ru[PD * PR], Y[3][PD * PR];
@@ -199,6 +202,7 @@ __global__ void __launch_bounds__(kIrThreads) k_condense_ir(hdg_mesh mesh, Table
 
     // ---- iterative refinement
     int sweep = 0;
+    bool converged = false;
     for (; sweep < max_sweeps; ++sweep) {
       // R = B - A1 X (FP64), stored as FP32
       for (int idx = t; idx < N4 * NR; idx += nt) {
@@ -233,37 +237,41 @@ __global__ void __launch_bounds__(kIrThreads) k_condense_ir(hdg_mesh mesh, Table
       for (int s = 0; s < 3; ++s) wg_gemm(PD, PR, PD, sm.C32[s], PD, false, sm.Y[s], PR, false, sm.Ru, PR, true, -1.f);
       wg_gemm(PD, PR, PD, sm.Sinv, PD, false, sm.Ru, PR, false, sm.Wk, PR, false, 1.f);
       for (int s = 0; s < 3; ++s) wg_gemm(PD, PR, PD, sm.G[s], PD, false, sm.Wk, PR, false, sm.Y[s], PR, true, 1.f);
-      // X += [Y; U] and the size of the correction
-      double dmax = 0, xmax = 0;
-      for (int idx = t; idx < N4 * NR; idx += nt) {
-        const int row = idx / NR, c = idx % NR, blk = row / D3, j = row % D3;
-        const double dv = blk < 3 ? (double)sm.Y[blk][j * PR + c] : (double)sm.Wk[j * PR + c];
-        const double xv = sm.X[idx] + dv;
-        sm.X[idx] = xv;
-        dmax = fmax(dmax, fabs(dv));
-        xmax = fmax(xmax, fabs(xv));
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        dmax = fmax(dmax, __shfl_xor(dmax, o));
-        xmax = fmax(xmax, __shfl_xor(xmax, o));
-      }
-      if ((t & 63) == 0) {
-        sm.red[0][t >> 6] = dmax;
-        sm.red[1][t >> 6] = xmax;
+      // X += [Y; U], and per right-hand-side column the size of the correction against the
+      // size of that column of X (one thread per column).  A column is settled once its
+      // correction is at most 1e-15 of its own scale, or once the correction stops shrinking
+      // (at least half the previous one) at a level already below 1e-12: the FP64 residual's
+      // rounding floor, about cond(A1) eps, which further sweeps cannot go below.  Every
+      // column is judged on its own scale, so a small column (f, or one face's columns) is
+      // refined as far as the large ones.
+      if (t == 0) sm.flag = 0;
+      __syncthreads();
+      for (int c = t; c < NR; c += nt) {
+        double dmax = 0, xmax = 0;
+        for (int row = 0; row < N4; ++row) {
+          const int blk = row / D3, j = row % D3, idx = row * NR + c;
+          const double dv = blk < 3 ? (double)sm.Y[blk][j * PR + c] : (double)sm.Wk[j * PR + c];
+          const double xv = sm.X[idx] + dv;
+          sm.X[idx] = xv;
+          dmax = fmax(dmax, fabs(dv));
+          xmax = fmax(xmax, fabs(xv));
+        }
+        const bool small = !(dmax > 1e-15 * xmax);
+        const bool floor_reached = sweep > 0 && dmax >= 0.5 * sm.dprev[c] && !(dmax > 1e-12 * xmax);
+        if (!small && !floor_reached) sm.flag = 1;  // every writer stores the same value
+        sm.dprev[c] = dmax;
       }
       __syncthreads();
-      double dm = 0, xm = 0;
-      for (int w = 0; w < nt / 64; ++w) {
-        dm = fmax(dm, sm.red[0][w]);
-        xm = fmax(xm, sm.red[1][w]);
-      }
+      const bool more = sm.flag != 0;
       __syncthreads();
-      if (!(dm > 1e-15 * xm)) {
+      if (!more) {
+        converged = true;
         ++sweep;
         break;
       }
     }
-    if (sweeps_out && t == 0) sweeps_out[w] = sweep;
+    // max_sweeps + 1 marks an element whose last correction still exceeded the bound
+    if (sweeps_out && t == 0) sweeps_out[w] = converged ? sweep : max_sweeps + 1;
     // ---- C^K = A3 X_2 + tauDD (upper triangle, mirrored), Cf^K = A3 X_f; scatter
     for (int idx = t; idx < M * NR; idx += nt) {
       const int a = idx / NR, b = idx % NR;

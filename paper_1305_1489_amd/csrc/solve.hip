@@ -557,3 +557,43 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
   info->iterations += used;
   return st2;
 }
+
+namespace hdg {
+namespace {
+template <int D2>
+void lpre_apply64(const hdg_mesh* mesh, const float* N, const float* Linv, const int* mirror, const double* r,
+                  double* z, double* tmp, hipStream_t s) {
+  const int nfc = (int)mesh->nfc;
+  const unsigned gf = (unsigned)((nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES);
+  constexpr unsigned TL = Lpre<D2>::THREADS;
+  k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(Linv, r, z, nfc);
+  k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, N, z, tmp, nfc);
+  k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, mirror, N, Linv, tmp, z,
+                                             nfc);
+}
+}  // namespace
+}  // namespace hdg
+
+extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N,
+                                            const float* d_Linv, const int32_t* d_mirror, const double* d_r,
+                                            double* d_z, void* d_ws, size_t ws_bytes, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_gnn_precond_apply");
+  if (st) return st;
+  if (!d_N || !d_Linv || !d_mirror || !d_r || !d_z || !mesh->d_row_ptr || !mesh->d_col_idx)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_precond_apply: NULL argument");
+  if (d_r == d_z) return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_precond_apply: r and z must not overlap");
+  const size_t need = (size_t)mesh->nfc * disc->host.d2 * sizeof(double);
+  if (!d_ws || ws_bytes < need) return set_error(HDG_ERR_WORKSPACE, "hdg_gnn_precond_apply: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  double* tmp = (double*)d_ws;
+  switch (disc->host.k) {
+    case 0: lpre_apply64<dim2(0)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 1: lpre_apply64<dim2(1)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 2: lpre_apply64<dim2(2)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 3: lpre_apply64<dim2(3)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 4: lpre_apply64<dim2(4)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_gnn_precond_apply: unsupported degree");
+  }
+  HDG_CHECK_LAUNCH("hdg_gnn_precond_apply");
+  return HDG_OK;
+}

@@ -100,6 +100,37 @@ def test_forward_loss_and_gradients_match_oracle(system):
     assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
 
 
+def test_preconditioner_apply_matches_oracle(system):
+    """The learned preconditioner as PCG applies it (k_lpre_scale, k_lpre_lower, k_lpre_upper:
+    z = L^{-T} G^T G L^{-1} r with G = I + N) against oracle/gnn.py's preconditioner_apply,
+    element by element, on a trained-looking N (random head) and a random r.  The factors are
+    FP32 on both sides (the oracle takes the GPU's FP32 L^{-1} and N), the accumulation FP64:
+    agreement to FP32 rounding of the inputs (1e-6 relative).  A wrong but SPD apply would
+    still let PCG converge, so this is checked on its own."""
+    from paper_1305_1489_amd import _lib as L
+    S, mesh, disc, H = system
+    shape = OGN.Shape(S["d2"], hidden=16, layers=2)
+    rng = np.random.default_rng(21)
+    th = (OGN.init_params(shape, seed=5) + 0.05 * rng.standard_normal(OGN.param_count(shape))).astype(np.float32)
+    gr = L.hdg_gnn_build_graph(disc, mesh, H)
+    N = L.hdg_gnn_forward((shape.d2, shape.hidden, shape.layers), torch.as_tensor(th, device="cuda"), mesh, gr)
+    nfc, d2 = S["ex"].nfc, S["d2"]
+    r = rng.standard_normal((nfc, d2))
+    z = L.hdg_gnn_precond_apply(disc, mesh, N, gr.Linv, gr.mirror, torch.as_tensor(r, device="cuda").contiguous())
+    torch.cuda.synchronize()
+    Nh = N.cpu().numpy().astype(np.float64)
+    Lh = gr.Linv.cpu().numpy().astype(np.float64)
+    zref = OGN.preconditioner_apply(Nh, Lh, r, S["rp"], S["ci"], S["er"])
+    assert rel_err(z.cpu().numpy(), zref) < 1e-6
+    assert np.abs(Nh).max() > 0  # a non-trivial factor
+    # symmetric positive definite as an operator: r.Mr > 0 and (Mr1).r2 = r1.(Mr2)
+    r2 = rng.standard_normal((nfc, d2))
+    z2 = L.hdg_gnn_precond_apply(disc, mesh, N, gr.Linv, gr.mirror, torch.as_tensor(r2, device="cuda").contiguous())
+    torch.cuda.synchronize()
+    a, b = float((z.cpu().numpy() * r2).sum()), float((z2.cpu().numpy() * r).sum())
+    assert abs(a - b) < 1e-10 * max(abs(a), 1.0) and float((z.cpu().numpy() * r).sum()) > 0
+
+
 def test_adam_step_matches_formula():
     from paper_1305_1489_amd import _lib as L
     rng = np.random.default_rng(0)

@@ -61,6 +61,7 @@ def test_precision_table_jitter_k3():
     whole = {"H": rel(c(Hir0), c(H64)), "F": rel(c(Fir0), c(F64)), "uhat": rel(c(uhir), c(S.uhat)),
              "q": rel(c(qir), c(q64)), "u": rel(c(uir), c(u64)), "ustar": rel(c(usir), c(us64))}
     sw = c(sweeps)
+    assert sw.max() <= 8, "an element's refinement did not meet the per-column bound (marked 9)"
     # oracle on sampled elements
     print("precision table: oracle sample", flush=True)
     rng = np.random.default_rng(2024)
