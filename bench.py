@@ -396,6 +396,72 @@ def bdm_metric(S, hip, flops_per_element, reps=20):
                                      "products with the degree-k u modes masked"}}
 
 
+def psweep_metric(reps=10, n=16):
+    """p-refinement (Section 10, Table 4, eq 10.3): the element hot path (the bench step:
+    condensation, boundary data, reconstruction, postprocess) at k = 0..4 on one fixed mesh
+    (Kuhn n^3, the smooth workload's data), elements/s per degree with the per-degree
+    algorithmic flops; and, on the small fixed mesh of the p-convergence test, the errors of
+    eq 10.1 from the GPU pipeline and their eq 10.3 ratios."""
+    import statistics
+    import torch
+    from hdg_inputs import kuhn_mesh, manufactured_sin_xyz
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem
+    pb = manufactured_sin_xyz("c1", "c1")
+    m = kuhn_mesh(n, dirichlet_sides=("x0", "x1"), neumann_sides=("y0", "y1", "z0", "z1"))
+    stream = torch.cuda.current_stream()
+    per_k = {}
+    for k in range(0, 5):
+        S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, pb)
+        S.assemble()
+        S.boundary()
+        S.solve(rtol=1e-10, check_every=50)
+        uh = S.uhat.clone()
+        ub = torch.empty_like(uh)
+        qq = torch.empty((m.nelt, 3, S.disc.d3), dtype=torch.float64, device="cuda")
+        uu = torch.empty((m.nelt, S.disc.d3), dtype=torch.float64, device="cuda")
+        us = torch.empty((m.nelt, S.disc.d3p), dtype=torch.float64, device="cuda")
+
+        def step():
+            S.assemble()
+            L.hdg_boundary(S.disc, S.mesh, S.uD, S.gN, S.H, S.F, ub)
+            L.hdg_recover(S.disc, S.mesh, S.kappa, S.tau, S.factors, uh, qq, uu, us, postprocess=True)
+
+        step()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            step()
+            e1.record(stream)
+            ts.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = statistics.median(a.elapsed_time(b) for a, b in ts)
+        fc, fr, fp = algorithmic_flops(k)
+        per_k[f"k{k}"] = {"ms": ms, "elements_per_s": m.nelt / (ms * 1e-3),
+                          "tflops": (fc + fr + fp) * m.nelt / (ms * 1e-3) / 1e12,
+                          "flops_per_element": fc + fr + fp, "trace_unknowns": S.mesh.nfc * S.disc.d2}
+        log(f"p-sweep k={k}: {ms:.3f} ms per step, {m.nelt / (ms * 1e-3) / 1e6:.1f} M elements/s")
+    # p-convergence from the GPU pipeline on the small fixed mesh
+    from oracle import globalsys as OG, mesh as OM
+    small = kuhn_mesh(3, jitter=0.1, seed=12, dirichlet_sides=("x0", "x1"), neumann_sides=("y0", "y1", "z0", "z1"))
+    ex = OM.expand(small.coordinates, small.elements, small.dirichlet, small.neumann)
+    errs = {a: [] for a in ("e_q", "e_u", "e_uhat")}
+    for k in range(0, 5):
+        S = HDGSystem(small.coordinates, small.elements, small.dirichlet, small.neumann, k, pb)
+        r = S.run(rtol=1e-13)
+        e = OG.errors(ex, pb, k, r["q"].cpu().numpy(), r["u"].cpu().numpy(), S.uhat.cpu().numpy())
+        for a in errs:
+            errs[a].append(e[a])
+    rat = {a: [math.log(v[i] / v[i + 1]) / math.log(v[i + 1] / v[i + 2]) for i in range(len(v) - 2)]
+           for a, v in errs.items()}
+    return {"workload": f"Kuhn {n}^3 ({m.nelt} tets), smooth data, k = 0..4; errors on the jittered n=3 mesh "
+                        f"({small.elements.shape[0]} tets)",
+            "step": "hdg_assemble_condense (+ per-face sums at k=1..3) + hdg_boundary + hdg_recover with u*",
+            "per_degree": per_k, "errors": errs, "ratios_eq_10_3": rat}
+
+
 GNN_CHECKPOINT = os.path.join(ROOT, "paper_1305_1489_amd", "checkpoints", "gnn_k2.safetensors")
 
 
@@ -459,6 +525,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-condensation workload")
     ap.add_argument("--no-projection", action="store_true", help="skip the HDG / trace projection timing")
     ap.add_argument("--no-bdm", action="store_true", help="skip the hybridized BDM condensation timing")
+    ap.add_argument("--no-psweep", action="store_true", help="skip the k = 0..4 p-refinement sweep")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -659,6 +726,9 @@ def main():
     if not args.no_solve:
         log("solve metric ...")
         result["solve"] = solve_metric(args)
+    if not args.no_psweep:
+        log("p-sweep ...")
+        result["psweep"] = psweep_metric()
     if not args.no_batch:
         log("batch metric ...")
         result["batch"] = batch_metric(args)
