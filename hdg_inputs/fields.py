@@ -283,3 +283,113 @@ def constant_rhs_problem(kappa_sigma: float, corr_len: float, field_seed: int, c
         return (z0, z0, z0)
 
     return Problem(kappa=kappa, c=c_f, f=f, uD=uD, gN=gN, tau=tau, name=f"lognormal(s={kappa_sigma},l={corr_len},seed={field_seed})")
+
+
+# --------------------------------------------------------------------------------------
+# convection-diffusion: div(q + beta u) + c u = f with q = -kappa grad u
+# --------------------------------------------------------------------------------------
+def _affine_beta(b0, Bm):
+    """beta(x) = b0 + Bm x (a tuple of three fields) and its divergence trace(Bm)."""
+    b0 = np.asarray(b0, dtype=np.float64)
+    Bm = np.asarray(Bm, dtype=np.float64)
+
+    def beta(x, y, z):
+        X = (x, y, z)
+        return tuple(b0[i] + Bm[i, 0] * X[0] + Bm[i, 1] * X[1] + Bm[i, 2] * X[2] for i in range(3))
+
+    return beta, float(np.trace(Bm))
+
+
+def convection_problem(u, grad_u, lap_u, kappa_const, beta_b0, beta_B, c, tau, name):
+    """Manufactured data for a constant kappa, an affine beta and a constant c: f and the
+    Neumann field g_N = kappa grad u - beta u, whose normal component is the total outward
+    flux -(q + beta u).nu.  ``tau`` is the stabilisation (a constant or per (element, face))."""
+    beta, divb = _affine_beta(beta_b0, beta_B)
+    kap = float(kappa_const)
+
+    def q(x, y, z):
+        g = grad_u(x, y, z)
+        return tuple(-kap * gi for gi in g)
+
+    def f(x, y, z):
+        g = grad_u(x, y, z)
+        b = beta(x, y, z)
+        uu = u(x, y, z)
+        return -kap * lap_u(x, y, z) + b[0] * g[0] + b[1] * g[1] + b[2] * g[2] + (divb + c) * uu
+
+    def gN(x, y, z):
+        g = grad_u(x, y, z)
+        b = beta(x, y, z)
+        uu = u(x, y, z)
+        return tuple(kap * g[i] - b[i] * uu for i in range(3))
+
+    p = Problem(kappa=lambda x, y, z: _full_like(x, kap), c=lambda x, y, z: _full_like(x, float(c)), f=f,
+                uD=u, gN=gN, tau=tau, u=u, q=q, name=name)
+    p.beta = beta
+    p.meta = {"beta_b0": list(map(float, beta_b0)), "beta_B": np.asarray(beta_B, dtype=float).tolist(),
+              "div_beta": divb}
+    return p
+
+
+def convection_sin_problem(beta_scale=1.0, kappa=1.0, c=1.0, tau=None) -> Problem:
+    """u = sin(xyz) with kappa constant, beta = beta_scale ((1, 0.5, -0.3) + (0.5 y, -0.4 z, 0.3 x))
+    (divergence free) and c constant; tau = 1 + max |beta| on the unit cube unless given."""
+    b0 = beta_scale * np.array([1.0, 0.5, -0.3])
+    B = beta_scale * np.array([[0.0, 0.5, 0.0], [0.0, 0.0, -0.4], [0.3, 0.0, 0.0]])
+    bmax = float(np.abs(b0).sum() + np.abs(B).sum())
+    xp = lambda a: _xp(a)
+
+    def u(x, y, z):
+        return xp(x).sin(x * y * z)
+
+    def grad_u(x, y, z):
+        cc = xp(x).cos(x * y * z)
+        return (y * z * cc, x * z * cc, x * y * cc)
+
+    def lap_u(x, y, z):
+        return -xp(x).sin(x * y * z) * ((y * z) ** 2 + (x * z) ** 2 + (x * y) ** 2)
+
+    return convection_problem(u, grad_u, lap_u, kappa, b0, B, c, 1.0 + bmax if tau is None else tau,
+                              f"convection_sin(beta x{beta_scale})")
+
+
+def convection_polynomial_problem(degree: int, seed: int = 0, kappa: float = 1.5, c: float = 1.0,
+                                  beta_scale: float = 1.0, tau=None) -> Problem:
+    """u a random polynomial of total degree <= ``degree``, constant kappa and c, affine beta
+    (seeded, with a non-zero divergence); tau = 1 + max |beta| on the unit cube unless given."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = polynomial_problem(degree, seed=seed, kappa=kappa, c=c)
+    exps, coef = base.meta["exps"], base.meta["coef"]
+    b0 = beta_scale * rng.uniform(-1.0, 1.0, size=3)
+    B = beta_scale * rng.uniform(-0.5, 0.5, size=(3, 3))
+    bmax = float(np.abs(b0).sum() + np.abs(B).sum())
+
+    def mono(x, a):
+        return x ** a if a else _full_like(x, 1.0)
+
+    def grad_u(x, y, z):
+        gx = 0.0 * x
+        gy = 0.0 * x
+        gz = 0.0 * x
+        for (a, b, g), cc in zip(exps, coef):
+            if a:
+                gx = gx + cc * a * mono(x, a - 1) * mono(y, b) * mono(z, g)
+            if b:
+                gy = gy + cc * b * mono(x, a) * mono(y, b - 1) * mono(z, g)
+            if g:
+                gz = gz + cc * g * mono(x, a) * mono(y, b) * mono(z, g - 1)
+        return (gx, gy, gz)
+
+    def lap_u(x, y, z):
+        s = 0.0 * x
+        for (a, b, g), cc in zip(exps, coef):
+            if a > 1:
+                s = s + cc * a * (a - 1) * mono(x, a - 2) * mono(y, b) * mono(z, g)
+            if b > 1:
+                s = s + cc * b * (b - 1) * mono(x, a) * mono(y, b - 2) * mono(z, g)
+            if g > 1:
+                s = s + cc * g * (g - 1) * mono(x, a) * mono(y, b) * mono(z, g - 2)
+        return s
+
+    return convection_problem(base.u, grad_u, lap_u, kappa, b0, B, c, 1.0 + bmax if tau is None else tau,
+                              f"convection_poly{degree}")

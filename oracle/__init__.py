@@ -20,6 +20,8 @@ Modules
               elimination, global solve, reconstruction (Section 6),
               postprocessing (eq 9.11) and errors (eq 10.1-10.2)
   brute       the uncondensed system eq 1.2a-e solved directly
+  convection  HDG for convection-diffusion (eq 9.1 matrices; the conservative method with the
+              numerical total flux), non-symmetric local solves and trace system
   bdm         hybridized BDM: the HDG local matrices with tau = 0 and the degree-k modes of
               u deleted (Section 9, "BDM"), condensed and uncondensed
   projection  the L2 projection onto M_h (eq 9.12), the HDG projection (eq 9.13) and the
