@@ -8,10 +8,12 @@ quadrature, no basis, no local matrices).  Both the CPU oracle and the HIP
 library's tests draw their inputs from here.
 """
 from .mesh import kuhn_mesh, KuhnMesh, permute_element_vertices
-from .fields import Problem, manufactured_sin_xyz, manufactured_sin_pi, polynomial_problem, rff_field, constant_rhs_problem
+from .fields import (Problem, manufactured_sin_xyz, manufactured_sin_pi, polynomial_problem, rff_field, constant_rhs_problem,
+                     convection_sin_problem, convection_polynomial_problem)
 from .configs import config, CONFIGS
 
 __all__ = [
     "kuhn_mesh", "KuhnMesh", "permute_element_vertices", "Problem", "manufactured_sin_xyz", "manufactured_sin_pi",
-    "polynomial_problem", "rff_field", "constant_rhs_problem", "config", "CONFIGS",
+    "polynomial_problem", "rff_field", "constant_rhs_problem", "convection_sin_problem",
+    "convection_polynomial_problem", "config", "CONFIGS",
 ]

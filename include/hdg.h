@@ -171,7 +171,8 @@ hdg_status hdg_disc_get_info(const hdg_disc* disc, hdg_disc_info* info);
  * [3][nqd][d3], "D" [nqd2][d2], "Pface" [4][nqd2][d3], "Chat" [3][d3][d3],
  * "PP" [4][d3][d3], "DP" [6][4][d2][d3], "P1grad" [3][nqd][d3p], "Shat"
  * [6][d3p][d3p] (xx, yy, zz, xy+yx, xz+zx, yz+zy), "DPtopinv" [6][4][d2][d2] (the inverse of
- * the last d2 columns of each DP_{mu,l}, used by the HDG projection), and the zero-padded layouts of the
+ * the last d2 columns of each DP_{mu,l}, used by the HDG projection), "Dmu" [6][nqd2][d2] (the
+ * face basis at F_mu(qhat_r), eq 2.2), and the zero-padded layouts of the
  * postprocess kernel: "P1grad_pad" [3][nqp][d3pp4] and "Shat_tiles" [6][ts(ts+1)/2][4][4]
  * (upper 4x4 tiles (I, N), I <= N, row by row), where nqp and d3pp4 are nqd and d3p
  * rounded up to multiples of 4 and ts = d3pp4 / 4.  *count receives the number of
@@ -428,10 +429,68 @@ hdg_status hdg_assemble_condense_ir(const hdg_disc* disc, const hdg_mesh* mesh, 
 hdg_status hdg_export_local_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_c,
                                const double* d_f, const double* d_tau, const int32_t* d_elems, int64_t n, double* d_C,
                                double* d_Cf, double* d_X, int max_sweeps, void* stream);
-/* Reconstruction from the stored X: [q; u] = X_f - X_2 uhat_K (Section 6).  Outputs as in
- * hdg_recover; the postprocess is hdg_postprocess. */
+/* Reconstruction from the stored X: [q; u] = X_f - X_2 uhat_K (Section 6), degrees 0..4 (X
+ * from hdg_assemble_condense_ir or hdg_assemble_condense_cd).  Outputs as in hdg_recover; the
+ * postprocess is hdg_postprocess. */
 hdg_status hdg_recover_ir(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_X, const double* d_uhat,
                           double* d_q, double* d_u, void* stream);
+
+/* ------------------------------------------------------------------------------
+ * Convection-diffusion (Section 9, "Matrices for convection-diffusion problems"; the
+ * element blocks of eq 9.1 with variable coefficients), degrees 0..3.
+ *   kappa^{-1} q + grad u = 0,  div(q + beta u) + c u = f,
+ * the numerical total flux q.nu + (beta.nu) uhat + tau (u - uhat) on every element boundary,
+ * u = u_D on Dirichlet faces and, on Neumann faces, the total outward flux given:
+ * -(q + beta u).nu = g_N . nu (hdg_boundary's g_N is then kappa grad u - beta u).  The local
+ * matrices are those of the diffusion element plus: -sum_s E_s^T in the u block of A1
+ * (E_s[i][j] = int_K beta_s P_i d_s P_j), +(beta.n DP_l)^T in the u rows of A2, and
+ * -(beta.n DD_l) on the diagonal blocks of C^K (int_{e_l} (beta.nu) D_i P_j and D_i D_j).
+ * The method is stable when tau >= beta.nu / 2 on every face and c + div(beta) / 2 >= 0;
+ * the caller ensures it (and a unique solution: a Dirichlet face, or c + div(beta) / 2 > 0
+ * somewhere).  H is then not symmetric: solve with hdg_solve_gmres.
+ *
+ * hdg_elem_face_qp_coords: the points phi_l^K(qhat_r) of each element's own parametrisation
+ * of its four faces (reference face l of eq 2.5 mapped by F_K):
+ *   d_xyz double [nelt][4][nqd2][3]; the caller evaluates beta there.
+ * hdg_assemble_condense_cd:
+ *   d_kappa, d_c, d_f  double [nelt][nqd]        at the points of hdg_qp_coords
+ *   d_beta_vol         double [nelt][nqd][3]     beta at the points of hdg_qp_coords
+ *   d_beta_face        double [nelt][4][nqd2][3] beta at the points of hdg_elem_face_qp_coords
+ *   d_tau              double [nelt][4]
+ * Outputs: d_H [nnzb][d2][d2] (every block written, row-major, not symmetric), d_F [nfc][d2],
+ * d_X [nelt][4 d3][4 d2 + 1] (may be NULL) X = A1^{-1} [A2 | Af] for hdg_recover_ir.
+ * The element's u Schur complement is factored by LU without pivoting (its symmetric part is
+ * positive definite under the stability condition).  Errors: HDG_ERR_INVALID_ARG,
+ * HDG_ERR_UNSUPPORTED_DEGREE (k = 4).
+ * hdg_export_local_cd: C^K [n][m][m], Cf^K [n][m] and (optional) X [n][4 d3][m + 1] of the
+ * listed elements instead of the scatter (for tests). */
+hdg_status hdg_elem_face_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, double* d_xyz, void* stream);
+hdg_status hdg_assemble_condense_cd(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
+                                    const double* d_c, const double* d_f, const double* d_beta_vol,
+                                    const double* d_beta_face, const double* d_tau, double* d_H, double* d_F,
+                                    double* d_X, void* stream);
+hdg_status hdg_export_local_cd(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_c,
+                               const double* d_f, const double* d_beta_vol, const double* d_beta_face,
+                               const double* d_tau, const int32_t* d_elems, int64_t n, double* d_C, double* d_Cf,
+                               double* d_X, void* stream);
+
+/* Restarted GMRES(restart) for the non-symmetric trace system after hdg_boundary (the paper
+ * leaves the solver open): right preconditioning by the inverses of the d2 x d2 diagonal
+ * blocks (Gauss-Jordan with partial pivoting), classical Gram-Schmidt applied twice,
+ * fixed-order reductions (the same bits on every run).  The host solves the small
+ * least-squares problem (Givens rotations) and reads one short vector per iteration; every
+ * cycle starts from the true FP64 residual b - H x, and the solve ends when
+ * ||b - H x|| <= rtol ||b|| or after max_iter inner iterations.
+ *   d_uhat  in: initial guess (Dirichlet values set by hdg_boundary); out: the solution
+ *   restart 1..64;  workspace of hdg_solve_gmres_workspace_size bytes, caller-owned
+ *   info->iterations = inner iterations, info->outer = cycles, info->rel_residual the
+ *   true relative residual.
+ * Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE, HDG_ERR_NOT_CONVERGED (the solution at
+ * max_iter is still written). */
+hdg_status hdg_solve_gmres_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, int restart, size_t* ws_bytes);
+hdg_status hdg_solve_gmres(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H, const double* d_b,
+                           double* d_uhat, double rtol, int max_iter, int restart, hdg_solve_info* info, void* d_ws,
+                           size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------------
  * Learned face-graph preconditioner for eq 6.5 (the paper leaves the solver open).

@@ -34,7 +34,9 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_assemble_condense_ir", "hdg_recover_ir", "hdg_export_local_ir", "hdg_condense_noalloc_capacity",
            "hdg_assemble_condense_noalloc", "hdg_set_kernel_timer", "hdg_project_trace",
            "hdg_project_hdg_workspace_size", "hdg_project_hdg", "hdg_superconvergence_norms_workspace_size",
-           "hdg_superconvergence_norms", "hdg_assemble_condense_bdm", "hdg_gnn_precond_apply"]
+           "hdg_superconvergence_norms", "hdg_assemble_condense_bdm", "hdg_gnn_precond_apply",
+           "hdg_elem_face_qp_coords", "hdg_assemble_condense_cd", "hdg_export_local_cd",
+           "hdg_solve_gmres_workspace_size", "hdg_solve_gmres"]
 
 
 class HdgError(RuntimeError):
@@ -665,3 +667,54 @@ def hdg_export_local_ir(disc: Disc, mesh: Mesh, kappa, c, f, tau, elems, max_swe
                                      _stream(stream)))
     return Cm, Cf, X
 
+
+
+# ----------------------------------------------------------------------------- convection-diffusion
+def hdg_elem_face_qp_coords(disc: Disc, mesh: Mesh, out=None, stream=None):
+    """Points phi_l^K(qhat_r) of every element's own parametrisation of its faces: [nelt][4][nqd2][3]."""
+    if out is None:
+        out = torch.empty((mesh.nelt, 4, disc.nqd2, 3), dtype=torch.float64, device=mesh.device)
+    _check(lib().hdg_elem_face_qp_coords(disc.handle, C.byref(mesh.struct), _ptr(out), _stream(stream)))
+    return out
+
+
+def hdg_assemble_condense_cd(disc: Disc, mesh: Mesh, kappa, c, f, beta_vol, beta_face, tau, H, F, X=None,
+                             stream=None):
+    _check(lib().hdg_assemble_condense_cd(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f),
+                                          _ptr(beta_vol), _ptr(beta_face), _ptr(tau), _ptr(H), _ptr(F), _ptr(X),
+                                          _stream(stream)))
+
+
+def hdg_export_local_cd(disc: Disc, mesh: Mesh, kappa, c, f, beta_vol, beta_face, tau, elems, want_x=False,
+                        stream=None):
+    elems = _dev(elems, torch.int32, mesh.device)
+    n = elems.numel()
+    m = disc.m
+    Cm = torch.empty((n, m, m), dtype=torch.float64, device=mesh.device)
+    Cf = torch.empty((n, m), dtype=torch.float64, device=mesh.device)
+    X = torch.empty((n, hdg_ir_store_len(disc)), dtype=torch.float64, device=mesh.device) if want_x else None
+    _check(lib().hdg_export_local_cd(disc.handle, C.byref(mesh.struct), _ptr(kappa), _ptr(c), _ptr(f),
+                                     _ptr(beta_vol), _ptr(beta_face), _ptr(tau), _ptr(elems), C.c_int64(n), _ptr(Cm),
+                                     _ptr(Cf), _ptr(X), _stream(stream)))
+    return Cm, Cf, X
+
+
+def hdg_solve_gmres_workspace_size(disc: Disc, mesh: Mesh, restart: int) -> int:
+    n = C.c_size_t()
+    _check(lib().hdg_solve_gmres_workspace_size(disc.handle, C.byref(mesh.struct), C.c_int(restart), C.byref(n)))
+    return n.value
+
+
+def hdg_solve_gmres(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=20000, restart=40, ws=None,
+                    stream=None, raise_on_fail=True):
+    need = hdg_solve_gmres_workspace_size(disc, mesh, restart)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 8), dtype=torch.uint8, device=mesh.device)
+    info = hdg_solve_info()
+    code = lib().hdg_solve_gmres(disc.handle, C.byref(mesh.struct), _ptr(H), _ptr(b), _ptr(uhat), C.c_double(rtol),
+                                 C.c_int(max_iter), C.c_int(restart), C.byref(info), _ptr(ws),
+                                 C.c_size_t(ws.numel()), _stream(stream))
+    out = {"iterations": info.iterations, "cycles": info.outer, "rel_residual": info.rel_residual, "status": code}
+    if code != 0 and raise_on_fail:
+        _check(code)
+    return out

@@ -105,7 +105,8 @@ hdg_status hdg_disc_create(int k, int nq, hdg_disc** out) {
   const double* b = d->d_tables;
   d->dev = Tables{b + o.vol_w, b + o.lambda, b + o.P, b + o.Pg, b + o.tri_w, b + o.xi, b + o.D,
                   b + o.Chat, b + o.PP, b + o.DP, b + o.P1g, b + o.Shat, b + o.Pt, b + o.ChatT,
-                  b + o.PPt, b + o.DPT, b + o.P1gt, b + o.Shatt, b + o.DPtopinv};
+                  b + o.PPt, b + o.DPT, b + o.P1gt, b + o.Shatt, b + o.DPtopinv, b + o.Pface, b + o.Dmu,
+                  b + o.tri_pts};
   d->factor_len = tile_factor_len(k) ? tile_factor_len(k) : h.d3 * (h.d3 + 1) + h.d3;
   *out = d;
   return HDG_OK;
@@ -146,6 +147,7 @@ static hdg_status table_lookup(const HostTables& h, const char* name, double* h_
       {"Chat", o.Chat, 3 * h.d3 * h.d3},      {"PP", o.PP, 4 * h.d3 * h.d3},
       {"DP", o.DP, 24 * h.d2 * h.d3},         {"P1grad", o.P1g, 3 * h.nqd * h.d3p},
       {"Shat", o.Shat, 6 * h.d3p * h.d3p},    {"DPtopinv", o.DPtopinv, 24 * h.d2 * h.d2},
+      {"Dmu", o.Dmu, 6 * h.nqd2 * h.d2},
       {"P1grad_pad", o.P1gt, 3 * h.nqp * h.d3pp4},
       {"Shat_tiles", o.Shatt, 6 * (h.d3pp4 / 4) * (h.d3pp4 / 4 + 1) / 2 * 16},
   };

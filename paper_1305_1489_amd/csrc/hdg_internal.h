@@ -37,7 +37,7 @@ inline size_t condense_ws_bytes(int d2, int64_t nelt) {
 }
 
 struct TableOffsets {
-  int vol_pts, vol_w, lambda, P, Pg, tri_pts, tri_w, xi, D, Pface, Chat, PP, DP, P1g, Shat, DPtopinv;
+  int vol_pts, vol_w, lambda, P, Pg, tri_pts, tri_w, xi, D, Pface, Chat, PP, DP, P1g, Shat, DPtopinv, Dmu;
   // zero-padded copies for the 4x4-tile kernels (dimensions rounded up to multiples of 4)
   int Pt, ChatT, PPt, DPT;
   // for the postprocess kernel: degree k+1 gradients padded, stiffness tables as upper tiles
@@ -66,6 +66,9 @@ struct Tables {
   const double* P1gt;    // [3][nqp][d3pp4]  P1g padded (d3pp4 = d3p rounded up to 4)
   const double* Shatt;   // [6][nus][16]  Shat as packed upper 4x4 tiles (nus = ts(ts+1)/2, ts = d3pp4/4)
   const double* DPtopinv;  // [6][4][d2][d2] inverse of DP_{mu,l}'s last d2 columns (eq 9.13)
+  const double* Pface;  // [4][nqd2][d3] basis at the points of reference face l (eq 2.5)
+  const double* Dmu;    // [6][nqd2][d2] face basis at F_mu(qhat_r) (eq 2.2)
+  const double* tri_pts;  // [nqd2][2] face points (s, t) on the reference triangle
 };
 
 struct HostTables {

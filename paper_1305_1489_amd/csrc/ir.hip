@@ -430,9 +430,11 @@ extern "C" hdg_status hdg_recover_ir(const hdg_disc* disc, const hdg_mesh* mesh,
   if (!d_X || !d_uhat || !d_q || !d_u) return set_error(HDG_ERR_INVALID_ARG, "hdg_recover_ir: NULL array");
   hipStream_t s = (hipStream_t)stream;
   switch (disc->host.k) {
+    case 0: return run_recover_x<0>(mesh, d_X, d_uhat, d_q, d_u, s);
     case 1: return run_recover_x<1>(mesh, d_X, d_uhat, d_q, d_u, s);
     case 2: return run_recover_x<2>(mesh, d_X, d_uhat, d_q, d_u, s);
     case 3: return run_recover_x<3>(mesh, d_X, d_uhat, d_q, d_u, s);
+    case 4: return run_recover_x<4>(mesh, d_X, d_uhat, d_q, d_u, s);
   }
-  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover_ir: degrees 1..3 only");
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover_ir: unsupported degree");
 }

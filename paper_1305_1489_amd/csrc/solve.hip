@@ -597,3 +597,269 @@ extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh
   HDG_CHECK_LAUNCH("hdg_gnn_precond_apply");
   return HDG_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// GMRES for non-symmetric trace systems (the convection-diffusion HDG): restarted GMRES(m)
+// with right block-Jacobi preconditioning (explicit inverses of the d2 x d2 diagonal blocks
+// by Gauss-Jordan with partial pivoting), classical Gram-Schmidt applied twice, fixed-order
+// reductions.  The small Hessenberg least-squares problem (Givens rotations) is solved on the
+// host; the host reads one column of it per iteration.
+namespace hdg {
+namespace {
+
+template <int D2>
+__global__ void k_bj_setup_lu(const double* __restrict__ H, const int* __restrict__ diag, int nfc,
+                              double* __restrict__ Minv) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfc) return;
+  double A[D2][2 * D2];
+  const double* blk = H + (size_t)diag[f] * D2 * D2;
+  for (int i = 0; i < D2; ++i)
+    for (int j = 0; j < D2; ++j) {
+      A[i][j] = blk[i * D2 + j];
+      A[i][D2 + j] = i == j ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < D2; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < D2; ++r)
+      if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+    if (piv != c)
+      for (int j = 0; j < 2 * D2; ++j) {
+        const double t = A[c][j];
+        A[c][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+    const double inv = 1.0 / A[c][c];
+    for (int j = 0; j < 2 * D2; ++j) A[c][j] *= inv;
+    for (int r = 0; r < D2; ++r)
+      if (r != c) {
+        const double m = A[r][c];
+        for (int j = 0; j < 2 * D2; ++j) A[r][j] -= m * A[c][j];
+      }
+  }
+  double* o = Minv + (size_t)f * D2 * D2;
+  for (int i = 0; i < D2; ++i)
+    for (int j = 0; j < D2; ++j) o[i * D2 + j] = A[i][D2 + j];
+}
+
+// part[b * nv + i] = partial (w, V_i) of block b, i < nv
+__global__ void k_mdot_partial(const double* __restrict__ V, size_t ldv, int nv, const double* __restrict__ w,
+                               size_t n, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  for (int i = 0; i < nv; ++i) {
+    const double* vi = V + (size_t)i * ldv;
+    double s = 0;
+    for (size_t t = blockIdx.x * (size_t)kRedThreads + threadIdx.x; t < n; t += (size_t)kRedBlocks * kRedThreads)
+      s += w[t] * vi[t];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.x * nv + i] = sh[0];
+    __syncthreads();
+  }
+}
+
+// out[i] (+)= sum over the blocks of part[b * nv + i], one workgroup per i
+__global__ void k_mdot_final(const double* __restrict__ part, int nv, double* __restrict__ out, int accumulate) {
+  __shared__ double sh[kRedThreads];
+  const int i = blockIdx.x;
+  double s = 0;
+  for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads) s += part[(size_t)b * nv + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kRedThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = accumulate ? out[i] + sh[0] : sh[0];
+}
+
+// w -= sum_i h[i] V_i
+__global__ void k_sub_combination(double* __restrict__ w, const double* __restrict__ V, size_t ldv, int nv,
+                                  const double* __restrict__ h, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    double s = w[t];
+    for (int i = 0; i < nv; ++i) s -= h[i] * V[(size_t)i * ldv + t];
+    w[t] = s;
+  }
+}
+
+// y = sum_i c[i] V_i
+__global__ void k_combination(double* __restrict__ y, const double* __restrict__ V, size_t ldv, int nv,
+                              const double* __restrict__ c, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int i = 0; i < nv; ++i) s += c[i] * V[(size_t)i * ldv + t];
+    y[t] = s;
+  }
+}
+
+// v = w / sqrt(nrm2[0]) (or w / a for a given scalar when nrm2 == NULL)
+__global__ void k_scale_into(double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ nrm2,
+                             double a, size_t n) {
+  const double d = nrm2 ? sqrt(nrm2[0]) : a;
+  const double inv = 1.0 / d;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+    v[t] = w[t] * inv;
+}
+
+__global__ void k_add_into(double* __restrict__ x, const double* __restrict__ z, size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+    x[t] += z[t];
+}
+
+constexpr int kMaxRestart = 64;
+
+// Workspace, in doubles: the m + 1 basis vectors, w, z, r, the inverse diagonal blocks, the
+// partial sums of the batched dots, and a small device array (both Gram-Schmidt passes'
+// coefficients, the norm, y).
+size_t gmres_ws_doubles(size_t n, int nfc, int d2, int m) {
+  return (size_t)(m + 4) * n + (size_t)nfc * d2 * d2 + (size_t)kRedBlocks * (m + 1) + 3 * (size_t)(m + 1) + 64;
+}
+
+template <int D2>
+hdg_status run_gmres(const hdg_mesh* mesh, const double* H, const double* b, double* x, double rtol, int max_iter,
+                     int m, hdg_solve_info* info, double* ws, hipStream_t s) {
+  const size_t n = (size_t)mesh->nfc * D2;
+  const int nfc = (int)mesh->nfc;
+  double* V = ws;  // basis vector i at V + i n
+  double* w = V + (size_t)(m + 1) * n;
+  double* z = w + n;
+  double* r = z + n;
+  double* Minv = r + n;
+  double* part = Minv + (size_t)nfc * D2 * D2;
+  // small: [0, m + 1) first-pass coefficients, [m + 1, 2m + 2) second-pass ones, [2m + 2] the
+  // squared norm; y reuses [0, m)
+  double* small = part + (size_t)kRedBlocks * (m + 1);
+  double* h1 = small;
+  double* h2 = small + (m + 1);
+  double* nrm = small + 2 * (m + 1);
+  const unsigned T = 256;
+  const unsigned gr = (unsigned)((n + T - 1) / T);
+  const unsigned gv = (unsigned)std::max<size_t>(1, std::min<size_t>((n + T - 1) / T, 8192));
+  if (nfc) k_bj_setup_lu<D2><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv);
+  auto norm2 = [&](const double* a) {
+    k_dot_partial<double, double><<<kRedBlocks, kRedThreads, 0, s>>>(a, a, n, part);
+    k_dot_final<<<1, kRedThreads, 0, s>>>(part, nrm);
+  };
+  auto read = [&](const double* d, double* h, int cnt) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+    return e == hipSuccess ? hipStreamSynchronize(s) : e;
+  };
+  std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(2 * (m + 1) + 1);
+  hipError_t e;
+  double bn2 = 0;
+  norm2(b);
+  if ((e = read(nrm, &bn2, 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
+  const double bnorm = bn2 > 0 ? std::sqrt(bn2) : 1.0;
+  int iters = 0, cycles = 0;
+  double rel = 0;
+  for (;;) {
+    // true residual at the start of every cycle (and once more at the end)
+    if (n) k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
+    double rn2 = 0;
+    norm2(r);
+    if ((e = read(nrm, &rn2, 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
+    const double beta = std::sqrt(rn2);
+    rel = beta / bnorm;
+    if (!std::isfinite(rel) || rel <= rtol || iters >= max_iter) break;
+    k_scale_into<<<gv, T, 0, s>>>(V, r, nullptr, beta, n);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    bool done = false;
+    while (j < m && iters < max_iter && !done) {
+      const double* vj = V + (size_t)j * n;
+      k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, vj, z, nfc);
+      k_spmv<D2, double, double><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, z, w, nfc);
+      // classical Gram-Schmidt against V_0..V_j, applied twice
+      for (double* h : {h1, h2}) {
+        k_mdot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(V, n, j + 1, w, n, part);
+        k_mdot_final<<<j + 1, kRedThreads, 0, s>>>(part, j + 1, h, 0);
+        k_sub_combination<<<gv, T, 0, s>>>(w, V, n, j + 1, h, n);
+      }
+      norm2(w);
+      if ((e = read(small, col.data(), 2 * (m + 1) + 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
+      const double hnext = std::sqrt(col[2 * (m + 1)]);
+      for (int i = 0; i <= j; ++i) Hh[(size_t)i * m + j] = col[i] + col[m + 1 + i];
+      Hh[(size_t)(j + 1) * m + j] = hnext;
+      if (hnext > 0) k_scale_into<<<gv, T, 0, s>>>(V + (size_t)(j + 1) * n, w, nullptr, hnext, n);
+      // the earlier Givens rotations, then one that zeroes H(j + 1, j)
+      for (int i = 0; i < j; ++i) {
+        const double a = Hh[(size_t)i * m + j], c2 = Hh[(size_t)(i + 1) * m + j];
+        Hh[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+        Hh[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+      }
+      const double a = Hh[(size_t)j * m + j], c2 = hnext;
+      const double den = std::hypot(a, c2);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? c2 / den : 0.0;
+      Hh[(size_t)j * m + j] = den;
+      Hh[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++j;
+      ++iters;
+      // the least-squares residual equals the preconditioned system's residual norm in exact
+      // arithmetic; stop the cycle a little early and let the true residual decide
+      done = std::fabs(g[j]) <= 0.5 * rtol * bnorm || hnext == 0;
+    }
+    // y = R^{-1} g by back substitution, then x += M^{-1} (V y)
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int c = i + 1; c < j; ++c) acc -= Hh[(size_t)i * m + c] * y[c];
+      y[i] = Hh[(size_t)i * m + i] != 0 ? acc / Hh[(size_t)i * m + i] : 0.0;
+    }
+    if ((e = hipMemcpyAsync(small, y.data(), sizeof(double) * j, hipMemcpyHostToDevice, s)) != hipSuccess)
+      return check_hip(e, "hdg_solve_gmres");
+    k_combination<<<gv, T, 0, s>>>(w, V, n, j, small, n);
+    k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, w, z, nfc);
+    k_add_into<<<gv, T, 0, s>>>(x, z, n);
+    ++cycles;
+  }
+  HDG_CHECK_LAUNCH("hdg_solve_gmres");
+  info->iterations = iters;
+  info->outer = cycles;
+  info->rel_residual = rel;
+  info->fell_back = 0;
+  if (!(rel <= rtol)) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve_gmres: tolerance not reached");
+  return HDG_OK;
+}
+
+}  // namespace
+}  // namespace hdg
+
+extern "C" hdg_status hdg_solve_gmres_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, int restart,
+                                                     size_t* ws_bytes) {
+  if (!disc || !mesh || !ws_bytes || restart < 1 || restart > hdg::kMaxRestart)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve_gmres_workspace_size: bad argument");
+  const int d2 = disc->host.d2;
+  *ws_bytes = sizeof(double) * hdg::gmres_ws_doubles((size_t)mesh->nfc * d2, (int)mesh->nfc, d2, restart);
+  return HDG_OK;
+}
+
+extern "C" hdg_status hdg_solve_gmres(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H, const double* d_b,
+                                      double* d_uhat, double rtol, int max_iter, int restart, hdg_solve_info* info,
+                                      void* d_ws, size_t ws_bytes, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_solve_gmres");
+  if (st) return st;
+  if (!d_H || !d_b || !d_uhat || !info || !(rtol > 0) || max_iter < 0 || restart < 1 ||
+      restart > hdg::kMaxRestart)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve_gmres: bad argument");
+  size_t need = 0;
+  hdg_solve_gmres_workspace_size(disc, mesh, restart, &need);
+  if (!d_ws || ws_bytes < need) return set_error(HDG_ERR_WORKSPACE, "hdg_solve_gmres: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  double* ws = (double*)d_ws;
+  switch (disc->host.k) {
+    case 0: return run_gmres<dim2(0)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, restart, info, ws, s);
+    case 1: return run_gmres<dim2(1)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, restart, info, ws, s);
+    case 2: return run_gmres<dim2(2)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, restart, info, ws, s);
+    case 3: return run_gmres<dim2(3)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, restart, info, ws, s);
+    case 4: return run_gmres<dim2(4)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, restart, info, ws, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve_gmres: unsupported degree");
+}

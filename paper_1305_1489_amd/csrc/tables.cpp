@@ -304,6 +304,7 @@ HostTables build_tables(int k, int nq) {
   o.P1g = take(3 * nqd * d3p);
   o.Shat = take(6 * d3p * d3p);
   o.DPtopinv = take(24 * d2 * d2);
+  o.Dmu = take(6 * nqd2 * d2);
   const int D3P4 = (d3 + 3) / 4 * 4, D2P4 = (d2 + 3) / 4 * 4, NQP = (nqd + 3) / 4 * 4;
   t.d3p4 = D3P4;
   t.d2p4 = D2P4;
@@ -348,6 +349,7 @@ HostTables build_tables(int k, int nq) {
   put(o.P1g, P1g);
   put(o.Shat, Shat);
   put(o.DPtopinv, DPtopinv);
+  put(o.Dmu, Dmu);
   for (int q = 0; q < nqd; ++q)
     for (int j = 0; j < d3; ++j) t.data[o.Pt + q * D3P4 + j] = (double)P[q * d3 + j];
   for (int h = 0; h < 3; ++h)

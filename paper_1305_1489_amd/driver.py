@@ -81,6 +81,35 @@ class HDGSystem:
             L.hdg_assemble_condense_ws(self.disc, self.mesh, self.kappa, self.c, self.f, self.tau, self.H, self.F,
                                        self.factors, ws=self.condense_ws, stream=self.stream)
 
+    # ---- convection-diffusion (problem.beta: a callable returning the three components)
+    def convection_fields(self):
+        """beta at the volume points and at every element's own face points (evaluated once)."""
+        if getattr(self, "beta_vol", None) is None:
+            X, Y, Z = self.qp[..., 0], self.qp[..., 1], self.qp[..., 2]
+            self.beta_vol = torch.stack([_field(lambda a, b, c, g=g: g, X, Y, Z) for g in self.problem.beta(X, Y, Z)],
+                                        dim=-1).contiguous()
+            y = L.hdg_elem_face_qp_coords(self.disc, self.mesh, stream=self.stream)
+            Yx, Yy, Yz = y[..., 0], y[..., 1], y[..., 2]
+            self.beta_face = torch.stack([_field(lambda a, b, c, g=g: g, Yx, Yy, Yz)
+                                          for g in self.problem.beta(Yx, Yy, Yz)], dim=-1).contiguous()
+            self.X = torch.empty((self.mesh.nelt, L.hdg_ir_store_len(self.disc)), dtype=torch.float64,
+                                 device=self.device)
+        return self.beta_vol, self.beta_face
+
+    def assemble_cd(self):
+        bv, bf = self.convection_fields()
+        L.hdg_assemble_condense_cd(self.disc, self.mesh, self.kappa, self.c, self.f, bv, bf, self.tau, self.H, self.F,
+                                   self.X, stream=self.stream)
+
+    def run_cd(self, rtol=1e-10, restart=40, max_iter=20000):
+        """Convection-diffusion: condensation, boundary data, GMRES, reconstruction from X."""
+        self.assemble_cd()
+        self.boundary()
+        info = L.hdg_solve_gmres(self.disc, self.mesh, self.H, self.F, self.uhat, rtol=rtol, max_iter=max_iter,
+                                 restart=restart, stream=self.stream)
+        q, u = L.hdg_recover_ir(self.disc, self.mesh, self.X, self.uhat, stream=self.stream)
+        return dict(info=info, q=q, u=u)
+
     def boundary(self):
         L.hdg_boundary(self.disc, self.mesh, self.uD, self.gN, self.H, self.F, self.uhat, stream=self.stream)
 
