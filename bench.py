@@ -396,6 +396,90 @@ def bdm_metric(S, hip, flops_per_element, reps=20):
                                      "products with the degree-k u modes masked"}}
 
 
+def cd_flops(k):
+    """FP64 flops per element of the convection-diffusion condensation kernel as implemented
+    (FMA = 2 flops): element blocks by quadrature, Cholesky of M, G_s = L^{-1} C_s^T, the
+    u Schur complement and its LU, the block solve for the 4 d2 + 1 right-hand sides, and
+    C^K = A3 X."""
+    d3, d2 = binom(k + 3, 3), binom(k + 2, 2)
+    m = 4 * d2
+    nr = m + 1
+    nqd, nqd2 = (k + 2) ** 3, (k + 2) ** 2
+    return (12 * d3 * d3 * nqd            # M_{1/kappa}, M_c and sum_s E_s^T
+            + 26 * d3 * d3                # tau PP, C_s^T
+            + 2 * d3 * nqd                # load vector
+            + 12 * d2 * d3 * nqd2         # beta.n DP_l
+            + 12 * d2 * d2 * nqd2         # beta.n DD_l
+            + d3 ** 3 // 3                # Cholesky of M
+            + 3 * d3 ** 3                 # G_s = L^{-1} C_s^T
+            + 6 * d3 ** 3                 # S += sum_s G_s^T G_s
+            + 2 * d3 ** 3 // 3            # LU of S
+            + 20 * d3 * d3 * nr           # Z_s, b_u - G^T Z, u, Z + G u, L^{-T}
+            + 9 * m * nr * d3)            # C^K = A3 X and Cf^K
+
+
+def convection_metric(cfg, hip, reps=10):
+    """Convection-diffusion (Section 9: the eq 9.1 convection blocks with a variable beta) on
+    the bench mesh at the bench degree: hdg_assemble_condense_cd timed (call and kernel),
+    then one GMRES solve of the non-symmetric trace system and the reconstruction from X."""
+    import statistics
+    import torch
+    from hdg_inputs import convection_sin_problem, kuhn_mesh
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem
+    k = cfg["k"]
+    if not 0 <= k <= 3:
+        return None
+    m = kuhn_mesh(cfg["n"], jitter=cfg["jitter"], seed=cfg["seed"], dirichlet_sides=cfg["dirichlet"],
+                  neumann_sides=cfg["neumann"])
+    pb = convection_sin_problem(beta_scale=1.0)
+    S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, pb)
+    S.convection_fields()
+    S.assemble_cd()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    call, kern = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0, k1 = hip.create(), hip.create()
+        L.hdg_set_kernel_timer("k_condense_cd", k0, k1)
+        e0.record(stream)
+        S.assemble_cd()
+        e1.record(stream)
+        call.append((e0, e1))
+        kern.append((k0, k1))
+    torch.cuda.synchronize()
+    L.hdg_set_kernel_timer(None)
+    call_ms = statistics.median(a.elapsed_time(b) for a, b in call)
+    kern_ms = statistics.median(hip.elapsed_ms(a, b) for a, b in kern)
+    for a, b in kern:
+        hip.destroy(a)
+        hip.destroy(b)
+    nelt = S.mesh.nelt
+    fl = cd_flops(k)
+    tf = fl * nelt / (kern_ms * 1e-3) / 1e12
+    S.boundary()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    info = L.hdg_solve_gmres(S.disc, S.mesh, S.H, S.F, S.uhat, rtol=1e-10, max_iter=5000, restart=40,
+                             raise_on_fail=False)
+    e1.record(stream)
+    q, u = L.hdg_recover_ir(S.disc, S.mesh, S.X, S.uhat)
+    torch.cuda.synchronize()
+    solve_ms = e0.elapsed_time(e1)
+    log(f"convection: hdg_assemble_condense_cd {call_ms:.3f} ms (k_condense_cd {kern_ms:.3f} ms, {tf:.2f} TFLOP/s); "
+        f"GMRES(40) {info['iterations']} it, {solve_ms:.1f} ms, rel res {info['rel_residual']:.2e}")
+    return {"workload": f"Kuhn {cfg['n']}^3, jitter {cfg['jitter']}h, {nelt} tets, k={k}, kappa=1, c=1, "
+                        f"beta = (1, 0.5, -0.3) + (0.5 y, -0.4 z, 0.3 x), tau = 1 + max|beta|, u = sin(xyz)",
+            "call": "hdg_assemble_condense_cd", "call_ms": call_ms, "elements_per_s": nelt / (call_ms * 1e-3),
+            "kernel": {"kernel": "k_condense_cd<k>", "bound": "alu", "avg_launch_ms": kern_ms,
+                       "achieved": round(tf, 3), "peak": 78.6, "unit": "TFLOP/s", "frac": round(tf / 78.6, 4),
+                       "flops_per_element": fl, "flops_note": "implementation count; FP64 vector ALU peak"},
+            "gmres": {"restart": 40, "rtol": 1e-10, "iterations": info["iterations"], "cycles": info["cycles"],
+                      "rel_residual": info["rel_residual"], "status": info["status"], "ms": solve_ms,
+                      "unknowns": S.mesh.nfc * S.disc.d2}}
+
+
 def psweep_metric(reps=10, n=16):
     """p-refinement (Section 10, Table 4, eq 10.3): the element hot path (the bench step:
     condensation, boundary data, reconstruction, postprocess) at k = 0..4 on one fixed mesh
@@ -526,6 +610,7 @@ def main():
     ap.add_argument("--no-projection", action="store_true", help="skip the HDG / trace projection timing")
     ap.add_argument("--no-bdm", action="store_true", help="skip the hybridized BDM condensation timing")
     ap.add_argument("--no-psweep", action="store_true", help="skip the k = 0..4 p-refinement sweep")
+    ap.add_argument("--no-convection", action="store_true", help="skip the convection-diffusion timing")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -726,6 +811,9 @@ def main():
     if not args.no_solve:
         log("solve metric ...")
         result["solve"] = solve_metric(args)
+    if not args.no_convection:
+        log("convection-diffusion ...")
+        result["convection"] = convection_metric(cfg, hip)
     if not args.no_psweep:
         log("p-sweep ...")
         result["psweep"] = psweep_metric()
