@@ -565,7 +565,9 @@ def solve_metric(args):
     LP = LearnedPreconditioner.load(ck) if os.path.exists(ck) else None
     forms = [(0, None, "fp64_block_jacobi"), (1, None, "fp32_refined")]
     if LP is not None:
-        forms += [(0, LP, "learned"), (1, LP, "learned_fp32_refined")]
+        # the untrained network of the same shape: zero heads, i.e. G = I - tril(Hs), B = I
+        LP0 = LearnedPreconditioner(LP.d2, LP.hidden, LP.layers, seed=0)
+        forms += [(0, LP0, "learned_untrained"), (0, LP, "learned"), (1, LP, "learned_fp32_refined")]
     else:
         log(f"no trained network at {ck}: learned forms skipped")
     for prec, lp, name in forms:
@@ -576,8 +578,8 @@ def solve_metric(args):
         t0 = time.perf_counter()
         learned = None
         if lp is not None:  # preconditioner set-up (graph + inference) is inside the timed region
-            g, N = lp.prepare(S.disc, S.mesh, S.H)
-            learned = (N, g)
+            g, N, B = lp.prepare(S.disc, S.mesh, S.H)
+            learned = (N, B, g)
         torch.cuda.synchronize()
         t_setup = time.perf_counter() - t0
         info = L.hdg_solve(S.disc, S.mesh, S.H, S.F, S.uhat, rtol=1e-10, precision=prec, check_every=50,
@@ -593,7 +595,50 @@ def solve_metric(args):
         out["network"] = {"checkpoint": os.path.relpath(ck, ROOT), "hidden": LP.hidden, "layers": LP.layers,
                           **{k: LP.meta[k] for k in ("systems", "train_seconds", "train_steps", "first_loss",
                                                      "last_loss") if k in LP.meta}}
+        out["held_out"] = held_out_metric(cfg, m, LP, LP0)
     return out
+
+
+def held_out_metric(cfg, m, LP, LP0, seeds=range(20000, 20020)):
+    """The learned factor against the untrained one (same shape, zero heads) and block-Jacobi
+    on 20 log-normal systems of the solve workload's size whose fields no training system
+    used (training seeds 10000..11999): PCG iterations (checked every 5) and seconds to the
+    true relative residual 1e-10, FP64."""
+    import statistics
+    import torch
+    from hdg_inputs.fields import constant_rhs_problem
+    from paper_1305_1489_amd import _lib as L
+    from paper_1305_1489_amd.driver import HDGSystem
+    rows = []
+    disc = L.hdg_disc_create(cfg["k"])
+    for sd in seeds:
+        S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, cfg["k"],
+                      constant_rhs_problem(1.5, 0.1, sd, 0.1), disc=disc)
+        S.assemble()
+        S.boundary()
+        b, x0 = S.F.clone(), S.uhat.clone()
+        row = {"field_seed": sd}
+        for name, lp in (("block_jacobi", None), ("untrained", LP0), ("trained", LP)):
+            S.uhat.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            learned = None
+            if lp is not None:
+                g, N, B = lp.prepare(S.disc, S.mesh, S.H)
+                learned = (N, B, g)
+            info = L.hdg_solve(S.disc, S.mesh, S.H, b, S.uhat, rtol=1e-10, check_every=5, learned=learned)
+            torch.cuda.synchronize()
+            row[name] = {"iterations": info["iterations"], "seconds": time.perf_counter() - t0,
+                         "fell_back": info["fell_back"]}
+        rows.append(row)
+    ratio = [r["trained"]["iterations"] / r["untrained"]["iterations"] for r in rows]
+    tr = [r["trained"]["seconds"] / r["untrained"]["seconds"] for r in rows]
+    log(f"held-out (20 seeds): trained/untrained iterations median {statistics.median(ratio):.3f} "
+        f"(max {max(ratio):.3f}), seconds median {statistics.median(tr):.3f}")
+    return {"seeds": f"field seeds {seeds.start}..{seeds.stop - 1}", "systems": rows,
+            "iteration_ratio_trained_over_untrained": {"median": statistics.median(ratio), "max": max(ratio),
+                                                       "min": min(ratio)},
+            "seconds_ratio_trained_over_untrained": {"median": statistics.median(tr), "max": max(tr)}}
 
 
 def main():

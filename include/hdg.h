@@ -265,6 +265,8 @@ typedef struct {
   const float* d_pre_N;      /* [nnzb][d2][d2] N of the learned factor (hdg_gnn_forward) */
   const float* d_pre_Linv;   /* [nfc][d2][d2]  hdg_gnn_graph.Linv */
   const int32_t* d_pre_mirror; /* [nnzb]      hdg_gnn_graph.mirror */
+  const float* d_pre_B;      /* [nfc][d2 (d2 + 1) / 2] block scaling of the learned factor
+                                (hdg_gnn_forward), or NULL for B = I */
 } hdg_solve_opts;
 
 typedef struct {
@@ -496,20 +498,26 @@ hdg_status hdg_solve_gmres(const hdg_disc* disc, const hdg_mesh* mesh, const dou
  * Learned face-graph preconditioner for eq 6.5 (the paper leaves the solver open).
  *
  * With H_ii = L_i L_i^T and Hs_ij = L_i^{-1} H_ij L_j^{-T} (block-Jacobi scaling), the
- * preconditioner is M^{-1} = L^{-T} G^T G L^{-1} with G = I + N and N strictly block-lower
- * on the pattern of H.  It is SPD for every N.  A message-passing network over the faces
- * (FP32; nodes = faces, edges = off-diagonal blocks of H) predicts N.  Its node features
- * are the face type, the log area and the row energy of Hs; its edge features are the
- * entries of Hs_ij.  The layers are
+ * preconditioner is M^{-1} = L^{-T} G^T G L^{-1} with G = B (I + N), N strictly block-lower
+ * on the pattern of H and B block diagonal with lower-triangular d2 x d2 blocks of positive
+ * diagonal.  It is SPD for every N and B.  A message-passing network over the faces (FP32;
+ * nodes = faces, edges = off-diagonal blocks of H) predicts N and B.  Its node features are
+ * the face type, the log area and the row energy of Hs; its edge features are the entries
+ * of Hs_ij.  The layers are
  *     X = relu(W0 a + c0), E = relu(We b + ce),
  *     M_ij = relu(Wm_l [X_i; X_j; E_ij] + cm_l), X_i += relu(Wu_l [X_i; sum_j M_ij] + cu_l),
- * and the head is
- *     N_ij = -Hs_ij + reshape(Wo [X_i; X_j; E_ij] + co)   (j < i, no Dirichlet face).
- * The parameters form one FP32 vector in the order W0, c0, We, ce, (Wm_l, cm_l, Wu_l,
- * cu_l) for l = 1..L, Wo, co; matrices are row-major (output, input).
- * Training objective (the Kaporin measure: G is unit triangular, so the determinant of
- * G Hs G^T is fixed and its trace is what remains):
- *     loss = 1/(p n) sum_z (G^T z)^T Hs (G^T z)   over p probe vectors z, n = nfc d2.
+ * and the two heads are
+ *     N_ij = -Hs_ij + reshape(Wo [X_i; X_j; E_ij] + co)   (j < i, no Dirichlet face),
+ *     beta_i = Wb X_i + cb   (fb = d2 (d2 + 1) / 2 values; zero on Dirichlet faces),
+ * with B_i[a][a] = exp(beta_i[a]) and B_i[a][b] = beta_i[d2 + a (a - 1) / 2 + b] for b < a.
+ * Zero heads give the first-order factor G = I - tril(Hs).  The parameters form one FP32
+ * vector in the order W0, c0, We, ce, (Wm_l, cm_l, Wu_l, cu_l) for l = 1..L, Wo, co, Wb,
+ * cb; matrices are row-major (output, input).
+ * Training objective: the logarithm of the Kaporin number (tr/n) / det^{1/n} of G Hs G^T,
+ * which bounds the PCG iteration count.  det(G Hs G^T) = det(B)^2 det(Hs), so up to a
+ * constant
+ *     loss = log T - (2/n) sum_i sum_a beta_i[a],
+ *     T = 1/(p n) sum_z (G^T z)^T Hs (G^T z)   over p probe vectors z, n = nfc d2.
  * Every array is caller-owned device memory.  No call allocates, and every reduction
  * has a fixed order.
  * ------------------------------------------------------------------------------ */
@@ -536,22 +544,26 @@ hdg_status hdg_gnn_build_graph(const hdg_disc* disc, const hdg_mesh* mesh, const
                                void* d_ws, size_t ws_bytes, void* stream);
 /* Activations and temporaries of forward / backward for nprobe probe vectors. */
 hdg_status hdg_gnn_workspace_size(const hdg_gnn_shape* shape, const hdg_mesh* mesh, int nprobe, size_t* bytes);
-/* d_N [nnzb][d2][d2]: N on the lower blocks without Dirichlet faces, zero elsewhere. */
+/* d_N [nnzb][d2][d2]: N on the lower blocks without Dirichlet faces, zero elsewhere;
+ * d_B [nfc][d2 (d2 + 1) / 2]: beta of every face (zero on Dirichlet faces). */
 hdg_status hdg_gnn_forward(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
-                           const hdg_gnn_graph* graph, float* d_N, void* d_ws, size_t ws_bytes, void* stream);
-/* Forward, the probe loss and its gradient: d_probes [nprobe][nfc][d2] (drawn by the
- * caller), d_loss one double (device), d_grad [param_count] (NULL: loss only). */
+                           const hdg_gnn_graph* graph, float* d_N, float* d_B, void* d_ws, size_t ws_bytes,
+                           void* stream);
+/* Forward, the loss and its gradient: d_probes [nprobe][nfc][d2] (drawn by the caller),
+ * d_N and d_B as from hdg_gnn_forward, d_loss one double (device), d_grad [param_count]
+ * (NULL: loss only). */
 hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
-                             const hdg_gnn_graph* graph, const float* d_probes, int nprobe, float* d_N,
+                             const hdg_gnn_graph* graph, const float* d_probes, int nprobe, float* d_N, float* d_B,
                              double* d_loss, float* d_grad, void* d_ws, size_t ws_bytes, void* stream);
-/* z = M^{-1} r = L^{-T} G^T G L^{-1} r with G = I + N: the learned preconditioner as hdg_solve
- * applies it (precond = 1), FP64 vectors with FP32 factors and FP64 accumulation.
- *   d_N [nnzb][d2][d2] (hdg_gnn_forward), d_Linv [nfc][d2][d2] and d_mirror [nnzb] (the
- *   graph), d_r and d_z double [nfc][d2] (distinct arrays).
+/* z = M^{-1} r = L^{-T} G^T G L^{-1} r with G = B (I + N): the learned preconditioner as
+ * hdg_solve applies it (precond = 1), FP64 vectors with FP32 factors and FP64 accumulation.
+ *   d_N [nnzb][d2][d2] and d_B [nfc][d2 (d2 + 1) / 2] (hdg_gnn_forward; d_B may be NULL for
+ *   B = I), d_Linv [nfc][d2][d2] and d_mirror [nnzb] (the graph), d_r and d_z double
+ *   [nfc][d2] (distinct arrays).
  * Workspace: nfc d2 doubles.  Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE. */
-hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N, const float* d_Linv,
-                                 const int32_t* d_mirror, const double* d_r, double* d_z, void* d_ws, size_t ws_bytes,
-                                 void* stream);
+hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N, const float* d_B,
+                                 const float* d_Linv, const int32_t* d_mirror, const double* d_r, double* d_z,
+                                 void* d_ws, size_t ws_bytes, void* stream);
 /* One Adam step (step = 1, 2, ...) on n parameters. */
 hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr,
                         float beta1, float beta2, float eps, void* stream);

@@ -17,9 +17,12 @@ which is the block-Jacobi-scaled matrix.
 
 Preconditioner
 --------------
-    G = I + N,  N strictly block-lower on the pattern of H,
+    G = B (I + N),  N strictly block-lower on the pattern of H,
+    B = diag(B_i) block diagonal, each B_i a d2 x d2 lower-triangular matrix with a positive
+    diagonal, B_i[a][a] = exp(s_ia),
     M^{-1} = L^{-T} G^T G L^{-1},
-which is symmetric positive definite for every N (G is unit triangular).
+which is symmetric positive definite for every N and B (G is triangular with a positive
+diagonal).
 
 Network
 -------
@@ -36,21 +39,28 @@ The layers (h channels, relu), for l = 1..L:
 
 The head acts on the lower edges (j < i):
     N_ij = mask_ij (-Hs_ij + reshape(Wo [X_i; X_j; E_ij] + co)),
-where mask_ij = 0 if face i or face j is a Dirichlet face.  With Wo = 0, co = 0 the head
-is the first-order factor G = I - tril(Hs).
+where mask_ij = 0 if face i or face j is a Dirichlet face, and a node head gives each face's
+block scaling,
+    beta_i = free_i (Wb X_i + cb),  fb = d2 (d2 + 1) / 2 values:
+    s_ia = beta_i[a] (a < d2), and the strictly lower entries of B_i row by row
+    (B_i[a][b] = beta_i[d2 + a (a - 1) / 2 + b], b < a),
+with free_i = 0 on Dirichlet faces (B_i = I there).  With Wo, co, Wb, cb all zero the
+preconditioner is the first-order factor G = I - tril(Hs).
 
 Objective
 ---------
-The objective is the probe estimate of the Kaporin measure.  det(G Hs G^T) = det(Hs) is
-fixed, because G is unit triangular.  The Kaporin number (tr/n) / det^{1/n} of the
-preconditioned matrix is therefore proportional to tr(G Hs G^T):
-    loss = 1 / (p n) sum_z (G^T z)^T Hs (G^T z),
-with p probe vectors z and n = nfc d2 unknowns.
+The objective is the logarithm of the Kaporin number (tr/n) / det^{1/n} of the
+preconditioned matrix G Hs G^T, which bounds the PCG iteration count.  det(G Hs G^T) =
+det(B)^2 det(Hs), and det(Hs) does not depend on the network, so up to a constant
+    loss = log T - (2 / n) sum_i sum_a s_ia,
+    T = 1 / (p n) sum_z (G^T z)^T Hs (G^T z)   (the probe estimate of tr(G Hs G^T) / n),
+with p probe vectors z and n = nfc d2 unknowns.  The loss does not change when G is
+multiplied by a constant.
 
 Parameter vector
 ----------------
 One flat array in the order W0, c0, We, ce, then (Wm_l, cm_l, Wu_l, cu_l) for each l,
-then Wo, co.  Matrices are stored row-major (output, input).
+then Wo, co, then Wb, cb.  Matrices are stored row-major (output, input).
 """
 from __future__ import annotations
 
@@ -71,13 +81,17 @@ class Shape:
     def fe(self):
         return self.d2 * self.d2
 
+    @property
+    def fb(self):
+        return self.d2 * (self.d2 + 1) // 2
+
 
 def param_layout(s: Shape):
     h, fe = s.hidden, s.fe
     lay = [("W0", (h, F0)), ("c0", (h,)), ("We", (h, fe)), ("ce", (h,))]
     for l in range(s.layers):
         lay += [(f"Wm{l}", (h, 3 * h)), (f"cm{l}", (h,)), (f"Wu{l}", (h, 2 * h)), (f"cu{l}", (h,))]
-    lay += [("Wo", (fe, 3 * h)), ("co", (fe,))]
+    lay += [("Wo", (fe, 3 * h)), ("co", (fe,)), ("Wb", (s.fb, h)), ("cb", (s.fb,))]
     return lay
 
 
@@ -164,7 +178,8 @@ def relu(x):
 
 
 def forward(theta, s: Shape, g, row_ptr, col_idx, erow, ftype):
-    """N (nnzb, d2, d2), nonzero on the lower off-diagonal blocks, and the cache for backward."""
+    """N (nnzb, d2, d2), nonzero on the lower off-diagonal blocks, the block-scaling
+    parameters beta (nfc, fb), zero on Dirichlet faces, and the cache for backward."""
     p = unpack(theta, s)
     nfc = row_ptr.size - 1
     off = erow != col_idx
@@ -186,8 +201,21 @@ def forward(theta, s: Shape, g, row_ptr, col_idx, erow, ftype):
     Z = np.concatenate([X[erow], X[col_idx], Eh], axis=1)
     D = Z @ p["Wo"].T + p["co"]
     N = (mask[:, None] * (-B + D)).reshape(-1, s.d2, s.d2)
-    cache.update(X=X, Zo=Z, mask=mask, off=off)
-    return N, cache
+    free = (np.asarray(ftype) != 1).astype(np.float64)
+    beta = free[:, None] * (X @ p["Wb"].T + p["cb"])
+    cache.update(X=X, Zo=Z, mask=mask, off=off, free=free)
+    return N, beta, cache
+
+
+def block_scale(beta, d2):
+    """B (nfc, d2, d2): lower triangular, B[a][a] = exp(beta[a]), B[a][b] = beta[d2 + a(a-1)/2 + b]."""
+    nfc = beta.shape[0]
+    B = np.zeros((nfc, d2, d2))
+    for a in range(d2):
+        B[:, a, a] = np.exp(beta[:, a])
+        for b in range(a):
+            B[:, a, b] = beta[:, d2 + a * (a - 1) // 2 + b]
+    return B
 
 
 def apply_GT(N, z, row_ptr, col_idx, erow):
@@ -204,35 +232,61 @@ def apply_H(Hs, u, col_idx, erow):
     return out
 
 
-def trace_loss(N, Hs, row_ptr, col_idx, erow, Z):
-    """loss = 1/(p n) sum_z (G^T z)^T Hs (G^T z) and dloss/dN (on the lower blocks).
-    Z: (p, nfc, d2) probe vectors."""
+def apply_G_lower(N, v, row_ptr, col_idx, erow):
+    """(I + N) v for block vectors (nfc, d2): v_i + sum_{j < i} N_ij v_j."""
+    out = v.copy()
+    low = col_idx < erow
+    np.add.at(out, erow[low], np.einsum("eab,eb->ea", N[low], v[col_idx[low]]))
+    return out
+
+
+def kaporin_loss(N, beta, Hs, row_ptr, col_idx, erow, Z):
+    """loss = log T - (2/n) sum s (module docstring) and its gradients dloss/dN (on the lower
+    blocks; the caller masks) and dloss/dbeta.  Z: (p, nfc, d2) probe vectors.
+
+    With y = B^T z, u = (I + N)^T y, hu = Hs u:
+      dT/dN_ij = 2/(p n) sum_z y_i hu_j^T,   dT/dB_i[a][b] = 2/(p n) sum_z z_i[a] w_i[b],
+    where w = (I + N) hu."""
     p = Z.shape[0]
     nfc, d2 = Z.shape[1], Z.shape[2]
-    scale = 1.0 / (p * nfc * d2)
-    loss = 0.0
-    dN = np.zeros_like(N)
+    n = nfc * d2
+    scale = 1.0 / (p * n)
+    Bm = block_scale(beta, d2)
+    T = 0.0
+    dTN = np.zeros_like(N)
+    dTB = np.zeros_like(Bm)
     low = col_idx < erow
     for z in Z:
-        u = apply_GT(N, z, row_ptr, col_idx, erow)
+        y = np.einsum("iab,ia->ib", Bm, z)
+        u = apply_GT(N, y, row_ptr, col_idx, erow)
         hu = apply_H(Hs, u, col_idx, erow)
-        loss += scale * float(np.sum(u * hu))
-        # u_j = z_j + sum_i N_ij^T z_i  ->  dloss/dN_ij = 2 scale z_i (Hs u)_j^T
-        dN[low] += 2.0 * scale * np.einsum("ea,eb->eab", z[erow[low]], hu[col_idx[low]])
-    return loss, dN
+        T += scale * float(np.sum(u * hu))
+        dTN[low] += 2.0 * scale * np.einsum("ea,eb->eab", y[erow[low]], hu[col_idx[low]])
+        w = apply_G_lower(N, hu, row_ptr, col_idx, erow)
+        dTB += 2.0 * scale * np.einsum("ia,ib->iab", z, w)
+    loss = np.log(T) - 2.0 / n * float(beta[:, :d2].sum())
+    dbeta = np.zeros_like(beta)
+    for a in range(d2):
+        dbeta[:, a] = dTB[:, a, a] * Bm[:, a, a] / T - 2.0 / n
+        for b in range(a):
+            dbeta[:, d2 + a * (a - 1) // 2 + b] = dTB[:, a, b] / T
+    return loss, dTN / T, dbeta
 
 
-def backward(theta, s: Shape, g, cache, dN, row_ptr, col_idx, erow):
-    """Gradient of a scalar objective with respect to theta, given its gradient dN."""
+def backward(theta, s: Shape, g, cache, dN, dbeta, row_ptr, col_idx, erow):
+    """Gradient of a scalar objective with respect to theta, given its gradients dN and dbeta."""
     p = unpack(theta, s)
     gp = {name: np.zeros(sh) for name, sh in param_layout(s)}
     h = s.hidden
     mask, off = cache["mask"], cache["off"]
+    dbeta = cache["free"][:, None] * dbeta
+    gp["Wb"] = dbeta.T @ cache["X"]
+    gp["cb"] = dbeta.sum(0)
     dD = mask[:, None] * dN.reshape(-1, s.fe)
     gp["Wo"] = dD.T @ cache["Zo"]
     gp["co"] = dD.sum(0)
     dZ = dD @ p["Wo"]
-    dX = np.zeros_like(cache["X"])
+    dX = dbeta @ p["Wb"]
     np.add.at(dX, erow, dZ[:, :h])
     np.add.at(dX, col_idx, dZ[:, h:2 * h])
     dEh = dZ[:, 2 * h:].copy()
@@ -261,28 +315,29 @@ def backward(theta, s: Shape, g, cache, dN, row_ptr, col_idx, erow):
 
 
 def loss_and_grad(theta, s: Shape, g, row_ptr, col_idx, erow, ftype, Z):
-    N, cache = forward(theta, s, g, row_ptr, col_idx, erow, ftype)
-    loss, dN = trace_loss(N, g["Hs"], row_ptr, col_idx, erow, Z)
-    return loss, backward(theta, s, g, cache, dN, row_ptr, col_idx, erow), N
+    N, beta, cache = forward(theta, s, g, row_ptr, col_idx, erow, ftype)
+    loss, dN, dbeta = kaporin_loss(N, beta, g["Hs"], row_ptr, col_idx, erow, Z)
+    return loss, backward(theta, s, g, cache, dN, dbeta, row_ptr, col_idx, erow), N, beta
 
 
 def init_params(s: Shape, seed=0):
-    """He-style random weights; the head starts at zero (G = I - tril(Hs))."""
+    """He-style random weights; both heads start at zero (G = I - tril(Hs), B = I)."""
     rng = np.random.default_rng(seed)
     p = {}
     for name, sh in param_layout(s):
-        if name.startswith("W") and name != "Wo":
+        if name.startswith("W") and name not in ("Wo", "Wb"):
             p[name] = rng.standard_normal(sh) * np.sqrt(2.0 / sh[1])
         else:
             p[name] = np.zeros(sh)
     return pack(p, s)
 
 
-def preconditioner_apply(N, Linv, r, row_ptr, col_idx, erow):
-    """z = L^{-T} G^T G L^{-1} r for block vectors (nfc, d2)."""
+def preconditioner_apply(N, beta, Linv, r, row_ptr, col_idx, erow):
+    """z = L^{-T} G^T G L^{-1} r with G = B (I + N), for block vectors (nfc, d2)."""
+    d2 = r.shape[1]
     t = np.einsum("iab,ib->ia", Linv, r)
-    low = col_idx < erow
-    s_ = t.copy()
-    np.add.at(s_, erow[low], np.einsum("eab,eb->ea", N[low], t[col_idx[low]]))
-    y = apply_GT(N, s_, row_ptr, col_idx, erow)
+    s_ = apply_G_lower(N, t, row_ptr, col_idx, erow)
+    Bm = block_scale(beta, d2)
+    v = np.einsum("iab,ib->ia", Bm, s_)
+    y = apply_GT(N, np.einsum("iba,ib->ia", Bm, v), row_ptr, col_idx, erow)
     return np.einsum("iba,ib->ia", Linv, y)

@@ -61,7 +61,7 @@ class hdg_disc_info(C.Structure):
 class hdg_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("precision", C.c_int),
                 ("precond", C.c_int), ("d_pre_N", C.c_void_p), ("d_pre_Linv", C.c_void_p),
-                ("d_pre_mirror", C.c_void_p)]
+                ("d_pre_mirror", C.c_void_p), ("d_pre_B", C.c_void_p)]
 
 
 class hdg_solve_info(C.Structure):
@@ -360,14 +360,14 @@ def hdg_assemble_condense_bdm(disc: Disc, mesh: Mesh, kappa, c, f, H, F, factors
     return H, F, factors
 
 
-def hdg_gnn_precond_apply(disc: Disc, mesh: Mesh, N, Linv, mirror, r, z=None, ws=None, stream=None):
-    """z = L^{-T} G^T G L^{-1} r (G = I + N), as the learned-preconditioner PCG applies it."""
+def hdg_gnn_precond_apply(disc: Disc, mesh: Mesh, N, B, Linv, mirror, r, z=None, ws=None, stream=None):
+    """z = L^{-T} G^T G L^{-1} r (G = B (I + N); B = None: the identity), as the learned PCG applies it."""
     if z is None:
         z = torch.empty_like(r)
     if ws is None:
         ws = torch.empty(mesh.nfc * disc.d2 * 8, dtype=torch.uint8, device=r.device)
-    _check(lib().hdg_gnn_precond_apply(disc.handle, C.byref(mesh.struct), _ptr(N), _ptr(Linv), _ptr(mirror), _ptr(r),
-                                       _ptr(z), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    _check(lib().hdg_gnn_precond_apply(disc.handle, C.byref(mesh.struct), _ptr(N), _ptr(B), _ptr(Linv), _ptr(mirror),
+                                       _ptr(r), _ptr(z), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
     return z
 
 
@@ -398,15 +398,17 @@ def hdg_solve_workspace_size(disc: Disc, mesh: Mesh, precision: int = 0) -> int:
 
 def hdg_solve(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=100000, check_every=10, precision=0,
               ws=None, stream=None, raise_on_fail=True, learned=None):
-    """learned: None (block-Jacobi) or (N, graph) from hdg_gnn_forward / hdg_gnn_build_graph."""
+    """learned: None (block-Jacobi), or (N, B, graph) / (N, graph) from hdg_gnn_forward and
+    hdg_gnn_build_graph (B = None: no block scaling)."""
     need = hdg_solve_workspace_size(disc, mesh, precision)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 8), dtype=torch.uint8, device=mesh.device)
     opts = hdg_solve_opts(rtol=rtol, max_iter=max_iter, check_every=check_every, precision=precision)
     if learned is not None:
-        N, graph = learned
+        N, B, graph = learned if len(learned) == 3 else (learned[0], None, learned[1])
         opts.precond = 1
         opts.d_pre_N = N.data_ptr()
+        opts.d_pre_B = B.data_ptr() if B is not None else None
         opts.d_pre_Linv = graph.Linv.data_ptr()
         opts.d_pre_mirror = graph.mirror.data_ptr()
     info = hdg_solve_info()
@@ -597,33 +599,43 @@ def hdg_gnn_workspace(shape, mesh: Mesh, nprobe=0):
     return torch.empty(max(need.value, 8), dtype=torch.uint8, device=mesh.device)
 
 
-def hdg_gnn_forward(shape, params, mesh: Mesh, graph: GnnGraph, N=None, ws=None, stream=None):
+def _fb(shp):
+    return shp.d2 * (shp.d2 + 1) // 2
+
+
+def hdg_gnn_forward(shape, params, mesh: Mesh, graph: GnnGraph, N=None, B=None, ws=None, stream=None):
+    """Returns (N, B): the lower-block factor entries and every face's block-scaling beta."""
     shp = _shape(shape)
     if N is None:
         N = torch.empty((mesh.nnzb, shp.d2, shp.d2), dtype=torch.float32, device=mesh.device)
+    if B is None:
+        B = torch.empty((mesh.nfc, _fb(shp)), dtype=torch.float32, device=mesh.device)
     if ws is None:
         ws = hdg_gnn_workspace(shp, mesh, 0)
     _check(lib().hdg_gnn_forward(C.byref(shp), _ptr(params), C.byref(mesh.struct), C.byref(graph.struct), _ptr(N),
-                                 _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
-    return N
+                                 _ptr(B), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    return N, B
 
 
-def hdg_gnn_loss_grad(shape, params, mesh: Mesh, graph: GnnGraph, probes, N=None, grad=None, want_grad=True,
+def hdg_gnn_loss_grad(shape, params, mesh: Mesh, graph: GnnGraph, probes, N=None, B=None, grad=None, want_grad=True,
                       ws=None, stream=None):
-    """Returns (loss as a 1-element device tensor, grad, N)."""
+    """Returns (loss as a 1-element device tensor, grad, N, B)."""
     shp = _shape(shape)
     np_ = probes.shape[0]
     if N is None:
         N = torch.empty((mesh.nnzb, shp.d2, shp.d2), dtype=torch.float32, device=mesh.device)
+    if B is None:
+        B = torch.empty((mesh.nfc, _fb(shp)), dtype=torch.float32, device=mesh.device)
     if want_grad and grad is None:
         grad = torch.empty(hdg_gnn_param_count(shp), dtype=torch.float32, device=mesh.device)
     if ws is None:
         ws = hdg_gnn_workspace(shp, mesh, np_)
     loss = torch.empty(1, dtype=torch.float64, device=mesh.device)
     _check(lib().hdg_gnn_loss_grad(C.byref(shp), _ptr(params), C.byref(mesh.struct), C.byref(graph.struct),
-                                   _ptr(probes), C.c_int(np_), _ptr(N), _ptr(loss), _ptr(grad) if want_grad else None,
-                                   _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
-    return loss, grad, N
+                                   _ptr(probes), C.c_int(np_), _ptr(N), _ptr(B), _ptr(loss),
+                                   _ptr(grad) if want_grad else None, _ptr(ws), C.c_size_t(ws.numel()),
+                                   _stream(stream)))
+    return loss, grad, N, B
 
 
 def hdg_gnn_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -2,18 +2,20 @@
 // leaves the solver open).
 //
 // Scaled system.  With H_ii = L_i L_i^T, Hs_ij = L_i^{-1} H_ij L_j^{-T} (so Hs_ii = I).
-// Preconditioner.  M^{-1} = L^{-T} G^T G L^{-1}, G = I + N, N strictly block-lower on the
-// pattern of H.  It is symmetric positive definite for every N.
+// Preconditioner.  M^{-1} = L^{-T} G^T G L^{-1}, G = B (I + N), N strictly block-lower on the
+// pattern of H, B block diagonal with lower-triangular blocks of positive diagonal.  It is
+// symmetric positive definite for every N and B.
 // Network (FP32).  One node per face and one edge per off-diagonal block.  Node features
 // are the one-hot face type, log(|e| nfc^{2/3}) and the row energy sum_j ||Hs_ij||_F^2.
 // Edge features are the entries of Hs_ij.  The layers, with relu activations:
 //     X = relu(W0 a + c0),  E = relu(We b + ce),
 //     M_ij = relu(Wm_l [X_i; X_j; E_ij] + cm_l),  X_i += relu(Wu_l [X_i; sum_j M_ij] + cu_l)
-// and the head, on the lower edges with no Dirichlet face:
-//     N_ij = -Hs_ij + reshape(Wo [X_i; X_j; E_ij] + co).
-// Objective.  G is unit triangular, so det(G Hs G^T) = det(Hs) is fixed.  The Kaporin
-// number of the preconditioned matrix is then proportional to its trace, estimated with
-// probe vectors z:  loss = 1/(p n) sum_z (G^T z)^T Hs (G^T z).
+// and the heads, N on the lower edges with no Dirichlet face and beta on the other faces:
+//     N_ij = -Hs_ij + reshape(Wo [X_i; X_j; E_ij] + co),   beta_i = Wb X_i + cb,
+// B_i[a][a] = exp(beta_i[a]), B_i[a][b] = beta_i[d2 + a (a - 1) / 2 + b] (b < a).
+// Objective.  The logarithm of the Kaporin number (tr/n) / det^{1/n} of G Hs G^T, with
+// det(G Hs G^T) = det(B)^2 det(Hs):  loss = log T - (2/n) sum_i sum_a beta_i[a],
+// T = 1/(p n) sum_z (G^T z)^T Hs (G^T z) over probe vectors z.
 //
 // Kernel layout.  Every layer is a row-wise dense product over gathered, concatenated
 // inputs (one thread per output entry; the weights sit transposed in LDS, so that the
@@ -33,10 +35,11 @@ namespace {
 constexpr int kF0 = 5;        // node features
 constexpr int kWgChunks = 120;  // row chunks of the weight-gradient reduction
 
-enum SelMode { SEL_ALL = 0, SEL_OFF = 1, SEL_HEAD = 2 };
+enum SelMode { SEL_ALL = 0, SEL_OFF = 1, SEL_HEAD = 2, SEL_FREE = 3 };
 
 __device__ __forceinline__ bool selected(int mode, int r, const int* erow, const int* col, const int* ftype) {
   if (mode == SEL_ALL) return true;
+  if (mode == SEL_FREE) return ftype[r] != 1;  // node rows: every face but a Dirichlet one
   const int i = erow[r], j = col[r];
   if (mode == SEL_OFF) return i != j;
   return j < i && ftype[i] != 1 && ftype[j] != 1;
@@ -282,7 +285,51 @@ __global__ void k_gnn_nodes(int nfc, int fe, const int* __restrict__ row_ptr, co
   a[4] = (float)en;
 }
 
-// ---- probe loss: u = G^T z, hu = Hs u, loss = sum u.hu / (p n), dN_e = 2/(p n) sum_z z_i hu_j^T
+// ---- probe loss: y = B^T z, u = (I + N)^T y, hu = Hs u, T = sum u.hu / (p n),
+// loss = log T - (2/n) sum beta_diag;  dT/dN_e = 2/(p n) sum_z y_i hu_j^T,
+// dT/dB_i[a][b] = 2/(p n) sum_z z_i[a] w_i[b] with w = (I + N) hu.
+
+__device__ __forceinline__ int tri_pair_a(int q) {  // q = a (a - 1) / 2 + b, b < a  ->  a
+  int a = 1;
+  while ((a + 1) * a / 2 <= q) ++a;
+  return a;
+}
+
+// y_i[b] = sum_{a >= b} B_i[a][b] z_i[a]
+__global__ void k_apply_BT(int nfc, int d2, int np, const float* __restrict__ Bp, const float* __restrict__ z,
+                           float* __restrict__ y) {
+  const size_t n = (size_t)nfc * d2, total = n * np;
+  const int fb = d2 * (d2 + 1) / 2;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = idx / n, rem = idx % n;
+    const int i = (int)(rem / d2), b = (int)(rem % d2);
+    const float* bp = Bp + (size_t)i * fb;
+    const float* zi = z + p * n + (size_t)i * d2;
+    float acc = expf(bp[b]) * zi[b];
+    for (int a = b + 1; a < d2; ++a) acc = fmaf(bp[d2 + a * (a - 1) / 2 + b], zi[a], acc);
+    y[idx] = acc;
+  }
+}
+
+// w_i = hu_i + sum_{e in row i, col(e) < i} N_e hu_{col(e)}
+__global__ void k_apply_G(int nfc, int d2, int np, const int* __restrict__ row_ptr, const int* __restrict__ col,
+                          const float* __restrict__ N, const float* __restrict__ hu, float* __restrict__ w) {
+  const size_t n = (size_t)nfc * d2, total = n * np;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t p = idx / n, rem = idx % n;
+    const int i = (int)(rem / d2), a = (int)(rem % d2);
+    const float* hp = hu + p * n;
+    float acc = hp[rem];
+    for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      const int j = col[e];
+      if (j >= i) break;  // columns ascend
+      const float* Na = N + ((size_t)e * d2 + a) * d2;
+      for (int b = 0; b < d2; ++b) acc = fmaf(Na[b], hp[(size_t)j * d2 + b], acc);
+    }
+    w[idx] = acc;
+  }
+}
+
 
 // u_j = z_j + sum_{e' in row j, col(e') > j} N_{mirror(e')}^T z_{col(e')}
 __global__ void k_apply_GT(int nfc, int d2, int np, const int* __restrict__ row_ptr, const int* __restrict__ col,
@@ -351,10 +398,69 @@ __global__ void k_dot_fin(const double* __restrict__ part, double scale, double*
   if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
-// dD[e][a*d2+b] = sel_head(e) ? scale sum_p z_p[i][a] hu_p[j][b] : 0
+// part[block] = partial sums of beta_i[a], a < d2 (the log-diagonal of B)
+__global__ void k_logdiag_part(int nfc, int d2, const float* __restrict__ Bp, double* __restrict__ part) {
+  __shared__ double sh[kRedT];
+  const int fb = d2 * (d2 + 1) / 2;
+  const size_t n = (size_t)nfc * d2;
+  double s = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    s += (double)Bp[(i / d2) * fb + i % d2];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// out = log T - c sum(part)
+__global__ void k_loss_fin(const double* __restrict__ part, const double* __restrict__ T, double c,
+                           double* __restrict__ out) {
+  __shared__ double sh[kRedT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kRedB; i += blockDim.x) s += part[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kRedT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = log(*T) - c * sh[0];
+}
+
+// dbeta_i[q] (free faces; zero on Dirichlet faces), with S = scale / T:
+//   q < d2:  S sum_p z_p[i][q] w_p[i][q] exp(beta_i[q]) - c
+//   q >= d2 (entry (a, b) of the strict lower triangle):  S sum_p z_p[i][a] w_p[i][b]
+__global__ void k_dbeta(int nfc, int d2, int np, size_t n, const int* __restrict__ ftype, const float* __restrict__ Bp,
+                        const float* __restrict__ z, const float* __restrict__ w, const double* __restrict__ T,
+                        double scale, double c, float* __restrict__ dB) {
+  const int fb = d2 * (d2 + 1) / 2;
+  const size_t total = (size_t)nfc * fb;
+  const double S = scale / *T;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / fb), q = (int)(idx % fb);
+    float v = 0.0f;
+    if (ftype[i] != 1) {
+      int a = q, b = q;
+      if (q >= d2) {
+        a = tri_pair_a(q - d2);
+        b = q - d2 - a * (a - 1) / 2;
+      }
+      double s = 0.0;
+      for (int p = 0; p < np; ++p) s += (double)z[p * n + (size_t)i * d2 + a] * (double)w[p * n + (size_t)i * d2 + b];
+      v = q < d2 ? (float)(S * s * exp((double)Bp[idx]) - c) : (float)(S * s);
+    }
+    dB[idx] = v;
+  }
+}
+
+// dD[e][a*d2+b] = sel_head(e) ? (scale / T) sum_p y_p[i][a] hu_p[j][b] : 0
 __global__ void k_dN(int nnzb, int d2, int np, size_t n, const int* __restrict__ erow, const int* __restrict__ col,
                      const int* __restrict__ ftype, const float* __restrict__ z, const float* __restrict__ hu,
-                     float scale, float* __restrict__ dD) {
+                     const double* __restrict__ T, double scale0, float* __restrict__ dD) {
+  const double scale = scale0 / *T;
   const int fe = d2 * d2;
   const size_t total = (size_t)nnzb * fe;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
@@ -385,7 +491,7 @@ __global__ void k_adam(int64_t n, float* __restrict__ x, const float* __restrict
 // ---- host side
 
 struct Layout {
-  int64_t W0, c0, We, ce, Wo, co, total;
+  int64_t W0, c0, We, ce, Wo, co, Wb, cb, total;
   std::vector<int64_t> Wm, cm, Wu, cu;
 };
 
@@ -410,6 +516,9 @@ Layout layout(const hdg_gnn_shape& s) {
   }
   L.Wo = take((int64_t)fe * 3 * h);
   L.co = take(fe);
+  const int fb = s.d2 * (s.d2 + 1) / 2;
+  L.Wb = take((int64_t)fb * h);
+  L.cb = take(fb);
   L.total = o;
   return L;
 }
@@ -443,7 +552,7 @@ struct Carve {
 // Workspace arrays of the forward pass (train adds the backward's).
 struct Work {
   std::vector<float*> X, V, Agg, U;
-  float *Eh, *M, *dX, *dXin, *dEh, *dV, *t, *dD, *u, *hu;
+  float *Eh, *M, *dX, *dXin, *dEh, *dV, *t, *dD, *dB, *u, *hu, *y, *wv;
   double *part, *wpart, *loss;
 };
 
@@ -480,9 +589,12 @@ size_t work_bytes(const hdg_gnn_shape& s, int64_t nfc, int64_t nnzb, int nprobe,
   W.dV = F(nnzb * h);
   W.t = F(nnzb * h);
   W.dD = F(nnzb * fe);
+  W.dB = F(nfc * (size_t)s.d2 * (s.d2 + 1) / 2);
   const size_t np = (size_t)std::max(nprobe, 1);
   W.u = F(np * nfc * s.d2);
   W.hu = F(np * nfc * s.d2);
+  W.y = F(np * nfc * s.d2);
+  W.wv = F(np * nfc * s.d2);
   W.part = D(kRedB);
   W.loss = D(8);
   size_t maxp = (size_t)h * (kF0 + 1);
@@ -490,6 +602,7 @@ size_t work_bytes(const hdg_gnn_shape& s, int64_t nfc, int64_t nnzb, int nprobe,
   maxp = std::max(maxp, (size_t)h * (3 * h + 1));
   maxp = std::max(maxp, (size_t)h * (2 * h + 1));
   maxp = std::max(maxp, fe * (3 * h + 1));
+  maxp = std::max(maxp, (size_t)s.d2 * (s.d2 + 1) / 2 * (h + 1));
   W.wpart = D((size_t)kWgChunks * maxp);
   if (ok) *ok = cv.ok;
   return total;
@@ -574,7 +687,8 @@ Segs segs3(const float* a, const int* ga, int wa, const float* b, const int* gb,
     if (st__) return st__;      \
   } while (0)
 
-hdg_status forward(const Ctx& c, const hdg_gnn_shape& s, const Layout& L, const float* th, Work& w, float* N) {
+hdg_status forward(const Ctx& c, const hdg_gnn_shape& s, const Layout& L, const float* th, Work& w, float* N,
+                   float* Bp) {
   const int h = s.hidden, fe = s.d2 * s.d2, nfc = (int)c.nfc, nnzb = (int)c.nnzb;
   GNN_TRY(dense(c, nfc, segs1(c.g->node, nullptr, kF0), th + L.W0, th + L.c0, h, 1, nullptr, nullptr, nullptr,
                 w.X[0], SEL_ALL));
@@ -588,17 +702,24 @@ hdg_status forward(const Ctx& c, const hdg_gnn_shape& s, const Layout& L, const 
                   nullptr, w.U[l], w.X[l + 1], SEL_ALL));
   }
   const int Lx = s.layers;
-  return dense(c, nnzb, segs3(w.X[Lx], c.erow(), h, w.X[Lx], c.col(), h, w.Eh, nullptr, h), th + L.Wo, th + L.co, fe,
-               0, nullptr, c.g->Hs, nullptr, N, SEL_HEAD);
+  GNN_TRY(dense(c, nnzb, segs3(w.X[Lx], c.erow(), h, w.X[Lx], c.col(), h, w.Eh, nullptr, h), th + L.Wo, th + L.co, fe,
+                0, nullptr, c.g->Hs, nullptr, N, SEL_HEAD));
+  const int fb = s.d2 * (s.d2 + 1) / 2;
+  return dense(c, nfc, segs1(w.X[Lx], nullptr, h), th + L.Wb, th + L.cb, fb, 0, nullptr, nullptr, nullptr, Bp,
+               SEL_FREE);
 }
 
 hdg_status backward(const Ctx& c, const hdg_gnn_shape& s, const Layout& L, const float* th, Work& w, float* gr) {
   const int h = s.hidden, fe = s.d2 * s.d2, nfc = (int)c.nfc, nnzb = (int)c.nnzb, Lx = s.layers;
-  // head
+  const int fb = s.d2 * (s.d2 + 1) / 2;
+  // node head (w.dB is zero on Dirichlet faces)
+  GNN_TRY(wgrad(c, nfc, segs1(w.X[Lx], nullptr, h), w.dB, fb, w.wpart, gr + L.Wb, gr + L.cb));
+  GNN_TRY(dense_t(c, nfc, th + L.Wb, h, fb, 0, h, w.dB, nullptr, w.dX));
+  // edge head
   GNN_TRY(wgrad(c, nnzb, segs3(w.X[Lx], c.erow(), h, w.X[Lx], c.col(), h, w.Eh, nullptr, h), w.dD, fe, w.wpart,
                 gr + L.Wo, gr + L.co));
   GNN_TRY(dense_t(c, nnzb, th + L.Wo, 3 * h, fe, 0, h, w.dD, nullptr, w.t));
-  GNN_TRY(rowsum(c, h, w.t, w.dX, false, false, SEL_HEAD));
+  GNN_TRY(rowsum(c, h, w.t, w.dX, true, false, SEL_HEAD));
   GNN_TRY(dense_t(c, nnzb, th + L.Wo, 3 * h, fe, h, h, w.dD, nullptr, w.t));
   GNN_TRY(rowsum(c, h, w.t, w.dX, true, true, SEL_HEAD));
   GNN_TRY(dense_t(c, nnzb, th + L.Wo, 3 * h, fe, 2 * h, h, w.dD, nullptr, w.dEh));
@@ -706,23 +827,24 @@ extern "C" hdg_status hdg_gnn_workspace_size(const hdg_gnn_shape* shape, const h
 }
 
 extern "C" hdg_status hdg_gnn_forward(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
-                                      const hdg_gnn_graph* graph, float* d_N, void* d_ws, size_t ws_bytes,
+                                      const hdg_gnn_graph* graph, float* d_N, float* d_B, void* d_ws, size_t ws_bytes,
                                       void* stream) {
   GNN_TRY(check_common(shape, mesh, graph, "hdg_gnn_forward"));
-  if (!d_params || !d_N || !d_ws) return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_forward: NULL argument");
+  if (!d_params || !d_N || !d_B || !d_ws) return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_forward: NULL argument");
   Work w;
   bool ok = false;
   work_bytes(*shape, mesh->nfc, mesh->nnzb, 0, true, &w, d_ws, ws_bytes, &ok);
   if (!ok) return set_error(HDG_ERR_WORKSPACE, "hdg_gnn_forward: workspace too small");
   Ctx c{(hipStream_t)stream, mesh->nfc, mesh->nnzb, mesh, graph};
-  return forward(c, *shape, layout(*shape), d_params, w, d_N);
+  return forward(c, *shape, layout(*shape), d_params, w, d_N, d_B);
 }
 
 extern "C" hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
                                         const hdg_gnn_graph* graph, const float* d_probes, int nprobe, float* d_N,
-                                        double* d_loss, float* d_grad, void* d_ws, size_t ws_bytes, void* stream) {
+                                        float* d_B, double* d_loss, float* d_grad, void* d_ws, size_t ws_bytes,
+                                        void* stream) {
   GNN_TRY(check_common(shape, mesh, graph, "hdg_gnn_loss_grad"));
-  if (!d_params || !d_probes || nprobe < 1 || !d_N || !d_loss || !d_ws)
+  if (!d_params || !d_probes || nprobe < 1 || !d_N || !d_B || !d_loss || !d_ws)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_loss_grad: NULL argument or nprobe < 1");
   Work w;
   bool ok = false;
@@ -730,21 +852,28 @@ extern "C" hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float*
   if (!ok) return set_error(HDG_ERR_WORKSPACE, "hdg_gnn_loss_grad: workspace too small");
   Ctx c{(hipStream_t)stream, mesh->nfc, mesh->nnzb, mesh, graph};
   const Layout L = layout(*shape);
-  GNN_TRY(forward(c, *shape, L, d_params, w, d_N));
+  GNN_TRY(forward(c, *shape, L, d_params, w, d_N, d_B));
   const int d2 = shape->d2, nfc = (int)mesh->nfc;
   const size_t n = (size_t)nfc * d2;
+  k_apply_BT<<<grid_for(n * nprobe), 256, 0, c.s>>>(nfc, d2, nprobe, d_B, d_probes, w.y);
   k_apply_GT<<<grid_for(n * nprobe), 256, 0, c.s>>>(nfc, d2, nprobe, mesh->d_row_ptr, mesh->d_col_idx, graph->mirror,
-                                                     d_N, d_probes, w.u);
+                                                     d_N, w.y, w.u);
   k_spmv_hs<<<grid_for(n * nprobe), 256, 0, c.s>>>(nfc, d2, nprobe, mesh->d_row_ptr, mesh->d_col_idx, graph->Hs, w.u,
                                                     w.hu);
   const double scale = 1.0 / ((double)nprobe * (double)n);
   k_dot_part<<<kRedB, kRedT, 0, c.s>>>(w.u, w.hu, n * nprobe, w.part);
-  k_dot_fin<<<1, kRedT, 0, c.s>>>(w.part, scale, d_loss);
+  k_dot_fin<<<1, kRedT, 0, c.s>>>(w.part, scale, w.loss);  // T
+  k_logdiag_part<<<kRedB, kRedT, 0, c.s>>>(nfc, d2, d_B, w.part);
+  k_loss_fin<<<1, kRedT, 0, c.s>>>(w.part, w.loss, 2.0 / (double)n, d_loss);
   HDG_CHECK_LAUNCH("hdg_gnn_loss_grad loss");
   if (!d_grad) return HDG_OK;
   k_dN<<<grid_for((size_t)mesh->nnzb * d2 * d2), 256, 0, c.s>>>((int)mesh->nnzb, d2, nprobe, n, graph->erow,
-                                                                  mesh->d_col_idx, mesh->d_ftype, d_probes, w.hu,
-                                                                  (float)(2.0 * scale), w.dD);
+                                                                  mesh->d_col_idx, mesh->d_ftype, w.y, w.hu, w.loss,
+                                                                  2.0 * scale, w.dD);
+  k_apply_G<<<grid_for(n * nprobe), 256, 0, c.s>>>(nfc, d2, nprobe, mesh->d_row_ptr, mesh->d_col_idx, d_N, w.hu, w.wv);
+  k_dbeta<<<grid_for((size_t)nfc * d2 * (d2 + 1) / 2), 256, 0, c.s>>>(nfc, d2, nprobe, n, mesh->d_ftype, d_B, d_probes,
+                                                                        w.wv, w.loss, 2.0 * scale, 2.0 / (double)n,
+                                                                        w.dB);
   return backward(c, *shape, L, d_params, w, d_grad);
 }
 

@@ -174,26 +174,46 @@ __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_scale(const float* _
 }
 
 // s_i = t_i + sum_{j < i} N_ij t_j: the lower blocks of row i are the entries before the
-// diagonal (columns ascend)
+// diagonal (columns ascend).  With a block scaling (Bp not NULL) the kernel stores
+// B_i^T B_i s_i instead: B_i lower triangular, B_i[a][a] = exp(Bp_i[a]),
+// B_i[a][b] = Bp_i[D2 + a (a - 1) / 2 + b] (b < a); a face's components meet in LDS.
 template <int D2, class TV>
 __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_lower(const int* __restrict__ row_ptr,
                                                                   const int* __restrict__ diag,
                                                                   const int* __restrict__ col,
                                                                   const float* __restrict__ N,
+                                                                  const float* __restrict__ Bp,
                                                                   const TV* __restrict__ t, TV* __restrict__ s,
                                                                   int nfc) {
-  const int i = blockIdx.x * Lpre<D2>::FACES + threadIdx.x / D2, a = threadIdx.x % D2;
-  if (i >= nfc) return;
-  const int e0 = row_ptr[i], e1 = diag[i];
-  double acc = (double)t[(size_t)i * D2 + a];
+  constexpr int FB = D2 * (D2 + 1) / 2;
+  __shared__ double sv[Lpre<D2>::THREADS];
+  const int lf = threadIdx.x / D2, a = threadIdx.x % D2;
+  const int i = blockIdx.x * Lpre<D2>::FACES + lf;
+  double acc = 0.0;
+  if (i < nfc) {
+    const int e0 = row_ptr[i], e1 = diag[i];
+    acc = (double)t[(size_t)i * D2 + a];
 #pragma unroll 3
-  for (int e = e0; e < e1; ++e) {
-    const TV* tj = t + (size_t)col[e] * D2;
-    const float* Na = N + ((size_t)e * D2 + a) * D2;
+    for (int e = e0; e < e1; ++e) {
+      const TV* tj = t + (size_t)col[e] * D2;
+      const float* Na = N + ((size_t)e * D2 + a) * D2;
 #pragma unroll
-    for (int b = 0; b < D2; ++b) acc += (double)Na[b] * (double)tj[b];
+      for (int b = 0; b < D2; ++b) acc += (double)Na[b] * (double)tj[b];
+    }
   }
-  s[(size_t)i * D2 + a] = (TV)acc;
+  if (Bp) {  // uniform over the launch
+    const float* bp = Bp + (size_t)(i < nfc ? i : 0) * FB;
+    sv[threadIdx.x] = acc;
+    __syncthreads();
+    double v = exp((double)bp[a]) * sv[lf * D2 + a];  // v = B_i s_i
+    for (int b = 0; b < a; ++b) v += (double)bp[D2 + a * (a - 1) / 2 + b] * sv[lf * D2 + b];
+    __syncthreads();
+    sv[threadIdx.x] = v;
+    __syncthreads();
+    acc = exp((double)bp[a]) * sv[lf * D2 + a];  // B_i^T v
+    for (int c = a + 1; c < D2; ++c) acc += (double)bp[D2 + c * (c - 1) / 2 + a] * sv[lf * D2 + c];
+  }
+  if (i < nfc) s[(size_t)i * D2 + a] = (TV)acc;
 }
 
 // z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i): the upper entries of row j, each read
@@ -377,7 +397,8 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   auto pre64 = [&](const double* rr_, double* zz_) {
     if (learned) {  // t -> zz_, s -> sw, then z -> zz_
       k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
-      k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N, zz_,
+      k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                 o->d_pre_B, zz_,
                                                  sw, nfc);
       k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_mirror,
                                                  o->d_pre_N, o->d_pre_Linv, sw, zz_, nfc);
@@ -388,7 +409,8 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   auto pre32 = [&](const float* rr_, float* zz_) {
     if (learned) {
       k_lpre_scale<D2, float><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
-      k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N, zz_,
+      k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                o->d_pre_B, zz_,
                                                 sw32, nfc);
       k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_mirror,
                                                 o->d_pre_N, o->d_pre_Linv, sw32, zz_, nfc);
@@ -561,13 +583,13 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
 namespace hdg {
 namespace {
 template <int D2>
-void lpre_apply64(const hdg_mesh* mesh, const float* N, const float* Linv, const int* mirror, const double* r,
-                  double* z, double* tmp, hipStream_t s) {
+void lpre_apply64(const hdg_mesh* mesh, const float* N, const float* Bp, const float* Linv, const int* mirror,
+                  const double* r, double* z, double* tmp, hipStream_t s) {
   const int nfc = (int)mesh->nfc;
   const unsigned gf = (unsigned)((nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES);
   constexpr unsigned TL = Lpre<D2>::THREADS;
   k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(Linv, r, z, nfc);
-  k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, N, z, tmp, nfc);
+  k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, N, Bp, z, tmp, nfc);
   k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, mirror, N, Linv, tmp, z,
                                              nfc);
 }
@@ -575,7 +597,8 @@ void lpre_apply64(const hdg_mesh* mesh, const float* N, const float* Linv, const
 }  // namespace hdg
 
 extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N,
-                                            const float* d_Linv, const int32_t* d_mirror, const double* d_r,
+                                            const float* d_B, const float* d_Linv, const int32_t* d_mirror,
+                                            const double* d_r,
                                             double* d_z, void* d_ws, size_t ws_bytes, void* stream) {
   hdg_status st = check_disc_mesh(disc, mesh, "hdg_gnn_precond_apply");
   if (st) return st;
@@ -587,11 +610,11 @@ extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh
   hipStream_t s = (hipStream_t)stream;
   double* tmp = (double*)d_ws;
   switch (disc->host.k) {
-    case 0: lpre_apply64<dim2(0)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 1: lpre_apply64<dim2(1)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 2: lpre_apply64<dim2(2)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 3: lpre_apply64<dim2(3)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 4: lpre_apply64<dim2(4)>(mesh, d_N, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 0: lpre_apply64<dim2(0)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 1: lpre_apply64<dim2(1)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 2: lpre_apply64<dim2(2)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 3: lpre_apply64<dim2(3)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 4: lpre_apply64<dim2(4)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
     default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_gnn_precond_apply: unsupported degree");
   }
   HDG_CHECK_LAUNCH("hdg_gnn_precond_apply");

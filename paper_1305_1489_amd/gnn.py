@@ -31,7 +31,8 @@ def param_layout(d2: int, hidden: int, layers: int):
     lay = [("W0", (h, F0)), ("c0", (h,)), ("We", (h, fe)), ("ce", (h,))]
     for l in range(layers):
         lay += [(f"Wm{l}", (h, 3 * h)), (f"cm{l}", (h,)), (f"Wu{l}", (h, 2 * h)), (f"cu{l}", (h,))]
-    lay += [("Wo", (fe, 3 * h)), ("co", (fe,))]
+    fb = d2 * (d2 + 1) // 2
+    lay += [("Wo", (fe, 3 * h)), ("co", (fe,)), ("Wb", (fb, h)), ("cb", (fb,))]
     return lay
 
 
@@ -45,7 +46,7 @@ class LearnedPreconditioner:
             gen = torch.Generator().manual_seed(seed)
             parts = []
             for name, sh in param_layout(d2, hidden, layers):
-                if name.startswith("W") and name != "Wo":  # He initialisation; the head starts at zero
+                if name.startswith("W") and name not in ("Wo", "Wb"):  # He initialisation; both heads start at zero
                     parts.append(torch.randn(sh, generator=gen, dtype=torch.float64).ravel() * math.sqrt(2.0 / sh[1]))
                 else:
                     parts.append(torch.zeros(int(torch.tensor(sh).prod())), )
@@ -58,10 +59,11 @@ class LearnedPreconditioner:
 
     # ---- inference
     def prepare(self, disc, mesh, H, stream=None):
-        """Graph of the system and the factor N (for hdg_solve(..., learned=(N, graph)))."""
+        """Graph of the system, the factor N and the block scaling B (for
+        hdg_solve(..., learned=(N, B, graph)))."""
         g = L.hdg_gnn_build_graph(disc, mesh, H, stream=stream)
-        N = L.hdg_gnn_forward(self.shape, self.params, mesh, g, ws=self._workspace(mesh, 0), stream=stream)
-        return g, N
+        N, B = L.hdg_gnn_forward(self.shape, self.params, mesh, g, ws=self._workspace(mesh, 0), stream=stream)
+        return g, N, B
 
     def _workspace(self, mesh, nprobe):
         key = (id(mesh), nprobe)
@@ -71,8 +73,8 @@ class LearnedPreconditioner:
 
     def loss(self, mesh, graph, nprobe=16, seed=0):
         z = self.probes(mesh, nprobe, seed)
-        loss, _, _ = L.hdg_gnn_loss_grad(self.shape, self.params, mesh, graph, z, want_grad=False,
-                                         ws=self._workspace(mesh, nprobe))
+        loss, _, _, _ = L.hdg_gnn_loss_grad(self.shape, self.params, mesh, graph, z, want_grad=False,
+                                            ws=self._workspace(mesh, nprobe))
         return float(loss.item())
 
     def probes(self, mesh, nprobe, seed):
@@ -94,7 +96,7 @@ class LearnedPreconditioner:
             for _ in range(steps_per_system):
                 t += 1
                 z = self.probes(mesh, nprobe, seed * 1000003 + t)
-                loss, _, _ = L.hdg_gnn_loss_grad(self.shape, self.params, mesh, g, z, grad=grad, ws=ws)
+                loss, _, _, _ = L.hdg_gnn_loss_grad(self.shape, self.params, mesh, g, z, grad=grad, ws=ws)
                 L.hdg_gnn_adam(self.params, grad, m, v, t, lr=lr)
                 hist.append(loss)
             if log and (si + 1) % 100 == 0:

@@ -23,9 +23,10 @@ def test_shape_errors():
 
 def test_checkpoint_round_trip(tmp_path):
     lp = LearnedPreconditioner(6, hidden=8, layers=2, seed=3, device="cpu")
-    # head starts at zero, weights are random
+    # both heads (Wo, co, Wb, cb) start at zero, the other weights are random
     lay = param_layout(6, 8, 2)
-    o = sum(int(torch.tensor(sh).prod()) for _, sh in lay[:-2])
+    assert [n for n, _ in lay[-4:]] == ["Wo", "co", "Wb", "cb"]
+    o = sum(int(torch.tensor(sh).prod()) for _, sh in lay[:-4])
     assert not lp.params[o:].any() and lp.params[:o].abs().sum() > 0
     lp.meta.update(systems=7, train_seconds=1.5)
     p = str(tmp_path / "g.safetensors")
@@ -43,3 +44,4 @@ def test_packaged_checkpoint_loads():
     lp = LearnedPreconditioner.load(GNN_CHECKPOINT, device="cpu")
     assert lp.d2 == 6 and lp.meta.get("systems") == 2000
     assert torch.isfinite(lp.params).all()
+    assert lp.meta["last_loss"] < lp.meta["first_loss"]  # training lowered the objective

@@ -3,7 +3,9 @@
 The preconditioner family and its network are not in the paper, so nothing here is a
 printed value.  Parity of the definitions is pinned instead:
   * the hand-written backward against central differences of the forward pass;
-  * the probe loss and its N-gradient against dense linear algebra (exact with unit probes);
+  * the log-Kaporin probe loss and its N- and B-gradients against dense linear algebra
+    (exact with unit probes: log(tr/n^2) and log det G by slogdet);
+  * the Kaporin stationarity of the optimal block scaling B_i = chol(A_ii)^{-1};
   * the structure: unit-diagonal scaling, SPD preconditioner, mirror and pattern integrity.
 """
 import numpy as np
@@ -82,34 +84,99 @@ def test_zero_head_is_first_order_factor(sysk1):
     S = sysk1
     s = OGN.Shape(S["d2"], hidden=8, layers=2)
     th = OGN.init_params(s, seed=1)
-    N, _ = OGN.forward(th, s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype)
+    N, beta, _ = OGN.forward(th, s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype)
     ft = S["ex"].ftype
     low = (S["ci"] < S["er"]) & (ft[S["er"]] != 1) & (ft[S["ci"]] != 1)
     assert np.array_equal(N[low], -S["g"]["Hs"][low])
     assert not N[~low].any()
+    assert not beta.any()  # B = I
+    assert np.array_equal(OGN.block_scale(beta, S["d2"]), np.broadcast_to(np.eye(S["d2"]), (S["ex"].nfc, S["d2"], S["d2"])))
 
 
-def test_trace_loss_with_unit_probes_is_the_trace(sysk1):
-    S = sysk1
-    s = OGN.Shape(S["d2"], hidden=8, layers=2)
-    rng = np.random.default_rng(3)
-    th = OGN.init_params(s, seed=2)
-    th[-(s.fe * 3 * s.hidden + s.fe):] = 0.05 * rng.standard_normal(s.fe * 3 * s.hidden + s.fe)
-    N, _ = OGN.forward(th, s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype)
+def _dense_G(N, beta, S):
     nfc, d2 = S["ex"].nfc, S["d2"]
     n = nfc * d2
+    Bm = OGN.block_scale(beta, d2)
+    Bd = np.zeros((n, n))
+    for i in range(nfc):
+        Bd[i * d2:(i + 1) * d2, i * d2:(i + 1) * d2] = Bm[i]
+    return Bd, np.eye(n) + dense_blocks(N, S["rp"], S["ci"], S["er"], nfc, d2)
+
+
+def _random_heads(S, s, seed):
+    rng = np.random.default_rng(seed)
+    th = OGN.init_params(s, seed=seed)
+    th += 0.05 * rng.standard_normal(th.size)
+    N, beta, _ = OGN.forward(th, s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype)
+    return N, beta
+
+
+def test_kaporin_loss_with_unit_probes(sysk1):
+    """Unit probes make T the exact trace: T = tr(G Hs G^T) / n^2.  The loss is then
+    log T - (1/n) log(det(G Hs G^T) / det(Hs)) = log T - (2/n) log det G, with det G by a
+    dense LU (slogdet) of the product G = B (I + N), and the gradients are those of the dense
+    formula d tr(G Hs G^T) / dG = 2 G Hs."""
+    S = sysk1
+    s = OGN.Shape(S["d2"], hidden=8, layers=2)
+    N, beta = _random_heads(S, s, 3)
+    nfc, d2 = S["ex"].nfc, S["d2"]
+    n = nfc * d2
+    assert beta[S["ex"].ftype != 1].any() and not beta[S["ex"].ftype == 1].any()
     Z = np.eye(n).reshape(n, nfc, d2)
-    loss, dN = OGN.trace_loss(N, S["g"]["Hs"], S["rp"], S["ci"], S["er"], Z)
-    G = np.eye(n) + dense_blocks(N, S["rp"], S["ci"], S["er"], nfc, d2)
+    loss, dN, dbeta = OGN.kaporin_loss(N, beta, S["g"]["Hs"], S["rp"], S["ci"], S["er"], Z)
+    Bd, U = _dense_G(N, beta, S)
+    G = Bd @ U
     Hs = dense_blocks(S["g"]["Hs"], S["rp"], S["ci"], S["er"], nfc, d2)
-    assert abs(loss - np.trace(G @ Hs @ G.T) / (n * n)) < 1e-12 * abs(loss)
-    # d tr(G Hs G^T) / dG = 2 G Hs, restricted to the strictly lower blocks
-    Dg = 2.0 * G @ Hs / (n * n)
+    A = G @ Hs @ G.T
+    T = np.trace(A) / (n * n)
+    ld = 2.0 * np.linalg.slogdet(G)[1]
+    assert abs(loss - (np.log(T) - ld / n)) < 1e-11
+    dG = 2.0 * G @ Hs / (n * n)                 # dT/dG
+    dU = Bd.T @ dG                              # dT/d(I + N)
+    dB = dG @ U.T                               # dT/dB
     low = S["ci"] < S["er"]
     for e in np.where(low)[0][:40]:
         i, j = S["er"][e], S["ci"][e]
-        assert np.abs(dN[e] - Dg[i * d2:(i + 1) * d2, j * d2:(j + 1) * d2]).max() < 1e-12 * np.abs(Dg).max()
+        ref = dU[i * d2:(i + 1) * d2, j * d2:(j + 1) * d2] / T
+        assert np.abs(dN[e] - ref).max() < 1e-10 * np.abs(dU / T).max()
     assert not dN[~low].any()
+    Bm = OGN.block_scale(beta, d2)
+    for i in range(nfc):
+        blk = dB[i * d2:(i + 1) * d2, i * d2:(i + 1) * d2] / T
+        for a in range(d2):
+            ref = blk[a, a] * Bm[i, a, a] - 2.0 / n
+            assert abs(dbeta[i, a] - ref) < 1e-10 * max(1.0, abs(ref))
+            for b in range(a):
+                assert abs(dbeta[i, d2 + a * (a - 1) // 2 + b] - blk[a, b]) < 1e-10 * max(1.0, abs(blk[a, b]))
+
+
+def test_optimal_block_scaling_is_stationary(sysk1):
+    """For fixed N the Kaporin measure is minimised over the lower-triangular B_i by
+    B_i = chol(A_ii)^{-1}, A = (I + N) Hs (I + N)^T (then B_i A_ii B_i^T = I): the gradient
+    in beta vanishes there (unit probes, exact)."""
+    S = sysk1
+    s = OGN.Shape(S["d2"], hidden=8, layers=2)
+    N, _ = _random_heads(S, s, 11)
+    nfc, d2 = S["ex"].nfc, S["d2"]
+    n = nfc * d2
+    _, U = _dense_G(N, np.zeros((nfc, s.fb)), S)
+    Hs = dense_blocks(S["g"]["Hs"], S["rp"], S["ci"], S["er"], nfc, d2)
+    A = U @ Hs @ U.T
+    beta = np.zeros((nfc, s.fb))
+    for i in range(nfc):
+        Bi = np.linalg.inv(np.linalg.cholesky(A[i * d2:(i + 1) * d2, i * d2:(i + 1) * d2]))
+        for a in range(d2):
+            beta[i, a] = np.log(Bi[a, a])
+            for b in range(a):
+                beta[i, d2 + a * (a - 1) // 2 + b] = Bi[a, b]
+    beta[S["ex"].ftype == 1] = 0.0  # identity blocks there: chol(I)^{-1} = I
+    Z = np.eye(n).reshape(n, nfc, d2)
+    _, _, dbeta = OGN.kaporin_loss(N, beta, S["g"]["Hs"], S["rp"], S["ci"], S["er"], Z)
+    assert np.abs(dbeta).max() < 1e-9
+    # and a perturbation raises the loss
+    l0 = OGN.kaporin_loss(N, beta, S["g"]["Hs"], S["rp"], S["ci"], S["er"], Z)[0]
+    bp = beta + 0.05 * np.random.default_rng(2).standard_normal(beta.shape) * (S["ex"].ftype != 1)[:, None]
+    assert OGN.kaporin_loss(N, bp, S["g"]["Hs"], S["rp"], S["ci"], S["er"], Z)[0] > l0
 
 
 def test_backward_matches_central_differences(sysk1):
@@ -121,7 +188,7 @@ def test_backward_matches_central_differences(sysk1):
     nfc, d2 = S["ex"].nfc, S["d2"]
     Z = rng.choice([-1.0, 1.0], size=(3, nfc, d2))
     args = (s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype, Z)
-    loss, grad, _ = OGN.loss_and_grad(th, *args)
+    loss, grad, _, _ = OGN.loss_and_grad(th, *args)
     offs = np.cumsum([0] + [int(np.prod(sh)) for _, sh in OGN.param_layout(s)])
     idx = np.concatenate([rng.choice(np.arange(a, b), size=min(4, b - a), replace=False)
                           for a, b in zip(offs[:-1], offs[1:])])
@@ -139,10 +206,18 @@ def test_preconditioner_is_spd(sysk1):
     s = OGN.Shape(S["d2"], hidden=8, layers=2)
     th = OGN.init_params(s, seed=7)
     th += 0.1 * np.random.default_rng(8).standard_normal(th.size)
-    N, _ = OGN.forward(th, s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype)
+    N, beta, _ = OGN.forward(th, s, S["g"], S["rp"], S["ci"], S["er"], S["ex"].ftype)
+    assert beta.any()
     nfc, d2 = S["ex"].nfc, S["d2"]
     n = nfc * d2
-    Minv = np.stack([OGN.preconditioner_apply(N, S["g"]["Linv"], e.reshape(nfc, d2), S["rp"], S["ci"],
+    Minv = np.stack([OGN.preconditioner_apply(N, beta, S["g"]["Linv"], e.reshape(nfc, d2), S["rp"], S["ci"],
                                               S["er"]).ravel() for e in np.eye(n)], 1)
+    # the definition M^{-1} = L^{-T} G^T G L^{-1} written densely
+    Bd, U = _dense_G(N, beta, S)
+    Li = np.zeros((n, n))
+    for i in range(nfc):
+        Li[i * d2:(i + 1) * d2, i * d2:(i + 1) * d2] = S["g"]["Linv"][i]
+    G = Bd @ U
+    assert np.abs(Minv - Li.T @ G.T @ G @ Li).max() < 1e-12 * np.abs(Minv).max()
     assert np.abs(Minv - Minv.T).max() < 1e-12 * np.abs(Minv).max()
     assert np.linalg.eigvalsh(0.5 * (Minv + Minv.T)).min() > 0
