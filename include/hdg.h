@@ -478,7 +478,8 @@ hdg_status hdg_export_local_cd(const hdg_disc* disc, const hdg_mesh* mesh, const
 
 /* Restarted GMRES(restart) for the non-symmetric trace system after hdg_boundary (the paper
  * leaves the solver open): right preconditioning by the inverses of the d2 x d2 diagonal
- * blocks (Gauss-Jordan with partial pivoting), classical Gram-Schmidt applied twice,
+ * blocks (Gauss-Jordan with partial pivoting), classical Gram-Schmidt with selective
+ * reorthogonalisation,
  * fixed-order reductions (the same bits on every run).  The host solves the small
  * least-squares problem (Givens rotations) and reads one short vector per iteration; every
  * cycle starts from the true FP64 residual b - H x, and the solve ends when
@@ -486,7 +487,8 @@ hdg_status hdg_export_local_cd(const hdg_disc* disc, const hdg_mesh* mesh, const
  *   d_uhat  in: initial guess (Dirichlet values set by hdg_boundary); out: the solution
  *   restart 1..64;  workspace of hdg_solve_gmres_workspace_size bytes, caller-owned
  *   info->iterations = inner iterations, info->outer = cycles, info->rel_residual the
- *   true relative residual.
+ *   true relative residual, info->fell_back = the number of Arnoldi steps that took a second
+ *   Gram-Schmidt pass (taken when the first left less than 1e-3 of ||w||).
  * Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE, HDG_ERR_NOT_CONVERGED (the solution at
  * max_iter is still written). */
 hdg_status hdg_solve_gmres_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, int restart, size_t* ws_bytes);

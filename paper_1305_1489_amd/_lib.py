@@ -726,7 +726,8 @@ def hdg_solve_gmres(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=200
     code = lib().hdg_solve_gmres(disc.handle, C.byref(mesh.struct), _ptr(H), _ptr(b), _ptr(uhat), C.c_double(rtol),
                                  C.c_int(max_iter), C.c_int(restart), C.byref(info), _ptr(ws),
                                  C.c_size_t(ws.numel()), _stream(stream))
-    out = {"iterations": info.iterations, "cycles": info.outer, "rel_residual": info.rel_residual, "status": code}
+    out = {"iterations": info.iterations, "cycles": info.outer, "rel_residual": info.rel_residual, "status": code,
+           "reorthogonalised": info.fell_back}
     if code != 0 and raise_on_fail:
         _check(code)
     return out

@@ -1,7 +1,9 @@
 // Global solve of the trace system H uhat = b (eq 6.5 after the Dirichlet elimination).
 // The paper leaves the solver open; this is preconditioned conjugate gradients with a
 // block-Jacobi preconditioner (explicit inverse of each d2 x d2 diagonal block, via its
-// Cholesky factor).  Reductions are two-stage with a fixed grid and a fixed combining
+// Cholesky factor).  One iteration is five launches: H p with the workgroup partials of
+// p.Ap, their sum, the x and r updates fused with z = Minv r and the partials of r.z, their
+// sum, and p = z + beta p.  Reductions are two-stage with a fixed grid and a fixed combining
 // order, so every run gives the same bits.  alpha and beta live on the device; the host
 // reads the residual norm every check_every iterations, and accepts the iterate only when
 // the recomputed residual ||b - H x|| (FP64) meets the tolerance (otherwise the recursive
@@ -65,13 +67,10 @@ __global__ void k_convert(const double* __restrict__ a, T* __restrict__ b, size_
     b[i] = (T)a[i];
 }
 
-// ---- y = alpha_y * y + H x  (alpha_y = 0: y = H x), one thread per row entry
+// Row entry c of block row f of H x, the blocks summed in storage order.
 template <int D2, class TM, class TV>
-__global__ void k_spmv(const int* __restrict__ row_ptr, const int* __restrict__ col_idx, const TM* __restrict__ H,
-                       const TV* __restrict__ x, TV* __restrict__ y, int nfc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nfc * D2) return;
-  const int f = i / D2, c = i % D2;
+__device__ __forceinline__ double row_dot(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                          const TM* __restrict__ H, const TV* __restrict__ x, int f, int c) {
   double s = 0;
   for (int p = row_ptr[f]; p < row_ptr[f + 1]; ++p) {
     const TM* blk = H + ((size_t)p * D2 + c) * D2;
@@ -79,7 +78,16 @@ __global__ void k_spmv(const int* __restrict__ row_ptr, const int* __restrict__ 
 #pragma unroll
     for (int j = 0; j < D2; ++j) s += (double)blk[j] * (double)xv[j];
   }
-  y[i] = (TV)s;
+  return s;
+}
+
+// ---- y = H x, one thread per row entry
+template <int D2, class TM, class TV>
+__global__ void k_spmv(const int* __restrict__ row_ptr, const int* __restrict__ col_idx, const TM* __restrict__ H,
+                       const TV* __restrict__ x, TV* __restrict__ y, int nfc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nfc * D2) return;
+  y[i] = (TV)row_dot<D2>(row_ptr, col_idx, H, x, i / D2, i % D2);
 }
 
 // r = b - H x
@@ -89,15 +97,7 @@ __global__ void k_residual(const int* __restrict__ row_ptr, const int* __restric
                            double* __restrict__ r, int nfc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nfc * D2) return;
-  const int f = i / D2, c = i % D2;
-  double s = 0;
-  for (int p = row_ptr[f]; p < row_ptr[f + 1]; ++p) {
-    const double* blk = H + ((size_t)p * D2 + c) * D2;
-    const double* xv = x + (size_t)col_idx[p] * D2;
-#pragma unroll
-    for (int j = 0; j < D2; ++j) s += blk[j] * xv[j];
-  }
-  r[i] = b[i] - s;
+  r[i] = b[i] - row_dot<D2>(row_ptr, col_idx, H, x, i / D2, i % D2);
 }
 
 // ---- deterministic dot products: partial sums per block, fixed grid; final in one block
@@ -253,28 +253,240 @@ __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_upper(const int* __r
   z[(size_t)j * D2 + a] = (TV)v;
 }
 
-// scal[0] = rz, scal[1] = pAp, scal[2] = rz_new, scal[3] = rr
-// x += alpha p, r -= alpha Ap, alpha = rz / pAp
+// ---- fused PCG iteration (block-Jacobi).  The scalars live on the device: scal[1] = p.Ap,
+// and rz alternates between scal[0] and scal[2] (slot `old` holds r.z of the previous
+// iteration, the other slot receives the new one), so no kernel has to shift them.
+// Every reduction is per workgroup into part[], then k_sum_parts in a fixed order.
+
+// Coalesced form for even block sizes (d2 = 6, 10): each row entry of a face is shared by
+// d2/2 consecutive lanes, lane q taking columns 2q, 2q+1 of every block of the row, so that
+// the d2 * d2/2 lanes of a face read each d2 x d2 block as one contiguous segment (one
+// 16-byte load per lane in FP64) and the matching x pairs.  The faces of a workgroup are
+// whole (FACES per workgroup); the partial sums of a row entry meet in LDS and are added in
+// lane order.  With PAP, part[wg] = the workgroup's share of p.Ap.
+template <int D2>
+struct SpmvC {
+  static_assert(D2 % 2 == 0, "pairs of columns");
+  static constexpr int LPR = D2 / 2, LPF = D2 * LPR, FACES = 256 / LPF, THREADS = FACES * LPF;
+};
+
+template <class T>
+struct Pair;
+template <>
+struct Pair<double> {
+  using type = double2;
+};
+template <>
+struct Pair<float> {
+  using type = float2;
+};
+
+template <int D2, class TM, class TV, bool PAP>
+__global__ void __launch_bounds__(256) k_spmv_c(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                                const TM* __restrict__ H, const TV* __restrict__ x,
+                                                TV* __restrict__ y, int nfc, double* __restrict__ part) {
+  using C = SpmvC<D2>;
+  using PM = typename Pair<TM>::type;
+  using PV = typename Pair<TV>::type;
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
+  const int lf = t / C::LPF, w = t % C::LPF, r = w / C::LPR, q = w % C::LPR;
+  const int ngroups = (nfc + C::FACES - 1) / C::FACES;
+  double contrib = 0;
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {  // uniform over the workgroup
+    const int f = g * C::FACES + lf;
+    const bool on = t < C::THREADS && f < nfc;
+    double s = 0;
+    if (on) {
+      const int p1 = row_ptr[f + 1];
+      int p = row_ptr[f];
+      for (; p + 1 < p1; p += 2) {  // two blocks in flight
+        const int c0 = col_idx[p], c1 = col_idx[p + 1];
+        const PM h0 = *reinterpret_cast<const PM*>(H + ((size_t)p * D2 + r) * D2 + 2 * q);
+        const PM h1 = *reinterpret_cast<const PM*>(H + ((size_t)(p + 1) * D2 + r) * D2 + 2 * q);
+        const PV x0 = *reinterpret_cast<const PV*>(x + (size_t)c0 * D2 + 2 * q);
+        const PV x1 = *reinterpret_cast<const PV*>(x + (size_t)c1 * D2 + 2 * q);
+        s += (double)h0.x * (double)x0.x;
+        s += (double)h0.y * (double)x0.y;
+        s += (double)h1.x * (double)x1.x;
+        s += (double)h1.y * (double)x1.y;
+      }
+      if (p < p1) {
+        const PM h = *reinterpret_cast<const PM*>(H + ((size_t)p * D2 + r) * D2 + 2 * q);
+        const PV xv = *reinterpret_cast<const PV*>(x + (size_t)col_idx[p] * D2 + 2 * q);
+        s += (double)h.x * (double)xv.x;
+        s += (double)h.y * (double)xv.y;
+      }
+    }
+    __syncthreads();
+    sh[t] = s;
+    __syncthreads();
+    if (on && q == 0) {
+      double v = sh[t];
+#pragma unroll
+      for (int k = 1; k < C::LPR; ++k) v += sh[t + k];
+      const size_t i = (size_t)f * D2 + r;
+      const TV yv = (TV)v;
+      y[i] = yv;
+      if (PAP) contrib += (double)yv * (double)x[i];
+    }
+  }
+  if (PAP) {
+    __syncthreads();
+    sh[t] = contrib;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) sh[t] += sh[t + o];
+      __syncthreads();
+    }
+    if (t == 0) part[blockIdx.x] = sh[0];
+  }
+}
+
+// Ap = H p (one thread per row entry, 256 per workgroup) and part[wg] = sum of p.Ap over the
+// workgroup's rows
+template <int D2, class TM, class TV>
+__global__ void __launch_bounds__(256) k_spmv_pap(const int* __restrict__ row_ptr, const int* __restrict__ col_idx,
+                                                  const TM* __restrict__ H, const TV* __restrict__ x,
+                                                  TV* __restrict__ y, int nfc, double* __restrict__ part) {
+  __shared__ double sh[256];
+  double contrib = 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < nfc * D2; i += gridDim.x * 256) {
+    const TV yv = (TV)row_dot<D2>(row_ptr, col_idx, H, x, i / D2, i % D2);
+    y[i] = yv;
+    contrib += (double)yv * (double)x[i];
+  }
+  sh[threadIdx.x] = contrib;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// Ap = H p with part[wg] = the workgroup's share of p.Ap; returns the number of partials.
+constexpr int kMaxParts = 2048;
+
+// y = H x (FP64), the coalesced kernel where the block size allows it
+template <int D2>
+void launch_spmv(const hdg_mesh* mesh, const double* H, const double* x, double* y, hipStream_t s) {
+  const int nfc = (int)mesh->nfc;
+  if constexpr (D2 % 2 == 0 && D2 >= 6) {
+    const int groups = (nfc + SpmvC<D2>::FACES - 1) / SpmvC<D2>::FACES;
+    k_spmv_c<D2, double, double, false><<<std::max(1, std::min(groups, kMaxParts)), 256, 0, s>>>(
+        mesh->d_row_ptr, mesh->d_col_idx, H, x, y, nfc, nullptr);
+  } else {
+    k_spmv<D2, double, double><<<(unsigned)((nfc * D2 + 255) / 256), 256, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx,
+                                                                                   H, x, y, nfc);
+  }
+}
+
+template <int D2, class TM, class TV>
+int launch_spmv_pap(const hdg_mesh* mesh, const TM* H, const TV* x, TV* y, double* part, hipStream_t s) {
+  const int nfc = (int)mesh->nfc;
+  if constexpr (D2 % 2 == 0 && D2 >= 6 && sizeof(TM) == 8) {  // 16-byte pairs (FP64 H)
+    const int groups = (nfc + SpmvC<D2>::FACES - 1) / SpmvC<D2>::FACES;
+    const int g = std::max(1, std::min(groups, kMaxParts));
+    k_spmv_c<D2, TM, TV, true><<<g, 256, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, y, nfc, part);
+    return g;
+  } else {
+    const int g = std::max(1, std::min((nfc * D2 + 255) / 256, kMaxParts));
+    k_spmv_pap<D2, TM, TV><<<g, 256, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, y, nfc, part);
+    return g;
+  }
+}
+
+// out = sum of part[0..count) in a fixed order (one workgroup of kSumThreads threads, four
+// independent accumulators per thread so that its loads overlap)
+constexpr int kSumThreads = 1024;
+
+__global__ void __launch_bounds__(kSumThreads) k_sum_parts(const double* __restrict__ part, int count,
+                                                           double* __restrict__ out) {
+  __shared__ double sh[kSumThreads];
+  double a[4] = {0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 3 * kSumThreads < count; i += 4 * kSumThreads) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] += part[i + q * kSumThreads];
+  }
+  for (int q = 0; i < count; i += kSumThreads, ++q) a[q] += part[i];
+  sh[threadIdx.x] = (a[0] + a[1]) + (a[2] + a[3]);
+  __syncthreads();
+  for (int o = kSumThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// x += alpha p, r -= alpha Ap (alpha = scal[old] / scal[1]), z = Minv r with a face's
+// components exchanged in LDS, part[wg] = sum of r.z over the workgroup's faces
+template <int D2, class TM, class TV>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_xr_precond_rz(TV* __restrict__ x, TV* __restrict__ r,
+                                                                     const TV* __restrict__ p,
+                                                                     const TV* __restrict__ Ap,
+                                                                     const TM* __restrict__ Minv, TV* __restrict__ z,
+                                                                     const double* __restrict__ scal, int old, int nfc,
+                                                                     double* __restrict__ part) {
+  __shared__ double rs[Lpre<D2>::THREADS];
+  __shared__ double sh[256];
+  const int lf = threadIdx.x / D2, c = threadIdx.x % D2;
+  const double alpha = scal[old] / scal[1];
+  const int ngroups = (nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES;
+  double contrib = 0.0;
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {  // uniform over the workgroup
+    const int f = g * Lpre<D2>::FACES + lf;
+    const size_t i = (size_t)f * D2 + c;
+    double rn = 0.0;
+    if (f < nfc) {
+      x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
+      const TV rv = (TV)((double)r[i] - alpha * (double)Ap[i]);
+      r[i] = rv;
+      rn = (double)rv;
+    }
+    __syncthreads();
+    rs[threadIdx.x] = rn;
+    __syncthreads();
+    if (f < nfc) {
+      const TM* m = Minv + ((size_t)f * D2 + c) * D2;
+      double acc = 0;
+#pragma unroll
+      for (int j = 0; j < D2; ++j) acc += (double)m[j] * rs[lf * D2 + j];
+      const TV zv = (TV)acc;
+      z[i] = zv;
+      contrib += rn * (double)zv;
+    }
+  }
+  sh[threadIdx.x] = contrib;
+  if (threadIdx.x < 256 - Lpre<D2>::THREADS) sh[Lpre<D2>::THREADS + threadIdx.x] = 0.0;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// x += alpha p, r -= alpha Ap with alpha = scal[old] / scal[1] (the learned form, whose
+// preconditioner needs neighbouring faces and so runs as its own kernels)
 template <class TV>
-__global__ void k_update_xr(TV* __restrict__ x, TV* __restrict__ r, const TV* __restrict__ p,
-                            const TV* __restrict__ Ap, const double* __restrict__ scal, size_t n) {
-  const double alpha = scal[0] / scal[1];
+__global__ void k_update_xr_slot(TV* __restrict__ x, TV* __restrict__ r, const TV* __restrict__ p,
+                                 const TV* __restrict__ Ap, const double* __restrict__ scal, int old, size_t n) {
+  const double alpha = scal[old] / scal[1];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
     r[i] = (TV)((double)r[i] - alpha * (double)Ap[i]);
   }
 }
 
-// p = z + beta p with beta = rz_new / rz; then rz <- rz_new
+// p = z + beta p with beta = scal[nw] / scal[old]
 template <class TV>
-__global__ void k_update_p(TV* __restrict__ p, const TV* __restrict__ z, const double* __restrict__ scal, size_t n) {
-  const double beta = scal[2] / scal[0];
+__global__ void k_update_p_slot(TV* __restrict__ p, const TV* __restrict__ z, const double* __restrict__ scal, int old,
+                                int nw, size_t n) {
+  const double beta = scal[nw] / scal[old];
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = (TV)((double)z[i] + beta * (double)p[i]);
-}
-
-__global__ void k_shift_rz(double* scal) {
-  if (threadIdx.x == 0) scal[0] = scal[2];
 }
 
 template <class TV>
@@ -322,13 +534,17 @@ struct Carve {
   }
 };
 
+// Partial sums: one per workgroup of the fused PCG kernels (at most kMaxParts), and the
+// kRedBlocks of the plain dot products.
+size_t part_count(size_t) { return std::max<size_t>(kRedBlocks, kMaxParts); }
+
 size_t ws_size(const hdg_mesh* mesh, int d2, int precision) {
   const size_t n = (size_t)mesh->nfc * d2;
   size_t b = 0;
   auto add = [&](size_t bytes) { b += (bytes + 255) & ~size_t(255); };
   for (int i = 0; i < 5; ++i) add(n * sizeof(double));  // r z p Ap, and the learned factor's sweep
   add((size_t)mesh->nfc * d2 * d2 * sizeof(double));    // Minv
-  add(kRedBlocks * sizeof(double));
+  add(part_count(n) * sizeof(double));
   add(8 * sizeof(double));
   if (precision == 1) {
     for (int i = 0; i < 6; ++i) add(n * sizeof(float));  // d r z p Ap sweep (inner)
@@ -371,7 +587,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   double* Ap = cv.take<double>(n);
   double* sw = cv.take<double>(n);
   double* Minv = cv.take<double>((size_t)mesh->nfc * D2 * D2);
-  double* part = cv.take<double>(kRedBlocks);
+  double* part = cv.take<double>(part_count(n));
   double* scal = cv.take<double>(8);
   float *d32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *Ap32 = nullptr, *H32 = nullptr,
         *Minv32 = nullptr, *sw32 = nullptr;
@@ -432,6 +648,9 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   }
   const double tol2 = o->rtol * o->rtol * bb;
   const int every = std::max(1, o->check_every);
+  const unsigned gfp = std::max(1u, std::min(gf, (unsigned)kMaxParts));  // k_xr_precond_rz grid
+  // rz of the previous iteration is in slot old(it), the new one goes to the other slot
+  auto old_slot = [](int it) { return (it & 1) ? 2 : 0; };
   if (o->precision == 0) {
     k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
     pre64(r, z);
@@ -461,16 +680,21 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
           // residual replacement and restart
           pre64(r, z);
           k_copy<double><<<gv, T, 0, s>>>(z, p, n);
-          S.dot(r, z, scal + 0);
+          S.dot(r, z, scal + old_slot(it));
         }
       }
-      k_spmv<D2, double, double><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, p, Ap, nfc);
-      S.dot(p, Ap, scal + 1);
-      k_update_xr<double><<<gv, T, 0, s>>>(x, r, p, Ap, scal, n);
-      pre64(r, z);
-      S.dot(r, z, scal + 2);
-      k_update_p<double><<<gv, T, 0, s>>>(p, z, scal, n);
-      k_shift_rz<<<1, 1, 0, s>>>(scal);
+      const int od = old_slot(it), nw = 2 - od;
+      const int np1 = launch_spmv_pap<D2>(mesh, H, p, Ap, part, s);
+      k_sum_parts<<<1, kSumThreads, 0, s>>>(part, np1, scal + 1);
+      if (learned) {
+        k_update_xr_slot<double><<<gv, T, 0, s>>>(x, r, p, Ap, scal, od, n);
+        pre64(r, z);
+        S.dot(r, z, scal + nw);
+      } else {
+        k_xr_precond_rz<D2, double, double><<<gfp, TL, 0, s>>>(x, r, p, Ap, Minv, z, scal, od, nfc, part);
+        k_sum_parts<<<1, kSumThreads, 0, s>>>(part, (int)gfp, scal + nw);
+      }
+      k_update_p_slot<double><<<gv, T, 0, s>>>(p, z, scal, od, nw, n);
       ++it;
     }
   }
@@ -507,13 +731,18 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
         double r2 = S.read(scal + 3);
         if (!(r2 > in_tol2) || total >= o->max_iter) break;
       }
-      k_spmv<D2, float, float><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H32, p32, Ap32, nfc);
-      S.dot(p32, Ap32, scal + 1);
-      k_update_xr<float><<<gv, T, 0, s>>>(d32, r32, p32, Ap32, scal, n);
-      pre32(r32, z32);
-      S.dot(r32, z32, scal + 2);
-      k_update_p<float><<<gv, T, 0, s>>>(p32, z32, scal, n);
-      k_shift_rz<<<1, 1, 0, s>>>(scal);
+      const int od = old_slot(it), nw = 2 - od;
+      const int np1 = launch_spmv_pap<D2>(mesh, H32, p32, Ap32, part, s);
+      k_sum_parts<<<1, kSumThreads, 0, s>>>(part, np1, scal + 1);
+      if (learned) {
+        k_update_xr_slot<float><<<gv, T, 0, s>>>(d32, r32, p32, Ap32, scal, od, n);
+        pre32(r32, z32);
+        S.dot(r32, z32, scal + nw);
+      } else {
+        k_xr_precond_rz<D2, float, float><<<gfp, TL, 0, s>>>(d32, r32, p32, Ap32, Minv32, z32, scal, od, nfc, part);
+        k_sum_parts<<<1, kSumThreads, 0, s>>>(part, (int)gfp, scal + nw);
+      }
+      k_update_p_slot<float><<<gv, T, 0, s>>>(p32, z32, scal, od, nw, n);
       ++total;
     }
     k_axpy_scaled<float, double><<<gv, T, 0, s>>>(d32, x, n, scal + 5);
@@ -624,9 +853,9 @@ extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh
 // ---------------------------------------------------------------------------------------
 // GMRES for non-symmetric trace systems (the convection-diffusion HDG): restarted GMRES(m)
 // with right block-Jacobi preconditioning (explicit inverses of the d2 x d2 diagonal blocks
-// by Gauss-Jordan with partial pivoting), classical Gram-Schmidt applied twice, fixed-order
-// reductions.  The small Hessenberg least-squares problem (Givens rotations) is solved on the
-// host; the host reads one column of it per iteration.
+// by Gauss-Jordan with partial pivoting), classical Gram-Schmidt with a second pass under
+// severe cancellation, fixed-order reductions.  The small Hessenberg least-squares problem
+// (Givens rotations) is solved on the host; the host reads one column of it per iteration.
 namespace hdg {
 namespace {
 
@@ -665,22 +894,39 @@ __global__ void k_bj_setup_lu(const double* __restrict__ H, const int* __restric
     for (int j = 0; j < D2; ++j) o[i * D2 + j] = A[i][D2 + j];
 }
 
-// part[b * nv + i] = partial (w, V_i) of block b, i < nv
-__global__ void k_mdot_partial(const double* __restrict__ V, size_t ldv, int nv, const double* __restrict__ w,
-                               size_t n, double* __restrict__ part) {
-  __shared__ double sh[kRedThreads];
-  for (int i = 0; i < nv; ++i) {
-    const double* vi = V + (size_t)i * ldv;
-    double s = 0;
-    for (size_t t = blockIdx.x * (size_t)kRedThreads + threadIdx.x; t < n; t += (size_t)kRedBlocks * kRedThreads)
-      s += w[t] * vi[t];
-    sh[threadIdx.x] = s;
+// part[b * nt + i] = partial (w, V_i) of block b for i < nv, and with self = 1 also
+// part[b * nt + nv] = partial (w, w); nt = nv + self.  The products are taken eight at a
+// time: one pass over the rows accumulates all eight in registers, and one tree reduction in
+// LDS finishes the eight together.
+constexpr int kMdotChunk = 8;
+constexpr int kMdotBlocks = 2048;  // enough waves in flight to stream the basis from HBM
+
+__global__ void __launch_bounds__(kRedThreads) k_mdot_partial(const double* __restrict__ V, size_t ldv, int nv,
+                                                              int self, const double* __restrict__ w, size_t n,
+                                                              double* __restrict__ part) {
+  __shared__ double sh[kMdotChunk][kRedThreads];
+  const int nt = nv + self;
+  for (int i0 = 0; i0 < nt; i0 += kMdotChunk) {
+    const int cnt = min(kMdotChunk, nt - i0);
+    double acc[kMdotChunk];
+#pragma unroll
+    for (int q = 0; q < kMdotChunk; ++q) acc[q] = 0;
+    for (size_t t = blockIdx.x * (size_t)kRedThreads + threadIdx.x; t < n; t += (size_t)kMdotBlocks * kRedThreads) {
+      const double wt = w[t];
+#pragma unroll
+      for (int q = 0; q < kMdotChunk; ++q)
+        if (q < cnt) acc[q] += wt * (i0 + q < nv ? V[(size_t)(i0 + q) * ldv + t] : wt);
+    }
+#pragma unroll
+    for (int q = 0; q < kMdotChunk; ++q) sh[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int o = kRedThreads / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      if ((int)threadIdx.x < o)
+#pragma unroll
+        for (int q = 0; q < kMdotChunk; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + o];
       __syncthreads();
     }
-    if (threadIdx.x == 0) part[(size_t)blockIdx.x * nv + i] = sh[0];
+    if ((int)threadIdx.x < cnt) part[(size_t)blockIdx.x * nt + i0 + threadIdx.x] = sh[threadIdx.x][0];
     __syncthreads();
   }
 }
@@ -690,7 +936,7 @@ __global__ void k_mdot_final(const double* __restrict__ part, int nv, double* __
   __shared__ double sh[kRedThreads];
   const int i = blockIdx.x;
   double s = 0;
-  for (int b = threadIdx.x; b < kRedBlocks; b += kRedThreads) s += part[(size_t)b * nv + i];
+  for (int b = threadIdx.x; b < kMdotBlocks; b += kRedThreads) s += part[(size_t)b * nv + i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = kRedThreads / 2; o > 0; o >>= 1) {
@@ -740,7 +986,7 @@ constexpr int kMaxRestart = 64;
 // partial sums of the batched dots, and a small device array (both Gram-Schmidt passes'
 // coefficients, the norm, y).
 size_t gmres_ws_doubles(size_t n, int nfc, int d2, int m) {
-  return (size_t)(m + 4) * n + (size_t)nfc * d2 * d2 + (size_t)kRedBlocks * (m + 1) + 3 * (size_t)(m + 1) + 64;
+  return (size_t)(m + 4) * n + (size_t)nfc * d2 * d2 + (size_t)kMdotBlocks * (m + 2) + 3 * (size_t)(m + 2) + 64;
 }
 
 template <int D2>
@@ -756,10 +1002,12 @@ hdg_status run_gmres(const hdg_mesh* mesh, const double* H, const double* b, dou
   double* part = Minv + (size_t)nfc * D2 * D2;
   // small: [0, m + 1) first-pass coefficients, [m + 1, 2m + 2) second-pass ones, [2m + 2] the
   // squared norm; y reuses [0, m)
-  double* small = part + (size_t)kRedBlocks * (m + 1);
+  double* small = part + (size_t)kMdotBlocks * (m + 2);
+  // small: [0, m + 2) first-pass coefficients and, after them, ||w||^2 before the pass;
+  // [m + 2, 2m + 4) second-pass coefficients; [2m + 4] ||w||^2 after; y reuses [0, m)
   double* h1 = small;
-  double* h2 = small + (m + 1);
-  double* nrm = small + 2 * (m + 1);
+  double* h2 = small + (m + 2);
+  double* nrm = small + 2 * (m + 2);
   const unsigned T = 256;
   const unsigned gr = (unsigned)((n + T - 1) / T);
   const unsigned gv = (unsigned)std::max<size_t>(1, std::min<size_t>((n + T - 1) / T, 8192));
@@ -772,13 +1020,13 @@ hdg_status run_gmres(const hdg_mesh* mesh, const double* H, const double* b, dou
     hipError_t e = hipMemcpyAsync(h, d, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
     return e == hipSuccess ? hipStreamSynchronize(s) : e;
   };
-  std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(2 * (m + 1) + 1);
+  std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(2 * (m + 2) + 1);
   hipError_t e;
   double bn2 = 0;
   norm2(b);
   if ((e = read(nrm, &bn2, 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
   const double bnorm = bn2 > 0 ? std::sqrt(bn2) : 1.0;
-  int iters = 0, cycles = 0;
+  int iters = 0, cycles = 0, reorth = 0;
   double rel = 0;
   for (;;) {
     // true residual at the start of every cycle (and once more at the end)
@@ -797,17 +1045,29 @@ hdg_status run_gmres(const hdg_mesh* mesh, const double* H, const double* b, dou
     while (j < m && iters < max_iter && !done) {
       const double* vj = V + (size_t)j * n;
       k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, vj, z, nfc);
-      k_spmv<D2, double, double><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, z, w, nfc);
-      // classical Gram-Schmidt against V_0..V_j, applied twice
-      for (double* h : {h1, h2}) {
-        k_mdot_partial<<<kRedBlocks, kRedThreads, 0, s>>>(V, n, j + 1, w, n, part);
-        k_mdot_final<<<j + 1, kRedThreads, 0, s>>>(part, j + 1, h, 0);
-        k_sub_combination<<<gv, T, 0, s>>>(w, V, n, j + 1, h, n);
-      }
+      launch_spmv<D2>(mesh, H, z, w, s);
+      // classical Gram-Schmidt against V_0..V_j; a second pass only under severe
+      // cancellation, when the first pass left less than 1e-3 of ||w|| (the usual 1/sqrt(2)
+      // criterion fires on nearly every Arnoldi step here and doubles the cost, while the
+      // iteration counts and the true-residual-checked results are the same without it)
+      k_mdot_partial<<<kMdotBlocks, kRedThreads, 0, s>>>(V, n, j + 1, 1, w, n, part);
+      k_mdot_final<<<j + 2, kRedThreads, 0, s>>>(part, j + 2, h1, 0);
+      k_sub_combination<<<gv, T, 0, s>>>(w, V, n, j + 1, h1, n);
       norm2(w);
-      if ((e = read(small, col.data(), 2 * (m + 1) + 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
-      const double hnext = std::sqrt(col[2 * (m + 1)]);
-      for (int i = 0; i <= j; ++i) Hh[(size_t)i * m + j] = col[i] + col[m + 1 + i];
+      if ((e = read(small, col.data(), 2 * (m + 2) + 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
+      for (int i = 0; i <= j; ++i) Hh[(size_t)i * m + j] = col[i];
+      double wa2 = col[2 * (m + 2)];
+      if (wa2 < 1e-6 * col[j + 1]) {
+        k_mdot_partial<<<kMdotBlocks, kRedThreads, 0, s>>>(V, n, j + 1, 0, w, n, part);
+        k_mdot_final<<<j + 1, kRedThreads, 0, s>>>(part, j + 1, h2, 0);
+        k_sub_combination<<<gv, T, 0, s>>>(w, V, n, j + 1, h2, n);
+        norm2(w);
+        if ((e = read(small, col.data(), 2 * (m + 2) + 1)) != hipSuccess) return check_hip(e, "hdg_solve_gmres");
+        for (int i = 0; i <= j; ++i) Hh[(size_t)i * m + j] += col[m + 2 + i];
+        wa2 = col[2 * (m + 2)];
+        ++reorth;
+      }
+      const double hnext = std::sqrt(wa2);
       Hh[(size_t)(j + 1) * m + j] = hnext;
       if (hnext > 0) k_scale_into<<<gv, T, 0, s>>>(V + (size_t)(j + 1) * n, w, nullptr, hnext, n);
       // the earlier Givens rotations, then one that zeroes H(j + 1, j)
@@ -847,7 +1107,7 @@ hdg_status run_gmres(const hdg_mesh* mesh, const double* H, const double* b, dou
   info->iterations = iters;
   info->outer = cycles;
   info->rel_residual = rel;
-  info->fell_back = 0;
+  info->fell_back = reorth;  // GMRES: the number of second Gram-Schmidt passes
   if (!(rel <= rtol)) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve_gmres: tolerance not reached");
   return HDG_OK;
 }
