@@ -26,7 +26,9 @@
 // their single writer, diagonal blocks and F by atomic adds onto zeros (two addends: the same
 // bits in either order).
 //
-// One element per workgroup of four wavefronts, everything in LDS.
+// One element per workgroup of four wavefronts, everything in LDS (78 KB at k = 3: two
+// workgroups per CU); the factorisations and triangular solves update all rows of all
+// right-hand sides in parallel at each elimination step.
 #include "device_common.h"
 
 namespace hdg {
@@ -53,20 +55,70 @@ struct CdSmem {
   double f[D3];
   double bnDP[4][D2 * D3];
   double bnDD[4][D2 * D2];
-  double X[N4 * NR];                 // [q_x; q_y; q_z; u] for every right-hand side
+  double T[NQD * D3];                // T[q][i] = sum_h gam_h(q) dhat_h P_i(q)
+  double X[N4 * NR];                 // [q_x; q_y; q_z; u] for every right-hand side; while the
+                                     // element blocks are formed, the basis table P[q][i]
 };
-static_assert(sizeof(CdSmem<3>) + sizeof(ElemGeom) <= 64 * 1024, "convection-diffusion LDS budget");
+static_assert(CdDims<3>::NQD * CdDims<3>::D3 <= CdDims<3>::N4 * CdDims<3>::NR, "P staged in X");
+// two workgroups per CU (160 KB of LDS)
+static_assert(sizeof(CdSmem<3>) + sizeof(ElemGeom) <= 80 * 1024, "convection-diffusion LDS budget");
 
 // In-place LU factorisation without pivoting (unit lower factor below the diagonal), all
-// threads of the block; ends with a barrier.
+// threads of the block, one (row, column) entry of the trailing block per thread and
+// step; ends with a barrier.
 template <int N>
 __device__ void lds_lu_nopiv(double* A) {
   for (int p = 0; p < N; ++p) {
     const double inv = 1.0 / A[p * N + p];
-    for (int i = p + 1 + threadIdx.x; i < N; i += blockDim.x) {
-      const double l = A[i * N + p] * inv;
-      A[i * N + p] = l;
-      for (int j = p + 1; j < N; ++j) A[i * N + j] -= l * A[p * N + j];
+    const int m = N - 1 - p;
+    for (int e = threadIdx.x; e < m * (m + 1); e += blockDim.x) {  // column p + e % (m + 1)
+      const int i = p + 1 + e / (m + 1), jj = e % (m + 1);
+      if (jj == 0) continue;
+      const int j = p + jj;
+      A[i * N + j] -= (A[i * N + p] * inv) * A[p * N + j];
+    }
+    __syncthreads();
+    for (int i = p + 1 + threadIdx.x; i < N; i += blockDim.x) A[i * N + p] *= inv;
+    __syncthreads();
+  }
+}
+
+// Triangular solves on NM sets of NC right-hand sides: set m holds its row r at
+// X + m * mstride + r * ldx.  Column-oriented, so that each step updates all remaining rows
+// of every right-hand side in parallel, with the operation order of row substitution
+// (subtractions in increasing k, then the division).  L is row-major with leading
+// dimension N; each ends with a barrier.
+//   lds_forward_par<UNIT>:    X <- L^{-1} X  (UNIT: L has a unit diagonal, not stored)
+//   lds_backward_par<TRANS>:  X <- L^{-T} X  (TRANS, L lower) or U^{-1} X (U upper)
+template <int N, bool UNIT>
+__device__ void lds_forward_par(const double* L, double* X, int ldx, int nc, int nm, int mstride) {
+  for (int k = 0; k < N; ++k) {
+    if (!UNIT) {
+      for (int e = threadIdx.x; e < nm * nc; e += blockDim.x)
+        X[(e / nc) * mstride + k * ldx + e % nc] /= L[k * N + k];
+      __syncthreads();
+    }
+    const int rows = N - 1 - k, per = rows * nc;
+    for (int e = threadIdx.x; e < nm * per; e += blockDim.x) {
+      const int m = e / per, rc = e % per, r = k + 1 + rc / nc, c = rc % nc;
+      double* x = X + m * mstride;
+      x[r * ldx + c] -= L[r * N + k] * x[k * ldx + c];
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, bool TRANS>
+__device__ void lds_backward_par(const double* L, double* X, int ldx, int nc, int nm, int mstride) {
+  for (int k = N - 1; k >= 0; --k) {
+    for (int e = threadIdx.x; e < nm * nc; e += blockDim.x)
+      X[(e / nc) * mstride + k * ldx + e % nc] /= L[k * N + k];
+    __syncthreads();
+    const int per = k * nc;
+    for (int e = threadIdx.x; e < nm * per; e += blockDim.x) {
+      const int m = e / per, rc = e % per, r = rc / nc, c = rc % nc;
+      double* x = X + m * mstride;
+      x[r * ldx + c] -= (TRANS ? L[k * N + r] : L[r * N + k]) * x[k * ldx + c];
     }
     __syncthreads();
   }
@@ -110,17 +162,23 @@ __global__ void __launch_bounds__(kCdThreads) k_condense_cd(hdg_mesh mesh, Table
       sm.al[l][r] = tb.tri_w[r] * (b[0] * g.n[l][0] + b[1] * g.n[l][1] + b[2] * g.n[l][2]);
     }
     __syncthreads();
-    // ---- element blocks
+    // ---- element blocks: the basis table goes to LDS (in X, free until the right-hand
+    // sides) and the beta-weighted reference gradients to T
+    for (int idx = t; idx < NQD * D3; idx += nt) {
+      const int q = idx / D3, i = idx % D3;
+      sm.X[idx] = tb.P[idx];
+      sm.T[idx] = sm.gam[0][q] * tb.Pg[q * D3 + i] + sm.gam[1][q] * tb.Pg[(NQD + q) * D3 + i] +
+                  sm.gam[2][q] * tb.Pg[(2 * NQD + q) * D3 + i];
+    }
+    __syncthreads();
     for (int idx = t; idx < D3 * D3; idx += nt) {
       const int i = idx / D3, j = idx % D3;
       double sk = 0, sc = 0, se = 0;
       for (int q = 0; q < NQD; ++q) {
-        const double pi = tb.P[q * D3 + i], pj = tb.P[q * D3 + j];
+        const double pi = sm.X[q * D3 + i], pj = sm.X[q * D3 + j];
         sk += sm.wk[q] * pi * pj;
         sc += sm.wc[q] * pi * pj;
-        // (sum_s E_s^T)[i][j] = sum_q P_j sum_h gam_h grad_h P_i
-        se += pj * (sm.gam[0][q] * tb.Pg[q * D3 + i] + sm.gam[1][q] * tb.Pg[(NQD + q) * D3 + i] +
-                    sm.gam[2][q] * tb.Pg[(2 * NQD + q) * D3 + i]);
+        se += pj * sm.T[q * D3 + i];  // (sum_s E_s^T)[i][j] = sum_q P_j sum_h gam_h grad_h P_i
       }
       for (int l = 0; l < 4; ++l) sc += g.T[l] * tb.PP[(l * D3 + i) * D3 + j];
       sm.Mm[idx] = sk;
@@ -133,7 +191,7 @@ __global__ void __launch_bounds__(kCdThreads) k_condense_cd(hdg_mesh mesh, Table
     }
     for (int i = t; i < D3; i += nt) {
       double s = 0;
-      for (int q = 0; q < NQD; ++q) s += sm.wf[q] * tb.P[q * D3 + i];
+      for (int q = 0; q < NQD; ++q) s += sm.wf[q] * sm.X[q * D3 + i];
       sm.f[i] = s;
     }
     for (int idx = t; idx < 4 * D2 * D3; idx += nt) {
@@ -154,16 +212,7 @@ __global__ void __launch_bounds__(kCdThreads) k_condense_cd(hdg_mesh mesh, Table
     __syncthreads();
     // ---- M = L L^T;  G_s = L^{-1} C_s^T;  S += sum_s G_s^T G_s;  S = LU
     lds_cholesky<D3>(sm.Mm, D3);
-    for (int cs = t; cs < 3 * D3; cs += nt) {
-      double* Gs = sm.G[cs / D3];
-      const int c = cs % D3;
-      for (int r = 0; r < D3; ++r) {
-        double v = Gs[r * D3 + c];
-        for (int k = 0; k < r; ++k) v -= sm.Mm[r * D3 + k] * Gs[k * D3 + c];
-        Gs[r * D3 + c] = v / sm.Mm[r * D3 + r];
-      }
-    }
-    __syncthreads();
+    lds_forward_par<D3, false>(sm.Mm, &sm.G[0][0], D3, D3, 3, D3 * D3);
     for (int idx = t; idx < D3 * D3; idx += nt) {
       const int i = idx / D3, j = idx % D3;
       double v = sm.S[idx];
@@ -187,16 +236,7 @@ __global__ void __launch_bounds__(kCdThreads) k_condense_cd(hdg_mesh mesh, Table
     __syncthreads();
     lds_lu_nopiv<D3>(sm.S);
     // Z_s = L^{-1} b_s (in the q rows of X)
-    for (int sc = t; sc < 3 * NR; sc += nt) {
-      const int s = sc / NR, c = sc % NR;
-      double* x = sm.X + s * D3 * NR + c;
-      for (int r = 0; r < D3; ++r) {
-        double v = x[r * NR];
-        for (int k = 0; k < r; ++k) v -= sm.Mm[r * D3 + k] * x[k * NR];
-        x[r * NR] = v / sm.Mm[r * D3 + r];
-      }
-    }
-    __syncthreads();
+    lds_forward_par<D3, false>(sm.Mm, sm.X, NR, NR, 3, D3 * NR);
     // b_u -= sum_s G_s^T Z_s
     for (int idx = t; idx < D3 * NR; idx += nt) {
       const int j = idx / NR, c = idx % NR;
@@ -207,20 +247,8 @@ __global__ void __launch_bounds__(kCdThreads) k_condense_cd(hdg_mesh mesh, Table
     }
     __syncthreads();
     // u = U^{-1} L_S^{-1} (b_u - ...)
-    for (int c = t; c < NR; c += nt) {
-      double* x = sm.X + 3 * D3 * NR + c;
-      for (int r = 0; r < D3; ++r) {
-        double v = x[r * NR];
-        for (int k = 0; k < r; ++k) v -= sm.S[r * D3 + k] * x[k * NR];
-        x[r * NR] = v;
-      }
-      for (int r = D3 - 1; r >= 0; --r) {
-        double v = x[r * NR];
-        for (int k = r + 1; k < D3; ++k) v -= sm.S[r * D3 + k] * x[k * NR];
-        x[r * NR] = v / sm.S[r * D3 + r];
-      }
-    }
-    __syncthreads();
+    lds_forward_par<D3, true>(sm.S, sm.X + 3 * D3 * NR, NR, NR, 1, 0);
+    lds_backward_par<D3, false>(sm.S, sm.X + 3 * D3 * NR, NR, NR, 1, 0);
     // q_s = L^{-T} (Z_s + G_s u)
     for (int idx = t; idx < 3 * D3 * NR; idx += nt) {
       const int s = idx / (D3 * NR), j = (idx / NR) % D3, c = idx % NR;
@@ -229,16 +257,7 @@ __global__ void __launch_bounds__(kCdThreads) k_condense_cd(hdg_mesh mesh, Table
       sm.X[idx] = v;
     }
     __syncthreads();
-    for (int sc = t; sc < 3 * NR; sc += nt) {
-      const int s = sc / NR, c = sc % NR;
-      double* x = sm.X + s * D3 * NR + c;
-      for (int r = D3 - 1; r >= 0; --r) {
-        double v = x[r * NR];
-        for (int k = r + 1; k < D3; ++k) v -= sm.Mm[k * D3 + r] * x[k * NR];
-        x[r * NR] = v / sm.Mm[r * D3 + r];
-      }
-    }
-    __syncthreads();
+    lds_backward_par<D3, true>(sm.Mm, sm.X, NR, NR, 3, D3 * NR);
     // ---- C^K = A3 X_2 + tauDD - beta.n DD,  Cf^K = A3 X_f;  scatter or export
     for (int idx = t; idx < M * NR; idx += nt) {
       const int a = idx / NR, b = idx % NR;
