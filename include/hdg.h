@@ -262,9 +262,9 @@ typedef struct {
   int precision;      /* 0: FP64 throughout; 1: FP32 matrix and preconditioner inside
                          an FP64 iterative-refinement loop */
   int precond;        /* 0: block-Jacobi; 1: learned factor (needs the three arrays below) */
-  const float* d_pre_N;      /* [nnzb][d2][d2] N of the learned factor (hdg_gnn_forward) */
+  const float* d_pre_N;      /* [nnzb][d2][d2] N of the learned factor, lower blocks and their
+                                transposes at the mirrored positions (hdg_gnn_forward) */
   const float* d_pre_Linv;   /* [nfc][d2][d2]  hdg_gnn_graph.Linv */
-  const int32_t* d_pre_mirror; /* [nnzb]      hdg_gnn_graph.mirror */
   const float* d_pre_B;      /* [nfc][d2 (d2 + 1) / 2] block scaling of the learned factor
                                 (hdg_gnn_forward), or NULL for B = I */
 } hdg_solve_opts;
@@ -546,7 +546,9 @@ hdg_status hdg_gnn_build_graph(const hdg_disc* disc, const hdg_mesh* mesh, const
                                void* d_ws, size_t ws_bytes, void* stream);
 /* Activations and temporaries of forward / backward for nprobe probe vectors. */
 hdg_status hdg_gnn_workspace_size(const hdg_gnn_shape* shape, const hdg_mesh* mesh, int nprobe, size_t* bytes);
-/* d_N [nnzb][d2][d2]: N on the lower blocks without Dirichlet faces, zero elsewhere;
+/* d_N [nnzb][d2][d2]: N_ij on the lower blocks (j < i) without Dirichlet faces, zero on the
+ * other lower blocks and on the diagonal, and N_ij^T at each mirrored upper position (j, i)
+ * (so that the transposed sweep of the preconditioner reads block rows);
  * d_B [nfc][d2 (d2 + 1) / 2]: beta of every face (zero on Dirichlet faces). */
 hdg_status hdg_gnn_forward(const hdg_gnn_shape* shape, const float* d_params, const hdg_mesh* mesh,
                            const hdg_gnn_graph* graph, float* d_N, float* d_B, void* d_ws, size_t ws_bytes,
@@ -560,12 +562,11 @@ hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float* d_params, 
 /* z = M^{-1} r = L^{-T} G^T G L^{-1} r with G = B (I + N): the learned preconditioner as
  * hdg_solve applies it (precond = 1), FP64 vectors with FP32 factors and FP64 accumulation.
  *   d_N [nnzb][d2][d2] and d_B [nfc][d2 (d2 + 1) / 2] (hdg_gnn_forward; d_B may be NULL for
- *   B = I), d_Linv [nfc][d2][d2] and d_mirror [nnzb] (the graph), d_r and d_z double
- *   [nfc][d2] (distinct arrays).
+ *   B = I), d_Linv [nfc][d2][d2] (the graph), d_r and d_z double [nfc][d2] (distinct arrays).
  * Workspace: nfc d2 doubles.  Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE. */
 hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N, const float* d_B,
-                                 const float* d_Linv, const int32_t* d_mirror, const double* d_r, double* d_z,
-                                 void* d_ws, size_t ws_bytes, void* stream);
+                                 const float* d_Linv, const double* d_r, double* d_z, void* d_ws, size_t ws_bytes,
+                                 void* stream);
 /* One Adam step (step = 1, 2, ...) on n parameters. */
 hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr,
                         float beta1, float beta2, float eps, void* stream);

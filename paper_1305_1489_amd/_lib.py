@@ -61,7 +61,7 @@ class hdg_disc_info(C.Structure):
 class hdg_solve_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int), ("precision", C.c_int),
                 ("precond", C.c_int), ("d_pre_N", C.c_void_p), ("d_pre_Linv", C.c_void_p),
-                ("d_pre_mirror", C.c_void_p), ("d_pre_B", C.c_void_p)]
+                ("d_pre_B", C.c_void_p)]
 
 
 class hdg_solve_info(C.Structure):
@@ -360,14 +360,14 @@ def hdg_assemble_condense_bdm(disc: Disc, mesh: Mesh, kappa, c, f, H, F, factors
     return H, F, factors
 
 
-def hdg_gnn_precond_apply(disc: Disc, mesh: Mesh, N, B, Linv, mirror, r, z=None, ws=None, stream=None):
+def hdg_gnn_precond_apply(disc: Disc, mesh: Mesh, N, B, Linv, r, z=None, ws=None, stream=None):
     """z = L^{-T} G^T G L^{-1} r (G = B (I + N); B = None: the identity), as the learned PCG applies it."""
     if z is None:
         z = torch.empty_like(r)
     if ws is None:
         ws = torch.empty(mesh.nfc * disc.d2 * 8, dtype=torch.uint8, device=r.device)
-    _check(lib().hdg_gnn_precond_apply(disc.handle, C.byref(mesh.struct), _ptr(N), _ptr(B), _ptr(Linv), _ptr(mirror),
-                                       _ptr(r), _ptr(z), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
+    _check(lib().hdg_gnn_precond_apply(disc.handle, C.byref(mesh.struct), _ptr(N), _ptr(B), _ptr(Linv), _ptr(r),
+                                       _ptr(z), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream)))
     return z
 
 
@@ -410,7 +410,6 @@ def hdg_solve(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=100000, c
         opts.d_pre_N = N.data_ptr()
         opts.d_pre_B = B.data_ptr() if B is not None else None
         opts.d_pre_Linv = graph.Linv.data_ptr()
-        opts.d_pre_mirror = graph.mirror.data_ptr()
     info = hdg_solve_info()
     code = lib().hdg_solve(disc.handle, C.byref(mesh.struct), _ptr(H), _ptr(b), _ptr(uhat), C.byref(opts),
                            C.byref(info), _ptr(ws), C.c_size_t(ws.numel()), _stream(stream))

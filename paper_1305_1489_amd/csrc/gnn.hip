@@ -107,6 +107,75 @@ __global__ void k_dense(int R, Segs in, const float* __restrict__ W, const float
   }
 }
 
+// The same layer on the FP32 matrix cores (v_mfma_f32_16x16x4f32): each wavefront takes 16
+// rows and all NT x 16 outputs; per step of 4 inputs a lane gathers one input value
+// (row = lane % 16, input = lane / 16) and the MFMA multiplies it against the transposed
+// weights in LDS (zero-padded to NT x 16 outputs and a multiple of 4 inputs).  The
+// accumulator of tile nt holds rows 4 (lane / 16) + i and output nt * 16 + lane % 16.
+// Same epilogue as k_dense.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_dense_mfma(int R, Segs in, const float* __restrict__ W,
+                                                    const float* __restrict__ b, int nout, int act,
+                                                    const float* __restrict__ resid, const float* __restrict__ sub,
+                                                    float* __restrict__ pre, float* __restrict__ out, int mode,
+                                                    const int* __restrict__ erow, const int* __restrict__ col,
+                                                    const int* __restrict__ ftype) {
+  constexpr int NP = NT * 16;
+  extern __shared__ float s_wt[];  // [kp][NP] transposed weights, then the bias [NP]
+  const int nin = in.nin, kp = (nin + 3) & ~3;
+  float* s_b = s_wt + kp * NP;
+  for (int t = threadIdx.x; t < kp * NP; t += blockDim.x) {
+    const int k = t / NP, o = t % NP;
+    s_wt[t] = (k < nin && o < nout) ? W[(size_t)o * nin + k] : 0.0f;
+  }
+  for (int t = threadIdx.x; t < NP; t += blockDim.x) s_b[t] = t < nout ? b[t] : 0.0f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int tiles = (R + 15) / 16;
+  for (int tile = blockIdx.x * 4 + wave; tile < tiles; tile += gridDim.x * 4) {
+    const int ra = tile * 16 + r16;  // the row this lane feeds to the A operand
+    v4f acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < kp; kk += 4) {
+      const int k = kk + k4;
+      const float a = (ra < R && k < nin) ? seg_in(in, ra, k) : 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, s_wt[k * NP + nt * 16 + r16], acc[nt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = tile * 16 + 4 * k4 + i;
+      if (r >= R) continue;
+      const bool sel = selected(mode, r, erow, col, ftype);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int o = nt * 16 + r16;
+        if (o >= nout) continue;
+        const size_t idx = (size_t)r * nout + o;
+        float v = 0.0f;
+        if (sel) {
+          const float pa = acc[nt][i] + s_b[o];
+          if (pre) pre[idx] = pa;
+          if (sub) {
+            v = pa - sub[idx];
+          } else {
+            v = act ? fmaxf(pa, 0.0f) : pa;
+            if (resid) v += resid[idx];
+          }
+        } else if (pre) {
+          pre[idx] = 0.0f;
+        }
+        out[idx] = v;
+      }
+    }
+  }
+}
+
 // out[r][k] = (resid ? resid[r][k] : 0) + sum_o W[o][koff + k] d[r][o]   (k < width)
 __global__ void k_dense_t(int R, const float* __restrict__ W, int nin, int nout, int koff, int width,
                           const float* __restrict__ d, const float* __restrict__ resid, float* __restrict__ out) {
@@ -398,6 +467,18 @@ __global__ void k_dot_fin(const double* __restrict__ part, double scale, double*
   if (threadIdx.x == 0) *out = sh[0] * scale;
 }
 
+// The upper position (j, i), i > j, of the factor receives N_ij^T (from its mirror (i, j)),
+// so that the transposed sweep of the preconditioner reads block rows contiguously.
+__global__ void k_mirror_upper(int nnzb, int d2, const int* __restrict__ erow, const int* __restrict__ col,
+                               const int* __restrict__ mirror, float* __restrict__ N) {
+  const int fe = d2 * d2;
+  const size_t total = (size_t)nnzb * fe;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int e = (int)(idx / fe), q = (int)(idx % fe), a = q / d2, b = q % d2;
+    if (col[e] > erow[e]) N[idx] = N[(size_t)mirror[e] * fe + b * d2 + a];
+  }
+}
+
 // part[block] = partial sums of beta_i[a], a < d2 (the log-diagonal of B)
 __global__ void k_logdiag_part(int nfc, int d2, const float* __restrict__ Bp, double* __restrict__ part) {
   __shared__ double sh[kRedT];
@@ -622,6 +703,19 @@ unsigned grid_for(size_t total) { return (unsigned)std::max<size_t>(1, std::min<
 
 hdg_status dense(const Ctx& c, int R, const Segs& in, const float* W, const float* b, int nout, int act,
                  const float* resid, const float* sub, float* pre, float* out, int mode) {
+  if (nout <= 64) {  // the matrix-core form: 16-row tiles, up to four 16-output tiles
+    const int nt = (nout + 15) / 16, kp = (in.nin + 3) & ~3;
+    const size_t lds = ((size_t)kp * nt * 16 + nt * 16) * sizeof(float);
+    const unsigned grid = (unsigned)std::max(1, std::min((R + 63) / 64, 8192));
+    switch (nt) {
+      case 1: k_dense_mfma<1><<<grid, 256, lds, c.s>>>(R, in, W, b, nout, act, resid, sub, pre, out, mode, c.erow(), c.col(), c.ftype()); break;
+      case 2: k_dense_mfma<2><<<grid, 256, lds, c.s>>>(R, in, W, b, nout, act, resid, sub, pre, out, mode, c.erow(), c.col(), c.ftype()); break;
+      case 3: k_dense_mfma<3><<<grid, 256, lds, c.s>>>(R, in, W, b, nout, act, resid, sub, pre, out, mode, c.erow(), c.col(), c.ftype()); break;
+      default: k_dense_mfma<4><<<grid, 256, lds, c.s>>>(R, in, W, b, nout, act, resid, sub, pre, out, mode, c.erow(), c.col(), c.ftype()); break;
+    }
+    HDG_CHECK_LAUNCH("k_dense_mfma");
+    return HDG_OK;
+  }
   const size_t lds = (size_t)in.nin * nout * sizeof(float);
   k_dense<<<grid_for((size_t)R * nout), 256, lds, c.s>>>(R, in, W, b, nout, act, resid, sub, pre, out, mode,
                                                            c.erow(), c.col(), c.ftype());
@@ -704,6 +798,7 @@ hdg_status forward(const Ctx& c, const hdg_gnn_shape& s, const Layout& L, const 
   const int Lx = s.layers;
   GNN_TRY(dense(c, nnzb, segs3(w.X[Lx], c.erow(), h, w.X[Lx], c.col(), h, w.Eh, nullptr, h), th + L.Wo, th + L.co, fe,
                 0, nullptr, c.g->Hs, nullptr, N, SEL_HEAD));
+  k_mirror_upper<<<grid_for((size_t)nnzb * fe), 256, 0, c.s>>>(nnzb, s.d2, c.erow(), c.col(), c.g->mirror, N);
   const int fb = s.d2 * (s.d2 + 1) / 2;
   return dense(c, nfc, segs1(w.X[Lx], nullptr, h), th + L.Wb, th + L.cb, fb, 0, nullptr, nullptr, nullptr, Bp,
                SEL_FREE);

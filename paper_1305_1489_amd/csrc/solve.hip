@@ -143,11 +143,12 @@ __global__ void k_precond(const TM* __restrict__ Minv, const TV* __restrict__ r,
   z[i] = (TV)s;
 }
 
-// Learned factor M^{-1} = L^{-T} G^T G L^{-1}, G = I + N (N strictly block-lower, FP32,
-// stored at the positions of the lower blocks of H; Linv the FP32 inverse Cholesky factors
-// of the diagonal blocks).  Two sweeps, one thread per face, FP64 accumulation:
-//   s_i = t_i + sum_{j < i} N_ij t_j,  t = L^{-1} r            (lower rows)
-//   z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i)              (through the mirror index)
+// Learned factor M^{-1} = L^{-T} G^T G L^{-1}, G = B (I + N) (N strictly block-lower, FP32,
+// stored at the positions of the lower blocks of H with each transpose at the mirrored
+// upper position; B the per-face block scaling; Linv the FP32 inverse Cholesky factors of
+// the diagonal blocks).  Two sweeps, FP64 accumulation:
+//   s_i = B_i^T B_i (t_i + sum_{j < i} N_ij t_j),  t = L^{-1} r   (lower blocks)
+//   z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i)                  (upper blocks)
 // One thread per (face, component), the faces of a workgroup contiguous (Lpre::FACES), so
 // that the threads of a face read whole block rows and the workgroup exchanges a face's
 // components through LDS.
@@ -216,13 +217,13 @@ __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_lower(const int* __r
   if (i < nfc) s[(size_t)i * D2 + a] = (TV)acc;
 }
 
-// z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i): the upper entries of row j, each read
-// through its mirror (block N_ij, column a)
+// z_j = L_j^{-T} (s_j + sum_{i > j} N_ij^T s_i): the upper blocks of row j hold N_ij^T
+// (hdg_gnn_forward writes each lower block's transpose at its mirrored position), so the
+// sweep reads block rows contiguously, as the lower one does
 template <int D2, class TV>
 __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_upper(const int* __restrict__ row_ptr,
                                                                   const int* __restrict__ diag,
                                                                   const int* __restrict__ col,
-                                                                  const int* __restrict__ mirror,
                                                                   const float* __restrict__ N,
                                                                   const float* __restrict__ Linv,
                                                                   const TV* __restrict__ s, TV* __restrict__ z,
@@ -236,10 +237,10 @@ __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_upper(const int* __r
     const int e0 = diag[j] + 1, e1 = row_ptr[j + 1];
 #pragma unroll 3
     for (int e = e0; e < e1; ++e) {
-      const float* Nb = N + (size_t)mirror[e] * D2 * D2 + a;
+      const float* Nr = N + ((size_t)e * D2 + a) * D2;  // row a of N_ij^T
       const TV* si = s + (size_t)col[e] * D2;
 #pragma unroll
-      for (int b = 0; b < D2; ++b) y += (double)Nb[b * D2] * (double)si[b];
+      for (int b = 0; b < D2; ++b) y += (double)Nr[b] * (double)si[b];
     }
   }
   ys[threadIdx.x] = y;
@@ -468,15 +469,39 @@ __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_xr_precond_rz(TV* __restr
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-// x += alpha p, r -= alpha Ap with alpha = scal[old] / scal[1] (the learned form, whose
-// preconditioner needs neighbouring faces and so runs as its own kernels)
-template <class TV>
-__global__ void k_update_xr_slot(TV* __restrict__ x, TV* __restrict__ r, const TV* __restrict__ p,
-                                 const TV* __restrict__ Ap, const double* __restrict__ scal, int old, size_t n) {
+// The learned form's first stage fused with the x and r updates: x += alpha p,
+// r -= alpha Ap, t = L^{-1} r per face (L^{-1} lower triangular, FP32), a face's
+// components exchanged in LDS
+template <int D2, class TV>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_xr_lscale(TV* __restrict__ x, TV* __restrict__ r,
+                                                                 const TV* __restrict__ p, const TV* __restrict__ Ap,
+                                                                 const float* __restrict__ Linv, TV* __restrict__ t,
+                                                                 const double* __restrict__ scal, int old, int nfc) {
+  __shared__ double rs[Lpre<D2>::THREADS];
+  const int lf = threadIdx.x / D2, c = threadIdx.x % D2;
   const double alpha = scal[old] / scal[1];
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
-    r[i] = (TV)((double)r[i] - alpha * (double)Ap[i]);
+  const int ngroups = (nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES;
+  for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {  // uniform over the workgroup
+    const int f = g * Lpre<D2>::FACES + lf;
+    const size_t i = (size_t)f * D2 + c;
+    double rn = 0.0;
+    if (f < nfc) {
+      x[i] = (TV)((double)x[i] + alpha * (double)p[i]);
+      const TV rv = (TV)((double)r[i] - alpha * (double)Ap[i]);
+      r[i] = rv;
+      rn = (double)rv;
+    }
+    __syncthreads();
+    rs[threadIdx.x] = rn;
+    __syncthreads();
+    if (f < nfc) {
+      const float* La = Linv + ((size_t)f * D2 + c) * D2;
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < D2; ++b)
+        if (b <= c) acc += (double)La[b] * rs[lf * D2 + b];
+      t[i] = (TV)acc;
+    }
   }
 }
 
@@ -616,8 +641,8 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
                                                  o->d_pre_B, zz_,
                                                  sw, nfc);
-      k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_mirror,
-                                                 o->d_pre_N, o->d_pre_Linv, sw, zz_, nfc);
+      k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                 o->d_pre_Linv, sw, zz_, nfc);
     } else {
       k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, rr_, zz_, nfc);
     }
@@ -628,8 +653,8 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
                                                 o->d_pre_B, zz_,
                                                 sw32, nfc);
-      k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_mirror,
-                                                o->d_pre_N, o->d_pre_Linv, sw32, zz_, nfc);
+      k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                o->d_pre_Linv, sw32, zz_, nfc);
     } else {
       k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, rr_, zz_, nfc);
     }
@@ -686,9 +711,12 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       const int od = old_slot(it), nw = 2 - od;
       const int np1 = launch_spmv_pap<D2>(mesh, H, p, Ap, part, s);
       k_sum_parts<<<1, kSumThreads, 0, s>>>(part, np1, scal + 1);
-      if (learned) {
-        k_update_xr_slot<double><<<gv, T, 0, s>>>(x, r, p, Ap, scal, od, n);
-        pre64(r, z);
+      if (learned) {  // t -> z, s -> sw, then z
+        k_xr_lscale<D2, double><<<gfp, TL, 0, s>>>(x, r, p, Ap, o->d_pre_Linv, z, scal, od, nfc);
+        k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                   o->d_pre_B, z, sw, nfc);
+        k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                   o->d_pre_Linv, sw, z, nfc);
         S.dot(r, z, scal + nw);
       } else {
         k_xr_precond_rz<D2, double, double><<<gfp, TL, 0, s>>>(x, r, p, Ap, Minv, z, scal, od, nfc, part);
@@ -735,8 +763,11 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       const int np1 = launch_spmv_pap<D2>(mesh, H32, p32, Ap32, part, s);
       k_sum_parts<<<1, kSumThreads, 0, s>>>(part, np1, scal + 1);
       if (learned) {
-        k_update_xr_slot<float><<<gv, T, 0, s>>>(d32, r32, p32, Ap32, scal, od, n);
-        pre32(r32, z32);
+        k_xr_lscale<D2, float><<<gfp, TL, 0, s>>>(d32, r32, p32, Ap32, o->d_pre_Linv, z32, scal, od, nfc);
+        k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                  o->d_pre_B, z32, sw32, nfc);
+        k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                  o->d_pre_Linv, sw32, z32, nfc);
         S.dot(r32, z32, scal + nw);
       } else {
         k_xr_precond_rz<D2, float, float><<<gfp, TL, 0, s>>>(d32, r32, p32, Ap32, Minv32, z32, scal, od, nfc, part);
@@ -776,8 +807,8 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
   if (!(opts->rtol > 0) || opts->max_iter < 0 || (opts->precision != 0 && opts->precision != 1) ||
       (opts->precond != 0 && opts->precond != 1))
     return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: bad options");
-  if (opts->precond == 1 && (!opts->d_pre_N || !opts->d_pre_Linv || !opts->d_pre_mirror))
-    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: the learned preconditioner needs N, Linv and mirror");
+  if (opts->precond == 1 && (!opts->d_pre_N || !opts->d_pre_Linv))
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: the learned preconditioner needs N and Linv");
   if (!d_ws || ws_bytes < ws_size(mesh, disc->host.d2, opts->precision))
     return set_error(HDG_ERR_WORKSPACE, "hdg_solve: workspace too small");
   hipStream_t s = (hipStream_t)stream;
@@ -812,26 +843,24 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
 namespace hdg {
 namespace {
 template <int D2>
-void lpre_apply64(const hdg_mesh* mesh, const float* N, const float* Bp, const float* Linv, const int* mirror,
-                  const double* r, double* z, double* tmp, hipStream_t s) {
+void lpre_apply64(const hdg_mesh* mesh, const float* N, const float* Bp, const float* Linv, const double* r, double* z,
+                  double* tmp, hipStream_t s) {
   const int nfc = (int)mesh->nfc;
   const unsigned gf = (unsigned)((nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES);
   constexpr unsigned TL = Lpre<D2>::THREADS;
   k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(Linv, r, z, nfc);
   k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, N, Bp, z, tmp, nfc);
-  k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, mirror, N, Linv, tmp, z,
-                                             nfc);
+  k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, N, Linv, tmp, z, nfc);
 }
 }  // namespace
 }  // namespace hdg
 
 extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N,
-                                            const float* d_B, const float* d_Linv, const int32_t* d_mirror,
-                                            const double* d_r,
+                                            const float* d_B, const float* d_Linv, const double* d_r,
                                             double* d_z, void* d_ws, size_t ws_bytes, void* stream) {
   hdg_status st = check_disc_mesh(disc, mesh, "hdg_gnn_precond_apply");
   if (st) return st;
-  if (!d_N || !d_Linv || !d_mirror || !d_r || !d_z || !mesh->d_row_ptr || !mesh->d_col_idx)
+  if (!d_N || !d_Linv || !d_r || !d_z || !mesh->d_row_ptr || !mesh->d_col_idx)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_precond_apply: NULL argument");
   if (d_r == d_z) return set_error(HDG_ERR_INVALID_ARG, "hdg_gnn_precond_apply: r and z must not overlap");
   const size_t need = (size_t)mesh->nfc * disc->host.d2 * sizeof(double);
@@ -839,11 +868,11 @@ extern "C" hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh
   hipStream_t s = (hipStream_t)stream;
   double* tmp = (double*)d_ws;
   switch (disc->host.k) {
-    case 0: lpre_apply64<dim2(0)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 1: lpre_apply64<dim2(1)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 2: lpre_apply64<dim2(2)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 3: lpre_apply64<dim2(3)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
-    case 4: lpre_apply64<dim2(4)>(mesh, d_N, d_B, d_Linv, d_mirror, d_r, d_z, tmp, s); break;
+    case 0: lpre_apply64<dim2(0)>(mesh, d_N, d_B, d_Linv, d_r, d_z, tmp, s); break;
+    case 1: lpre_apply64<dim2(1)>(mesh, d_N, d_B, d_Linv, d_r, d_z, tmp, s); break;
+    case 2: lpre_apply64<dim2(2)>(mesh, d_N, d_B, d_Linv, d_r, d_z, tmp, s); break;
+    case 3: lpre_apply64<dim2(3)>(mesh, d_N, d_B, d_Linv, d_r, d_z, tmp, s); break;
+    case 4: lpre_apply64<dim2(4)>(mesh, d_N, d_B, d_Linv, d_r, d_z, tmp, s); break;
     default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_gnn_precond_apply: unsupported degree");
   }
   HDG_CHECK_LAUNCH("hdg_gnn_precond_apply");
