@@ -88,7 +88,7 @@ def local_blocks(ex, problem, R: Rules, elems=None):
     v, B, vol, BinvT = geometry(ex, elems)
     Ne = elems.size
     # ---- volume terms
-    xq = v[:, None, 0, :] + np.einsum("eij,qj->eqi", B, R.vol_pts)
+    xq = volume_points(ex, elems, R)
     X, Y, Z = xq[..., 0], xq[..., 1], xq[..., 2]
     W = vol[:, None] * R.vol_w[None, :]                   # |K| w_q
     kinv = 1.0 / np.asarray(problem.kappa(X, Y, Z), dtype=np.float64)

@@ -46,12 +46,3 @@ def tri_rule(n: int):
     w = W.ravel()
     return pts, w / w.sum()
 
-
-def barycentric_tet(pts):
-    """Rows (1 - x - y - z, x, y, z): the matrix Lambda of eq 3.4."""
-    return np.concatenate([1 - pts.sum(axis=1, keepdims=True), pts], axis=1)
-
-
-def barycentric_tri(pts):
-    """Rows (1 - s - t, s, t): the matrix Xi of Section 4."""
-    return np.concatenate([1 - pts.sum(axis=1, keepdims=True), pts], axis=1)
