@@ -31,7 +31,7 @@ namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int kIrThreads = 256;
+constexpr int kIrThreads = 512;
 
 __host__ __device__ constexpr int up16(int n) { return (n + 15) / 16 * 16; }
 
