@@ -567,6 +567,20 @@ hdg_status hdg_gnn_loss_grad(const hdg_gnn_shape* shape, const float* d_params, 
 hdg_status hdg_gnn_precond_apply(const hdg_disc* disc, const hdg_mesh* mesh, const float* d_N, const float* d_B,
                                  const float* d_Linv, const double* d_r, double* d_z, void* d_ws, size_t ws_bytes,
                                  void* stream);
+/* Checkpoints of the parameter vector in the safetensors layout: an 8-byte little-endian
+ * header length, a JSON header {"__metadata__": {string: string}, "params": {"dtype": "F32",
+ * "shape": [n], "data_offsets": [0, 4 n]}}, then n little-endian FP32 words.  The metadata
+ * holds the shape as "d2", "hidden", "layers" and any caller pairs.  Host memory only.
+ *   hdg_gnn_save: h_params [n] (n = hdg_gnn_param_count(shape)), nmeta caller pairs
+ *   hdg_gnn_load_info: the shape and n of a file;  hdg_gnn_load: its parameters into h_params [n]
+ *   hdg_gnn_checkpoint_meta: the value of one metadata key; *len its length, out (may be NULL)
+ *     receives at most cap - 1 bytes and a terminating zero
+ * Errors: HDG_ERR_INVALID_ARG (I/O failure, malformed file, count or shape mismatch). */
+hdg_status hdg_gnn_save(const char* path, const hdg_gnn_shape* shape, const float* h_params, int64_t n,
+                        const char* const* meta_keys, const char* const* meta_values, int nmeta);
+hdg_status hdg_gnn_load_info(const char* path, hdg_gnn_shape* shape, int64_t* n);
+hdg_status hdg_gnn_load(const char* path, float* h_params, int64_t n);
+hdg_status hdg_gnn_checkpoint_meta(const char* path, const char* key, char* out, size_t cap, size_t* len);
 /* One Adam step (step = 1, 2, ...) on n parameters. */
 hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* d_m, float* d_v, int step, float lr,
                         float beta1, float beta2, float eps, void* stream);

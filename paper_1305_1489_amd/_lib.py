@@ -36,7 +36,8 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_project_hdg_workspace_size", "hdg_project_hdg", "hdg_superconvergence_norms_workspace_size",
            "hdg_superconvergence_norms", "hdg_assemble_condense_bdm", "hdg_gnn_precond_apply",
            "hdg_elem_face_qp_coords", "hdg_assemble_condense_cd", "hdg_export_local_cd",
-           "hdg_solve_gmres_workspace_size", "hdg_solve_gmres"]
+           "hdg_solve_gmres_workspace_size", "hdg_solve_gmres", "hdg_gnn_save", "hdg_gnn_load_info", "hdg_gnn_load",
+           "hdg_gnn_checkpoint_meta"]
 
 
 class HdgError(RuntimeError):
@@ -730,3 +731,34 @@ def hdg_solve_gmres(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=200
     if code != 0 and raise_on_fail:
         _check(code)
     return out
+
+
+# ----------------------------------------------------------------------------- checkpoints
+def hdg_gnn_save(path, shape, params, meta=None):
+    """params: FP32 vector (any device; copied to the host); meta: {str: str}."""
+    shp = _shape(shape)
+    h = params.detach().to("cpu", torch.float32).contiguous()
+    meta = meta or {}
+    keys = (C.c_char_p * max(len(meta), 1))(*[k.encode() for k in meta])
+    vals = (C.c_char_p * max(len(meta), 1))(*[str(v).encode() for v in meta.values()])
+    _check(lib().hdg_gnn_save(str(path).encode(), C.byref(shp), C.c_void_p(h.data_ptr()), C.c_int64(h.numel()),
+                              keys, vals, C.c_int(len(meta))))
+
+
+def hdg_gnn_load(path):
+    """Returns ((d2, hidden, layers), FP32 host tensor of the parameters)."""
+    shp = hdg_gnn_shape()
+    n = C.c_int64()
+    _check(lib().hdg_gnn_load_info(str(path).encode(), C.byref(shp), C.byref(n)))
+    h = torch.empty(n.value, dtype=torch.float32)
+    _check(lib().hdg_gnn_load(str(path).encode(), C.c_void_p(h.data_ptr()), n))
+    return (shp.d2, shp.hidden, shp.layers), h
+
+
+def hdg_gnn_checkpoint_meta(path, key):
+    ln = C.c_size_t()
+    _check(lib().hdg_gnn_checkpoint_meta(str(path).encode(), key.encode(), None, C.c_size_t(0), C.byref(ln)))
+    buf = C.create_string_buffer(ln.value + 1)
+    _check(lib().hdg_gnn_checkpoint_meta(str(path).encode(), key.encode(), buf, C.c_size_t(ln.value + 1),
+                                         C.byref(ln)))
+    return buf.value.decode()

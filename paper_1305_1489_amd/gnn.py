@@ -1,8 +1,8 @@
 """Learned face-graph preconditioner: parameters, training loop, checkpoints.
 
 The network, its loss and its gradient run in the library's kernels (hdg_gnn_*).  This
-module holds the parameter vector, draws the probe vectors and calls Adam, and it saves
-and loads checkpoints (safetensors).
+module holds the parameter vector, draws the probe vectors and calls Adam; checkpoints are
+written and read by the library (hdg_gnn_save, hdg_gnn_load: the safetensors layout).
 
 Training data follows the log-normal workload family: Kuhn cubes n ~ U{8..16}, degree 2,
 kappa = exp(1.5 g) with a fresh Gaussian random field per system (correlation length
@@ -108,19 +108,20 @@ class LearnedPreconditioner:
 
     # ---- checkpoints
     def save(self, path):
-        from safetensors.torch import save_file
+        """Through the library's checkpoint writer (safetensors layout, metadata as JSON strings)."""
         meta = {k: json.dumps(v) for k, v in self.meta.items()}
-        meta.update(d2=str(self.d2), hidden=str(self.hidden), layers=str(self.layers))
-        save_file({"params": self.params.detach().cpu().contiguous()}, path, metadata=meta)
+        L.hdg_gnn_save(path, self.shape, self.params, meta)
 
     @classmethod
     def load(cls, path, device="cuda"):
-        from safetensors import safe_open
-        with safe_open(path, framework="pt") as fh:
-            meta = fh.metadata()
-            params = fh.get_tensor("params")
-        obj = cls(int(meta["d2"]), int(meta["hidden"]), int(meta["layers"]), device=device, params=params)
-        obj.meta = {k: json.loads(v) for k, v in meta.items() if k not in ("d2", "hidden", "layers")}
+        (d2, hidden, layers), params = L.hdg_gnn_load(path)
+        obj = cls(d2, hidden, layers, device=device, params=params)
+        obj.meta = {}
+        for key in ("systems", "train_seconds", "train_steps", "first_loss", "last_loss", "lr", "nprobe", "data"):
+            try:
+                obj.meta[key] = json.loads(L.hdg_gnn_checkpoint_meta(path, key))
+            except L.HdgError:
+                pass
         return obj
 
 

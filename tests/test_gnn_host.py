@@ -45,3 +45,37 @@ def test_packaged_checkpoint_loads():
     assert lp.d2 == 6 and lp.meta.get("systems") == 2000
     assert torch.isfinite(lp.params).all()
     assert lp.meta["last_loss"] < lp.meta["first_loss"]  # training lowered the objective
+
+
+def test_checkpoint_io_agrees_with_the_safetensors_library(tmp_path):
+    """The library's checkpoint writer and reader against the independent safetensors
+    package: files written by either are read by the other with the same values and
+    metadata, and the packaged checkpoint loads in both."""
+    from safetensors import safe_open
+    from safetensors.torch import save_file
+    from bench import GNN_CHECKPOINT
+    shape = (6, 8, 2)
+    n = L.hdg_gnn_param_count(shape)
+    params = torch.randn(n, generator=torch.Generator().manual_seed(5))
+    p1 = str(tmp_path / "lib.safetensors")
+    L.hdg_gnn_save(p1, shape, params, {"note": 'quoted "text" \\ and\nnewline', "systems": "7"})
+    with safe_open(p1, framework="pt") as fh:
+        meta = fh.metadata()
+        assert torch.equal(fh.get_tensor("params"), params)
+    assert meta["d2"] == "6" and meta["hidden"] == "8" and meta["layers"] == "2"
+    assert meta["note"] == 'quoted "text" \\ and\nnewline' and meta["systems"] == "7"
+    p2 = str(tmp_path / "ref.safetensors")
+    save_file({"params": params}, p2, metadata={"d2": "6", "hidden": "8", "layers": "2", "x": "y"})
+    shp, h = L.hdg_gnn_load(p2)
+    assert shp == shape and torch.equal(h, params)
+    assert L.hdg_gnn_checkpoint_meta(p2, "x") == "y"
+    shp, h = L.hdg_gnn_load(GNN_CHECKPOINT)
+    with safe_open(GNN_CHECKPOINT, framework="pt") as fh:
+        assert torch.equal(fh.get_tensor("params"), h)
+    import pytest
+    with pytest.raises(L.HdgError):
+        L.hdg_gnn_save(p1, (6, 8, 3), params)  # count does not match the shape
+    bad = tmp_path / "bad.safetensors"
+    bad.write_bytes(b"\x05\x00\x00\x00\x00\x00\x00\x00{oops")
+    with pytest.raises(L.HdgError):
+        L.hdg_gnn_load(str(bad))
