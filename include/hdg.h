@@ -496,6 +496,21 @@ hdg_status hdg_solve_gmres(const hdg_disc* disc, const hdg_mesh* mesh, const dou
                            double* d_uhat, double rtol, int max_iter, int restart, hdg_solve_info* info, void* d_ws,
                            size_t ws_bytes, void* stream);
 
+/* BiCGStab (van der Vorst's stabilised bi-conjugate gradients) for the same non-symmetric
+ * systems, right-preconditioned by the same block-Jacobi inverses: two products with H per
+ * iteration and no restart.  The scalars stay on the device; the host reads ||r||^2 every
+ * check_every iterations and accepts the iterate on the recomputed FP64 residual
+ * ||b - H x|| <= rtol ||b|| (otherwise the residual is replaced by the true one and the
+ * iteration starts again from x).  A breakdown (a non-finite residual) restarts from the
+ * last checked iterate.  info->iterations = iterations, info->outer = restarts,
+ * info->rel_residual = the true relative residual.  Workspace of
+ * hdg_solve_bicgstab_workspace_size bytes, caller-owned.
+ * Errors: HDG_ERR_INVALID_ARG, HDG_ERR_WORKSPACE, HDG_ERR_NOT_CONVERGED. */
+hdg_status hdg_solve_bicgstab_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* ws_bytes);
+hdg_status hdg_solve_bicgstab(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H, const double* d_b,
+                              double* d_uhat, double rtol, int max_iter, int check_every, hdg_solve_info* info,
+                              void* d_ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------------
  * Learned face-graph preconditioner for eq 6.5 (the paper leaves the solver open).
  *

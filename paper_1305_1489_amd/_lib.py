@@ -37,7 +37,7 @@ EXPORTS = ["hdg_last_error", "hdg_max_degree", "hdg_mesh_sizes", "hdg_mesh_expan
            "hdg_superconvergence_norms", "hdg_assemble_condense_bdm", "hdg_gnn_precond_apply",
            "hdg_elem_face_qp_coords", "hdg_assemble_condense_cd", "hdg_export_local_cd",
            "hdg_solve_gmres_workspace_size", "hdg_solve_gmres", "hdg_gnn_save", "hdg_gnn_load_info", "hdg_gnn_load",
-           "hdg_gnn_checkpoint_meta"]
+           "hdg_gnn_checkpoint_meta", "hdg_solve_bicgstab_workspace_size", "hdg_solve_bicgstab"]
 
 
 class HdgError(RuntimeError):
@@ -762,3 +762,19 @@ def hdg_gnn_checkpoint_meta(path, key):
     _check(lib().hdg_gnn_checkpoint_meta(str(path).encode(), key.encode(), buf, C.c_size_t(ln.value + 1),
                                          C.byref(ln)))
     return buf.value.decode()
+
+
+def hdg_solve_bicgstab(disc: Disc, mesh: Mesh, H, b, uhat, rtol=1e-10, max_iter=20000, check_every=10, ws=None,
+                       stream=None, raise_on_fail=True):
+    need = C.c_size_t()
+    _check(lib().hdg_solve_bicgstab_workspace_size(disc.handle, C.byref(mesh.struct), C.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(max(need.value, 8), dtype=torch.uint8, device=mesh.device)
+    info = hdg_solve_info()
+    code = lib().hdg_solve_bicgstab(disc.handle, C.byref(mesh.struct), _ptr(H), _ptr(b), _ptr(uhat),
+                                    C.c_double(rtol), C.c_int(max_iter), C.c_int(check_every), C.byref(info),
+                                    _ptr(ws), C.c_size_t(ws.numel()), _stream(stream))
+    out = {"iterations": info.iterations, "restarts": info.outer, "rel_residual": info.rel_residual, "status": code}
+    if code != 0 and raise_on_fail:
+        _check(code)
+    return out

@@ -1175,3 +1175,222 @@ extern "C" hdg_status hdg_solve_gmres(const hdg_disc* disc, const hdg_mesh* mesh
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve_gmres: unsupported degree");
 }
+
+// ---------------------------------------------------------------------------------------
+// BiCGStab for the non-symmetric trace system (van der Vorst's stabilised bi-conjugate
+// gradients), right-preconditioned by the same block-Jacobi inverses as GMRES: two
+// products with H per iteration and short recurrences, so no restart.  The scalars stay
+// on the device: scal[0] rho, scal[1] rho_new = (rh, r), scal[2] alpha, scal[3] omega,
+// scal[4] (rh, v), scal[5] (t, s), scal[6] (t, t), scal[7] (r, r).  The preconditioner is
+// applied inside the vector updates, one face's components meeting in LDS.  Every
+// reduction has a fixed order.
+namespace hdg {
+namespace {
+
+// p = r + beta (p - omega v) (p = r on the first step), ph = Minv p
+template <int D2>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_bicg_p(const double* __restrict__ r, double* __restrict__ p,
+                                                              const double* __restrict__ v,
+                                                              const double* __restrict__ Minv, double* __restrict__ ph,
+                                                              const double* __restrict__ scal, int first, int nfc) {
+  __shared__ double ps[Lpre<D2>::THREADS];
+  const int lf = threadIdx.x / D2, c = threadIdx.x % D2;
+  const int f = blockIdx.x * Lpre<D2>::FACES + lf;
+  const size_t i = (size_t)f * D2 + c;
+  double pv = 0.0;
+  if (f < nfc) {
+    if (first) {
+      pv = r[i];
+    } else {
+      const double beta = (scal[1] / scal[0]) * (scal[2] / scal[3]);
+      pv = r[i] + beta * (p[i] - scal[3] * v[i]);
+    }
+    p[i] = pv;
+  }
+  ps[threadIdx.x] = pv;
+  __syncthreads();
+  if (f < nfc) {
+    const double* m = Minv + ((size_t)f * D2 + c) * D2;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < D2; ++j) acc += m[j] * ps[lf * D2 + j];
+    ph[i] = acc;
+  }
+}
+
+// alpha = rho_new / (rh, v);  s = r - alpha v,  sh = Minv s
+template <int D2>
+__global__ void __launch_bounds__(Lpre<D2>::THREADS) k_bicg_s(const double* __restrict__ r,
+                                                              const double* __restrict__ v,
+                                                              const double* __restrict__ Minv, double* __restrict__ s,
+                                                              double* __restrict__ sh, double* __restrict__ scal,
+                                                              int nfc) {
+  __shared__ double ss[Lpre<D2>::THREADS];
+  const int lf = threadIdx.x / D2, c = threadIdx.x % D2;
+  const int f = blockIdx.x * Lpre<D2>::FACES + lf;
+  const size_t i = (size_t)f * D2 + c;
+  const double alpha = scal[1] / scal[4];
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[2] = alpha;  // no thread of this kernel reads it
+  double sv = 0.0;
+  if (f < nfc) {
+    sv = r[i] - alpha * v[i];
+    s[i] = sv;
+  }
+  ss[threadIdx.x] = sv;
+  __syncthreads();
+  if (f < nfc) {
+    const double* m = Minv + ((size_t)f * D2 + c) * D2;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < D2; ++j) acc += m[j] * ss[lf * D2 + j];
+    sh[i] = acc;
+  }
+}
+
+// omega = (t, s) / (t, t);  x += alpha ph + omega sh,  r = s - omega t;  rho <- rho_new
+__global__ void k_bicg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ s,
+                          const double* __restrict__ t, const double* __restrict__ ph, const double* __restrict__ sh,
+                          double* __restrict__ scal, size_t n) {
+  const double alpha = scal[2], omega = scal[5] / scal[6];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    x[i] = x[i] + alpha * ph[i] + omega * sh[i];
+    r[i] = s[i] - omega * t[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // no thread of this kernel reads these slots
+    scal[3] = omega;
+    scal[0] = scal[1];
+  }
+}
+
+size_t bicg_ws_doubles(size_t n, int nfc, int d2) { return 10 * n + (size_t)nfc * d2 * d2 + kRedBlocks + 16 + 64; }
+
+template <int D2>
+hdg_status run_bicgstab(const hdg_mesh* mesh, const double* H, const double* b, double* x, double rtol, int max_iter,
+                        int every, hdg_solve_info* info, double* ws, hipStream_t s) {
+  const size_t n = (size_t)mesh->nfc * D2;
+  const int nfc = (int)mesh->nfc;
+  double* r = ws;
+  double* rh = r + n;
+  double* p = rh + n;
+  double* ph = p + n;
+  double* v = ph + n;
+  double* sv = v + n;
+  double* sh = sv + n;
+  double* t = sh + n;
+  double* xs = t + n;  // the last iterate whose residual was finite
+  double* Minv = xs + n + n;
+  double* part = Minv + (size_t)nfc * D2 * D2;
+  double* scal = part + kRedBlocks;
+  const unsigned T = 256;
+  const unsigned gr = (unsigned)((n + T - 1) / T);
+  const unsigned gv = (unsigned)std::max<size_t>(1, std::min<size_t>((n + T - 1) / T, 8192));
+  const unsigned gf = (unsigned)((nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES);
+  constexpr unsigned TL = Lpre<D2>::THREADS;
+  auto dot = [&](const double* a, const double* c, double* out) {
+    k_dot_partial<double, double><<<kRedBlocks, kRedThreads, 0, s>>>(a, c, n, part);
+    k_dot_final<<<1, kRedThreads, 0, s>>>(part, out);
+  };
+  auto read = [&](const double* d) -> double {
+    double h = 0;
+    if (hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess) return std::nan("");
+    if (hipStreamSynchronize(s) != hipSuccess) return std::nan("");
+    return h;
+  };
+  k_bj_setup_lu<D2><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv);
+  dot(b, b, scal + 8);
+  const double bb = read(scal + 8);
+  HDG_CHECK_LAUNCH("hdg_solve_bicgstab setup");
+  info->iterations = 0;
+  info->outer = 0;
+  info->fell_back = 0;
+  info->rel_residual = 0;
+  if (!(bb > 0)) {
+    k_fill<double><<<gv, T, 0, s>>>(x, n, 0.0);
+    return HDG_OK;
+  }
+  const double tol2 = rtol * rtol * bb;
+  int it = 0, restarts = 0;
+  auto restart = [&]() {  // the true residual, a new shadow vector, and a first step
+    k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
+    k_copy<double><<<gv, T, 0, s>>>(r, rh, n);
+    k_copy<double><<<gv, T, 0, s>>>(x, xs, n);
+  };
+  restart();
+  bool first = true;
+  for (;;) {
+    if (it % every == 0 || it >= max_iter) {
+      dot(r, r, scal + 7);
+      const double rr = read(scal + 7);
+      HDG_CHECK_LAUNCH("hdg_solve_bicgstab");
+      if (!std::isfinite(rr)) {  // breakdown: back to the last finite iterate
+        if (restarts >= 50) break;
+        k_copy<double><<<gv, T, 0, s>>>(xs, x, n);
+        restart();
+        first = true;
+        ++restarts;
+        continue;
+      }
+      k_copy<double><<<gv, T, 0, s>>>(x, xs, n);
+      if (rr <= tol2 || it >= max_iter) {
+        k_residual<D2><<<gr, T, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, b, r, nfc);
+        dot(r, r, scal + 7);
+        const double tr = read(scal + 7);
+        info->iterations = it;
+        info->outer = restarts;
+        info->rel_residual = std::sqrt(tr / bb);
+        if (tr <= tol2) return HDG_OK;
+        if (it >= max_iter) return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve_bicgstab: iteration limit reached");
+        restart();  // the recursive residual drifted from the true one
+        first = true;
+        ++restarts;
+      }
+    }
+    dot(rh, r, scal + 1);
+    k_bicg_p<D2><<<gf, TL, 0, s>>>(r, p, v, Minv, ph, scal, first ? 1 : 0, nfc);
+    launch_spmv<D2>(mesh, H, ph, v, s);
+    dot(rh, v, scal + 4);
+    k_bicg_s<D2><<<gf, TL, 0, s>>>(r, v, Minv, sv, sh, scal, nfc);
+    launch_spmv<D2>(mesh, H, sh, t, s);
+    dot(t, sv, scal + 5);
+    dot(t, t, scal + 6);
+    k_bicg_xr<<<gv, T, 0, s>>>(x, r, sv, t, ph, sh, scal, n);
+    first = false;
+    ++it;
+  }
+  info->iterations = it;
+  info->outer = restarts;
+  info->rel_residual = std::nan("");
+  return set_error(HDG_ERR_NOT_CONVERGED, "hdg_solve_bicgstab: repeated breakdown");
+}
+
+}  // namespace
+}  // namespace hdg
+
+extern "C" hdg_status hdg_solve_bicgstab_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* ws_bytes) {
+  if (!disc || !mesh || !ws_bytes) return set_error(HDG_ERR_INVALID_ARG, "hdg_solve_bicgstab_workspace_size: NULL");
+  const int d2 = disc->host.d2;
+  *ws_bytes = sizeof(double) * hdg::bicg_ws_doubles((size_t)mesh->nfc * d2, (int)mesh->nfc, d2);
+  return HDG_OK;
+}
+
+extern "C" hdg_status hdg_solve_bicgstab(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_H,
+                                         const double* d_b, double* d_uhat, double rtol, int max_iter, int check_every,
+                                         hdg_solve_info* info, void* d_ws, size_t ws_bytes, void* stream) {
+  hdg_status st = check_disc_mesh(disc, mesh, "hdg_solve_bicgstab");
+  if (st) return st;
+  if (!d_H || !d_b || !d_uhat || !info || !(rtol > 0) || max_iter < 0 || check_every < 1)
+    return set_error(HDG_ERR_INVALID_ARG, "hdg_solve_bicgstab: bad argument");
+  size_t need = 0;
+  hdg_solve_bicgstab_workspace_size(disc, mesh, &need);
+  if (!d_ws || ws_bytes < need) return set_error(HDG_ERR_WORKSPACE, "hdg_solve_bicgstab: workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  double* ws = (double*)d_ws;
+  switch (disc->host.k) {
+    case 0: return run_bicgstab<dim2(0)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, check_every, info, ws, s);
+    case 1: return run_bicgstab<dim2(1)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, check_every, info, ws, s);
+    case 2: return run_bicgstab<dim2(2)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, check_every, info, ws, s);
+    case 3: return run_bicgstab<dim2(3)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, check_every, info, ws, s);
+    case 4: return run_bicgstab<dim2(4)>(mesh, d_H, d_b, d_uhat, rtol, max_iter, check_every, info, ws, s);
+  }
+  return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve_bicgstab: unsupported degree");
+}

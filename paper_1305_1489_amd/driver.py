@@ -101,12 +101,17 @@ class HDGSystem:
         L.hdg_assemble_condense_cd(self.disc, self.mesh, self.kappa, self.c, self.f, bv, bf, self.tau, self.H, self.F,
                                    self.X, stream=self.stream)
 
-    def run_cd(self, rtol=1e-10, restart=40, max_iter=20000):
-        """Convection-diffusion: condensation, boundary data, GMRES, reconstruction from X."""
+    def run_cd(self, rtol=1e-10, restart=40, max_iter=20000, solver="gmres"):
+        """Convection-diffusion: condensation, boundary data, GMRES(restart) or BiCGStab,
+        reconstruction from X."""
         self.assemble_cd()
         self.boundary()
-        info = L.hdg_solve_gmres(self.disc, self.mesh, self.H, self.F, self.uhat, rtol=rtol, max_iter=max_iter,
-                                 restart=restart, stream=self.stream)
+        if solver == "bicgstab":
+            info = L.hdg_solve_bicgstab(self.disc, self.mesh, self.H, self.F, self.uhat, rtol=rtol,
+                                        max_iter=max_iter, check_every=5, stream=self.stream)
+        else:
+            info = L.hdg_solve_gmres(self.disc, self.mesh, self.H, self.F, self.uhat, rtol=rtol, max_iter=max_iter,
+                                     restart=restart, stream=self.stream)
         q, u = L.hdg_recover_ir(self.disc, self.mesh, self.X, self.uhat, stream=self.stream)
         return dict(info=info, q=q, u=u)
 

@@ -78,15 +78,15 @@ def test_cd_system_matches_oracle(k, n):
     assert rel(S.F.cpu().numpy().ravel(), F) < TOL
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
-def test_cd_solution_matches_oracle(k):
-    """Condensation, boundary data, GMRES and the reconstruction against the oracle's
-    sparse-LU solution of the same discrete problem."""
+@pytest.mark.parametrize("k,solver", [(1, "gmres"), (2, "gmres"), (3, "gmres"), (1, "bicgstab"), (3, "bicgstab")])
+def test_cd_solution_matches_oracle(k, solver):
+    """Condensation, boundary data, GMRES or BiCGStab, and the reconstruction against the
+    oracle's sparse-LU solution of the same discrete problem."""
     m = _perm(3, 60 + k)
     pb = convection_sin_problem(beta_scale=2.0)
-    print(f"cd solve k={k}", flush=True)
+    print(f"cd solve k={k} {solver}", flush=True)
     S = gpu_system(m, k, pb)
-    r = S.run_cd(rtol=1e-13, restart=40)
+    r = S.run_cd(rtol=1e-13, restart=40, solver=solver)
     assert r["info"]["rel_residual"] <= 1e-13
     ex = oracle_expand(m)
     ref = OC.solve_problem(ex, pb, k)
@@ -121,6 +121,25 @@ def test_cd_beta_zero_is_diffusion(k):
     torch.cuda.synchronize()
     assert rel(S.H.cpu().numpy(), H0.cpu().numpy()) < 1e-13
     assert rel(S.F.cpu().numpy(), F0.cpu().numpy()) < 1e-13
+
+
+def test_bicgstab_polynomial_exactness_and_errors():
+    """BiCGStab through the whole chain on polynomial data (exact), and its argument checks."""
+    from paper_1305_1489_amd import _lib as L
+    k = 2
+    m = _perm(2, 83)
+    pb = convection_polynomial_problem(k, seed=k, kappa=1.3, c=0.7, beta_scale=1.5)
+    S = gpu_system(m, k, pb)
+    r = S.run_cd(rtol=1e-14, solver="bicgstab")
+    ex = oracle_expand(m)
+    err = OG.errors(ex, pb, k, r["q"].cpu().numpy(), r["u"].cpu().numpy(), S.uhat.cpu().numpy())
+    assert err["e_q"] < 1e-10 and err["e_u"] < 1e-10 and err["e_uhat"] < 1e-10, err
+    with pytest.raises(L.HdgError) as e:
+        L.hdg_solve_bicgstab(S.disc, S.mesh, S.H, S.F, S.uhat, check_every=0)
+    assert e.value.name == "HDG_ERR_INVALID_ARG"
+    out = L.hdg_solve_bicgstab(S.disc, S.mesh, S.H, S.F, S.uhat, rtol=1e-300, max_iter=3, check_every=1,
+                               raise_on_fail=False)
+    assert L.STATUS[out["status"]] == "HDG_ERR_NOT_CONVERGED"
 
 
 def test_gmres_on_symmetric_system_matches_pcg():
