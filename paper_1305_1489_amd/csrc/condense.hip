@@ -446,6 +446,114 @@ __global__ void __launch_bounds__(NT) k_condense(hdg_mesh mesh, Tables tb, const
                         EXPORT ? Cout : nullptr, EXPORT ? Cfout : nullptr, w);
 }
 
+// Degree 0, one thread per element: every block is 1 x 1, so the local solve of eq 5.1-5.6
+// is scalar.  With m = M (kappa^{-1} mass), C_s the divergence entries and
+// S = Mc + tauPP + sum_s C_s^2 / m, each right-hand side (b_x, b_y, b_z, b_u) gives
+//   u = (b_u - sum_s C_s b_s / m) / S,   q_s = (b_s + C_s u) / m,
+// with b_s = n_{l s} DP_l, b_u = -T_l DP_l for face column l and (0, 0, 0, f) for the load;
+// C^K[l][m] = sum_s n_{l s} DP_l q_s^(m) + T_l DP_l u^(m) + delta_lm T_l,
+// Cf^K[l] the same with the load column.  The factor store is (sqrt m, sqrt S, f), the
+// layout of the per-element kernel at d3 = 1.
+template <bool EXPORT>
+__device__ __forceinline__ void condense_k0_element(const hdg_mesh& mesh, const Tables& tb,
+                                                    const double* __restrict__ kappa, const double* __restrict__ cco,
+                                                    const double* __restrict__ fco, const double* __restrict__ tau,
+                                                    double* __restrict__ H, double* __restrict__ F,
+                                                    double* __restrict__ factors, const int* __restrict__ elems,
+                                                    double* __restrict__ Cout, double* __restrict__ Cfout, int w) {
+  constexpr int NQD = 8;  // (k + 2)^3 at k = 0
+  {
+    const int E = EXPORT ? elems[w] : w;
+    if (E < 0 || E >= mesh.nelt) return;
+    ElemGeom g;
+    load_geometry(E, mesh, tau, g);
+    double m = 0, mc = 0, f = 0;
+    for (int q = 0; q < NQD; ++q) {
+      const double wq = g.vol * tb.vol_w[q], p0 = tb.P[q];
+      const size_t e = (size_t)E * NQD + q;
+      m += wq / kappa[e] * p0 * p0;
+      mc += wq * cco[e] * p0 * p0;
+      f += wq * fco[e] * p0;
+    }
+    double cs[3], S = mc;
+    for (int l = 0; l < 4; ++l) S += g.T[l] * tb.PP[l];
+    for (int sd = 0; sd < 3; ++sd) {
+      cs[sd] = g.a[sd][0] * tb.Chat[0] + g.a[sd][1] * tb.Chat[1] + g.a[sd][2] * tb.Chat[2];
+      S += cs[sd] * cs[sd] / m;
+    }
+    double dp[4], qq[5][3], uu[5];
+    for (int l = 0; l < 4; ++l) dp[l] = tb.DP[g.mu[l] * 4 + l];
+    for (int c = 0; c < 5; ++c) {  // columns: faces 0..3, then the load
+      double bs[3], bu;
+      if (c < 4) {
+        for (int sd = 0; sd < 3; ++sd) bs[sd] = g.n[c][sd] * dp[c];
+        bu = -g.T[c] * dp[c];
+      } else {
+        bs[0] = bs[1] = bs[2] = 0.0;
+        bu = f;
+      }
+      double r = bu;
+      for (int sd = 0; sd < 3; ++sd) r -= cs[sd] * bs[sd] / m;
+      uu[c] = r / S;
+      for (int sd = 0; sd < 3; ++sd) qq[c][sd] = (bs[sd] + cs[sd] * uu[c]) / m;
+    }
+    // the upper triangle of C^K (c >= l), mirrored, so that H is exactly symmetric; column 4
+    // is the load, reached for every l
+    for (int l = 0; l < 4; ++l) {
+      const double a0 = g.n[l][0] * dp[l], a1 = g.n[l][1] * dp[l], a2 = g.n[l][2] * dp[l], a3 = g.T[l] * dp[l];
+      for (int c = l; c < 5; ++c) {
+        double v = a0 * qq[c][0] + a1 * qq[c][1] + a2 * qq[c][2] + a3 * uu[c];
+        if (c == 4) {
+          if (EXPORT)
+            Cfout[(size_t)w * 4 + l] = v;
+          else
+            unsafeAtomicAdd(&F[mesh.d_facebyele[4 * E + l]], v);
+          continue;
+        }
+        if (c == l) v += g.T[l];
+        if (EXPORT) {
+          Cout[((size_t)w * 4 + l) * 4 + c] = v;
+          Cout[((size_t)w * 4 + c) * 4 + l] = v;
+        } else if (c == l) {
+          unsafeAtomicAdd(&H[mesh.d_slot[16 * E + 5 * l]], v);
+        } else {
+          H[mesh.d_slot[16 * E + 4 * l + c]] = v;
+          H[mesh.d_slot[16 * E + 4 * c + l]] = v;
+        }
+      }
+    }
+    if (!EXPORT && factors) {
+      double* fa = factors + (size_t)E * 3;
+      fa[0] = sqrt(m);
+      fa[1] = sqrt(S);
+      fa[2] = f;
+    }
+  }
+}
+
+template <bool EXPORT>
+__global__ void __launch_bounds__(256) k_condense_k0(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+                                                     const double* __restrict__ cco, const double* __restrict__ fco,
+                                                     const double* __restrict__ tau, double* __restrict__ H,
+                                                     double* __restrict__ F, double* __restrict__ factors,
+                                                     const int* __restrict__ elems, int nwork,
+                                                     double* __restrict__ Cout, double* __restrict__ Cfout) {
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < nwork; w += gridDim.x * blockDim.x)
+    condense_k0_element<EXPORT>(mesh, tb, kappa, cco, fco, tau, H, F, factors, elems, Cout, Cfout, w);
+}
+
+// Batched degree 0: thread u takes element u - unit_begin of its mesh (same arithmetic, so the
+// same bits as a separate call).
+__global__ void __launch_bounds__(256) k_batch_condense_k0(const BatchItem* __restrict__ items, int nitems,
+                                                           int total_units, Tables tb) {
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < total_units; u += gridDim.x * blockDim.x) {
+    const BatchItem* it = items + batch_find(items, nitems, u);
+    condense_k0_element<false>(as_global(it->mesh), tb, as_global(it->kappa), as_global(it->c), as_global(it->f),
+                               as_global(it->tau), as_global(it->H), as_global(it->F), as_global(it->factors),
+                               nullptr, nullptr, nullptr, u - it->unit_begin);
+  }
+}
+
 // Persistent batched form: work unit u is element u - unit_begin of its mesh.
 template <int K, int NT>
 __global__ void __launch_bounds__(NT) k_batch_condense(const BatchItem* __restrict__ items, int nitems, int total_units,
@@ -479,10 +587,23 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
     HDG_CHECK_LAUNCH("k_zero_diag");
   }
   if (n == 0) return HDG_OK;
-  const hdg_tile_config lc = launch_config(K);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)lc.workgroups_per_cu * device_cu_count()));
   const hdg_mesh& m = *mesh;
   const Tables& tb = disc->dev;
+  if constexpr (K == 0) {  // scalar local systems: one thread per element
+    const unsigned g0 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65535));
+    if (Cout)
+      k_condense_k0<true><<<g0, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout);
+    else {
+      timer_begin("k_condense", s);
+      k_condense_k0<false><<<g0, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, nullptr, (int)n, nullptr,
+                                              nullptr);
+      timer_end("k_condense", s);
+    }
+    HDG_CHECK_LAUNCH("k_condense_k0");
+    return HDG_OK;
+  }
+  const hdg_tile_config lc = launch_config(K);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)lc.workgroups_per_cu * device_cu_count()));
   const int rm = lc.xcd_remap;
   if (Cout) {  // export form: one shape is enough
     k_condense<K, 256, true><<<grid, 256, 0, s>>>(m, tb, kappa, c, f, tau, H, F, factors, elems, (int)n, Cout, Cfout, rm);
@@ -552,7 +673,11 @@ hdg_status launch_batch_condense(int k, const Tables& tb, const BatchItem* d_ite
   if (nitems <= 0 || total_units <= 0) return HDG_OK;
   if (k >= 1 && k <= 3) return launch_batch_condense_tile(k, tb, d_items, nitems, total_units, grid, xcd_remap, s);
   switch (k) {
-    case 0: return launch_batch_element<0>(tb, d_items, nitems, total_units, grid, xcd_remap, waves, s);
+    case 0:  // one thread per element; the workgroup shape of the other degrees does not apply
+      k_batch_condense_k0<<<(unsigned)std::max(1, std::min((total_units + 255) / 256, 65535)), 256, 0, s>>>(
+          d_items, nitems, total_units, tb);
+      HDG_CHECK_LAUNCH("k_batch_condense_k0");
+      return HDG_OK;
     case 4: return launch_batch_element<4>(tb, d_items, nitems, total_units, grid, xcd_remap, waves, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "batched condensation: unsupported degree");
