@@ -496,7 +496,7 @@ def convection_metric(cfg, hip, reps=10):
 
 def psweep_metric(reps=10, n=16):
     """p-refinement (Section 10, Table 4, eq 10.3): the element hot path (the bench step:
-    condensation, boundary data, reconstruction, postprocess) at k = 0..4 on one fixed mesh
+    condensation, boundary data, reconstruction, postprocess) at k = 0..6 on one fixed mesh
     (Kuhn n^3, the smooth workload's data), elements/s per degree with the per-degree
     algorithmic flops; and, on the small fixed mesh of the p-convergence test, the errors of
     eq 10.1 from the GPU pipeline and their eq 10.3 ratios."""
@@ -509,7 +509,7 @@ def psweep_metric(reps=10, n=16):
     m = kuhn_mesh(n, dirichlet_sides=("x0", "x1"), neumann_sides=("y0", "y1", "z0", "z1"))
     stream = torch.cuda.current_stream()
     per_k = {}
-    for k in range(0, 5):
+    for k in range(0, 7):
         S = HDGSystem(m.coordinates, m.elements, m.dirichlet, m.neumann, k, pb)
         S.assemble()
         S.boundary()
@@ -546,7 +546,7 @@ def psweep_metric(reps=10, n=16):
     small = kuhn_mesh(3, jitter=0.1, seed=12, dirichlet_sides=("x0", "x1"), neumann_sides=("y0", "y1", "z0", "z1"))
     ex = OM.expand(small.coordinates, small.elements, small.dirichlet, small.neumann)
     errs = {a: [] for a in ("e_q", "e_u", "e_uhat")}
-    for k in range(0, 5):
+    for k in range(0, 7):
         S = HDGSystem(small.coordinates, small.elements, small.dirichlet, small.neumann, k, pb)
         r = S.run(rtol=1e-13)
         e = OG.errors(ex, pb, k, r["q"].cpu().numpy(), r["u"].cpu().numpy(), S.uhat.cpu().numpy())
@@ -554,7 +554,7 @@ def psweep_metric(reps=10, n=16):
             errs[a].append(e[a])
     rat = {a: [math.log(v[i] / v[i + 1]) / math.log(v[i + 1] / v[i + 2]) for i in range(len(v) - 2)]
            for a, v in errs.items()}
-    return {"workload": f"Kuhn {n}^3 ({m.nelt} tets), smooth data, k = 0..4; errors on the jittered n=3 mesh "
+    return {"workload": f"Kuhn {n}^3 ({m.nelt} tets), smooth data, k = 0..6; errors on the jittered n=3 mesh "
                         f"({small.elements.shape[0]} tets)",
             "step": "hdg_assemble_condense (+ per-face sums at k=1..3) + hdg_boundary + hdg_recover with u*",
             "per_degree": per_k, "errors": errs, "ratios_eq_10_3": rat}
@@ -668,7 +668,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-condensation workload")
     ap.add_argument("--no-projection", action="store_true", help="skip the HDG / trace projection timing")
     ap.add_argument("--no-bdm", action="store_true", help="skip the hybridized BDM condensation timing")
-    ap.add_argument("--no-psweep", action="store_true", help="skip the k = 0..4 p-refinement sweep")
+    ap.add_argument("--no-psweep", action="store_true", help="skip the k = 0..6 p-refinement sweep")
     ap.add_argument("--no-convection", action="store_true", help="skip the convection-diffusion timing")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run a plain device copy of this many bytes (counter calibration)")

@@ -60,7 +60,9 @@ enum {
 /* Thread-local message describing the last failing call (never NULL). */
 const char* hdg_last_error(void);
 
-/* Largest supported polynomial degree. */
+/* Largest supported polynomial degree (6).  Degrees 0..6 have the whole path (condensation,
+ * boundary data, PCG, reconstruction, postprocess); the batched, FP32-refined, learned,
+ * export and non-symmetric forms stop at the degrees their entries state. */
 int hdg_max_degree(void);
 
 /* Measurement hook (no effect on results): while set, every launch by this thread of the
@@ -212,6 +214,10 @@ hdg_status hdg_face_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, const 
  * Every block of H and every entry of F is written; off-diagonal blocks have one
  * contributing element, diagonal blocks and F entries at most two, summed in an
  * order-independent way, so results are bitwise reproducible.
+ * Degrees 5 and 6 keep each element's solved blocks (the columns L^{-1} [C^T | DP^T] and
+ * Ls^{-1} [B | f], 147 KB per element at k = 5 and 313 KB at k = 6) in a caller workspace,
+ * so this entry, which takes none, returns HDG_ERR_WORKSPACE for them: use
+ * hdg_assemble_condense_ws (or hdg_assemble_condense_noalloc).
  * Errors: HDG_ERR_INVALID_ARG; HDG_ERR_SINGULAR when the mesh has no Dirichlet face and
  * c == 0 at every volume point (Section 1: constants then solve the homogeneous system).
  * That check runs only for meshes without Dirichlet faces; it reads one flag back and so
@@ -225,7 +231,8 @@ hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh* mesh, con
 hdg_status hdg_check_tau(const hdg_mesh* mesh, const double* d_tau, void* stream);
 
 /* Debug / parity export: C^K (m x m, row-major) and Cf^K for the listed elements,
- * computed by the same device code as hdg_assemble_condense.
+ * computed by the same device code as hdg_assemble_condense.  Degrees 0..4
+ * (HDG_ERR_UNSUPPORTED_DEGREE above).
  *   d_elems int32 [n], d_C double [n][m][m], d_Cf double [n][m]. */
 hdg_status hdg_export_local(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa, const double* d_c,
                             const double* d_f, const double* d_tau, const int32_t* d_elems, int64_t n,
@@ -261,7 +268,8 @@ typedef struct {
   int check_every;    /* iterations between host convergence checks (>= 1) */
   int precision;      /* 0: FP64 throughout; 1: FP32 matrix and preconditioner inside
                          an FP64 iterative-refinement loop */
-  int precond;        /* 0: block-Jacobi; 1: learned factor (needs the three arrays below) */
+  int precond;        /* 0: block-Jacobi; 1: learned factor (needs the three arrays below;
+                         degrees 0..4, else HDG_ERR_UNSUPPORTED_DEGREE) */
   const float* d_pre_N;      /* [nnzb][d2][d2] N of the learned factor, lower blocks and their
                                 transposes at the mirrored positions (hdg_gnn_forward) */
   const float* d_pre_Linv;   /* [nfc][d2][d2]  hdg_gnn_graph.Linv */
@@ -304,7 +312,7 @@ hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
  *   d_q      double [nelt][3][d3]   d_u   double [nelt][d3]   (layouts of hdg_recover)
  *   d_factors  the factor store of hdg_assemble_condense(_ws) for the same mesh and tau,
  *            or NULL: for degrees 1..3 the element geometry is then read from it instead
- *            of recomputed (same values); ignored for degrees 0 and 4
+ *            of recomputed (same values); ignored for degrees 0, 4, 5 and 6
  * Output: d_ustar double [nelt][d3p].  Errors: HDG_ERR_INVALID_ARG (NULL array),
  * HDG_ERR_UNSUPPORTED_DEGREE, HDG_ERR_DEVICE.  Nothing is allocated.
  * ------------------------------------------------------------------------------ */
@@ -320,7 +328,11 @@ hdg_status hdg_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const dou
  * condensation loads it in one pass.  Workspace: hdg_condense_workspace_size bytes =
  * round_up(4 Nelt (d2 (d2 + 1) / 2 + d2) 8, 256) + 384 Nelt, device memory owned by the
  * caller, contents undefined on entry and exit (0 for degrees 0 and 4, which always use
- * the atomic scatter).  Errors: those of hdg_assemble_condense, HDG_ERR_WORKSPACE. */
+ * the atomic scatter).  Degrees 5 and 6 scatter with the two-addend atomics as well and use
+ * the workspace for the element blocks: one slice of d3 (3 d3 + 4 d2) + d3 (4 d2 + 1)
+ * doubles per workgroup of the persistent grid (workgroups_per_cu of hdg_set_launch_config
+ * times the compute units, at most Nelt): 37.7 MB at k = 5 and 80 MB at k = 6 on 256
+ * compute units.  Errors: those of hdg_assemble_condense, HDG_ERR_WORKSPACE. */
 hdg_status hdg_condense_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes);
 hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, const double* d_kappa,
                                     const double* d_c, const double* d_f, const double* d_tau, double* d_H, double* d_F,
@@ -333,7 +345,8 @@ hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_mesh* mesh, 
  * held until the process ends; the call itself allocates nothing.  The caller still passes
  * every input and output.  Same results as hdg_assemble_condense_ws, bit for bit.
  * Limit: hdg_condense_workspace_size(disc, mesh) must not exceed the capacity (k = 3: up to
- * about 108,000 elements; k = 2: 215,000; k = 1: 399,000; k = 0, 4 need none), else
+ * about 108,000 elements; k = 2: 215,000; k = 1: 399,000; k = 0, 4 need none; k = 5, 6 any
+ * mesh at one workgroup per compute unit), else
  * HDG_ERR_WORKSPACE before any launch.  Every call on a device shares that device's array
  * and leaves it in an undefined state: calls that overlap in time on one device (two
  * streams, two threads) race and must be serialised by the caller.  Errors: those of
@@ -606,7 +619,8 @@ hdg_status hdg_gnn_adam(int64_t n, float* d_params, const float* d_grad, float* 
  * Each mesh of the batch gets exactly what hdg_assemble_condense gives it (H, F and the
  * factor store, bit for bit); the element work is that of Sections 3-6 (eq 5.5-5.6) and
  * the scatter of eq 6.5, cut into work units (groups of four elements for k = 1..3,
- * single elements for k = 0 and 4) and swept by one persistent kernel per degree.
+ * single elements for k = 0 and 4) and swept by one persistent kernel per degree; degrees
+ * 0..4 (hdg_batch_create returns HDG_ERR_UNSUPPORTED_DEGREE for a mesh of degree 5 or 6).
  *
  * hdg_batch_create copies the item list and the mesh structs; the discs, the mesh arrays,
  * the coefficient arrays and the outputs stay owned by the caller and must outlive the

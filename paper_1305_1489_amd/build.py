@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhdg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "tables.cpp", "mesh.hip", "condense.hip", "condense_tile.hip", "boundary.hip", "recover.hip", "postprocess.hip", "solve.hip", "batch.hip", "gnn.hip", "ir.hip", "projection.hip", "convection.hip", "checkpoint.cpp"]
+SOURCES = ["api.cpp", "tables.cpp", "mesh.hip", "condense.hip", "condense_tile.hip", "boundary.hip", "recover.hip", "postprocess.hip", "solve.hip", "batch.hip", "gnn.hip", "ir.hip", "projection.hip", "convection.hip", "condense_big.hip", "checkpoint.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]

@@ -126,6 +126,8 @@ extern "C" hdg_status hdg_batch_create(int n, const hdg_batch_item* items, hdg_b
     if (st) return st;
     if (!it.d_kappa || !it.d_c || !it.d_f || !it.d_tau || !it.d_H || !it.d_F)
       return set_error(HDG_ERR_INVALID_ARG, "hdg_batch_create: NULL array in item " + std::to_string(i));
+    if (it.disc->host.k > kMaxBatchDegree)
+      return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_batch_create: degrees 0..4 (item " + std::to_string(i) + ")");
     st = check_not_singular(it.disc, it.mesh, it.d_c, nullptr, "hdg_batch_create");
     if (st) return set_error(st, std::string(hdg_last_error()) + " (item " + std::to_string(i) + ")");
   }

@@ -173,6 +173,9 @@ extern "C" hdg_status hdg_qp_coords(const hdg_disc* disc, const hdg_mesh* mesh, 
     case 2: k_qp_coords<Dims<2>::NQD><<<grid, 256, 0, s>>>(*mesh, disc->d_tables + disc->host.off.lambda, d_xyz); break;
     case 3: k_qp_coords<Dims<3>::NQD><<<grid, 256, 0, s>>>(*mesh, disc->d_tables + disc->host.off.lambda, d_xyz); break;
     case 4: k_qp_coords<Dims<4>::NQD><<<grid, 256, 0, s>>>(*mesh, disc->d_tables + disc->host.off.lambda, d_xyz); break;
+    case 5: k_qp_coords<Dims<5>::NQD><<<grid, 256, 0, s>>>(*mesh, disc->d_tables + disc->host.off.lambda, d_xyz); break;
+    case 6: k_qp_coords<Dims<6>::NQD><<<grid, 256, 0, s>>>(*mesh, disc->d_tables + disc->host.off.lambda, d_xyz); break;
+    default: return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_qp_coords: unsupported degree");
   }
   HDG_CHECK_LAUNCH("hdg_qp_coords");
   return HDG_OK;
@@ -206,6 +209,8 @@ extern "C" hdg_status hdg_boundary(const hdg_disc* disc, const hdg_mesh* mesh, c
     case 2: return run_boundary<2>(disc, mesh, d_uD, d_gN, d_H, d_F, d_uhat, s);
     case 3: return run_boundary<3>(disc, mesh, d_uD, d_gN, d_H, d_F, d_uhat, s);
     case 4: return run_boundary<4>(disc, mesh, d_uD, d_gN, d_H, d_F, d_uhat, s);
+    case 5: return run_boundary<5>(disc, mesh, d_uD, d_gN, d_H, d_F, d_uhat, s);
+    case 6: return run_boundary<6>(disc, mesh, d_uD, d_gN, d_H, d_F, d_uhat, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_boundary: unsupported degree");
 }

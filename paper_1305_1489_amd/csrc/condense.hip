@@ -633,7 +633,9 @@ namespace {
 hdg_status dispatch_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
                              const double* f, const double* tau, double* H, double* F, double* factors,
                              const int* elems, int64_t n, double* Cout, double* Cfout, hipStream_t s,
-                             double* dws = nullptr) {
+                             double* dws = nullptr, size_t ws_bytes = 0) {
+  if (disc->host.k >= 5)
+    return dispatch_condense_big(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, dws, ws_bytes, s);
   if (disc->host.k >= 1 && disc->host.k <= 3)
     return dispatch_condense_tile(disc, mesh, kappa, c, f, tau, H, F, factors, elems, n, Cout, Cfout, dws, s);
   switch (disc->host.k) {
@@ -744,7 +746,10 @@ extern "C" hdg_status hdg_assemble_condense(const hdg_disc* disc, const hdg_mesh
 
 extern "C" hdg_status hdg_condense_workspace_size(const hdg_disc* disc, const hdg_mesh* mesh, size_t* bytes) {
   if (!disc || !mesh || !bytes) return set_error(HDG_ERR_INVALID_ARG, "hdg_condense_workspace_size: NULL argument");
-  *bytes = (disc->host.k >= 1 && disc->host.k <= 3) ? condense_ws_bytes(disc->host.d2, mesh->nelt) : 0;
+  const int k = disc->host.k;
+  *bytes = (k >= 1 && k <= 3) ? condense_ws_bytes(disc->host.d2, mesh->nelt)
+           : k >= 5           ? condense_big_workspace_bytes(k, mesh->nelt)
+                              : 0;
   return HDG_OK;
 }
 
@@ -763,7 +768,7 @@ extern "C" hdg_status hdg_assemble_condense_ws(const hdg_disc* disc, const hdg_m
   st = check_not_singular(disc, mesh, d_c, (hipStream_t)stream, "hdg_assemble_condense_ws");
   if (st) return st;
   return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
-                           nullptr, (hipStream_t)stream, need ? (double*)d_ws : nullptr);
+                           nullptr, (hipStream_t)stream, need ? (double*)d_ws : nullptr, ws_bytes);
 }
 
 namespace hdg {
@@ -792,7 +797,7 @@ extern "C" hdg_status hdg_assemble_condense_noalloc(const hdg_disc* disc, const 
   st = check_not_singular(disc, mesh, d_c, (hipStream_t)stream, "hdg_assemble_condense_noalloc");
   if (st) return st;
   return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, d_H, d_F, d_factors, nullptr, mesh->nelt, nullptr,
-                           nullptr, (hipStream_t)stream, ws);
+                           nullptr, (hipStream_t)stream, ws, need);
 }
 
 namespace hdg {
@@ -826,6 +831,8 @@ extern "C" hdg_status hdg_export_local(const hdg_disc* disc, const hdg_mesh* mes
   if (st) return st;
   if (!d_kappa || !d_c || !d_f || !d_tau || !d_elems || !d_C || !d_Cf || n < 0)
     return set_error(HDG_ERR_INVALID_ARG, "hdg_export_local: NULL array");
+  if (disc->host.k > kMaxBatchDegree)
+    return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_export_local: degrees 0..4");
   return dispatch_condense(disc, mesh, d_kappa, d_c, d_f, d_tau, nullptr, nullptr, nullptr, d_elems, n, d_C, d_Cf,
                            (hipStream_t)stream);
 }

@@ -11,7 +11,9 @@
 
 namespace hdg {
 
-constexpr int kMaxDegree = 4;
+constexpr int kMaxDegree = 6;
+// Highest degree of the batched, FP32-refined and learned forms (the per-element LDS kernels).
+constexpr int kMaxBatchDegree = 4;
 
 inline constexpr int dim3(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 inline constexpr int dim2(int k) { return (k + 1) * (k + 2) / 2; }
@@ -94,6 +96,16 @@ struct BatchItem {
   int unit_begin;
   int pad_;
 };
+
+// Degrees 5 and 6 (condense_big.hip): workspace bytes of the condensation of n elements,
+// the condensation itself (ws: that workspace), and the postprocess u*.
+size_t condense_big_workspace_bytes(int k, int64_t n);
+hdg_status dispatch_condense_big(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* c,
+                                 const double* f, const double* tau, double* H, double* F, double* factors,
+                                 const int* elems, int64_t n, double* Cout, double* Cfout, double* ws,
+                                 size_t ws_bytes, hipStream_t s);
+hdg_status launch_postprocess_big(const hdg_disc* disc, const hdg_mesh* mesh, const double* kappa, const double* tau,
+                                  const double* q, const double* u, double* us, hipStream_t s);
 
 // Elements per work unit of the condensation kernel used for degree k.
 int condense_unit(int k);

@@ -320,6 +320,8 @@ hdg_status launch_postprocess(const hdg_disc* disc, const hdg_mesh* mesh, const 
     case 2: return run_postprocess<2>(disc, mesh, kappa, tau, q, u, factors, us, s);
     case 3: return run_postprocess<3>(disc, mesh, kappa, tau, q, u, factors, us, s);
     case 4: return run_postprocess<4>(disc, mesh, kappa, tau, q, u, factors, us, s);
+    case 5:
+    case 6: return launch_postprocess_big(disc, mesh, kappa, tau, q, u, us, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover: unsupported degree");
 }

@@ -437,6 +437,8 @@ extern "C" hdg_status hdg_recover(const hdg_disc* disc, const hdg_mesh* mesh, co
     case 2: return run_recover<2>(disc, mesh, d_kappa, d_tau, d_factors, d_uhat, d_q, d_u, d_ustar, s);
     case 3: return run_recover<3>(disc, mesh, d_kappa, d_tau, d_factors, d_uhat, d_q, d_u, d_ustar, s);
     case 4: return run_recover<4>(disc, mesh, d_kappa, d_tau, d_factors, d_uhat, d_q, d_u, d_ustar, s);
+    case 5: return run_recover<5>(disc, mesh, d_kappa, d_tau, d_factors, d_uhat, d_q, d_u, d_ustar, s);
+    case 6: return run_recover<6>(disc, mesh, d_kappa, d_tau, d_factors, d_uhat, d_q, d_u, d_ustar, s);
   }
   return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_recover: unsupported degree");
 }

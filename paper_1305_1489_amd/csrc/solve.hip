@@ -61,6 +61,63 @@ __global__ void k_bj_setup(const double* __restrict__ H, const int* __restrict__
     for (int j = 0; j < D2; ++j) o[i * D2 + j] = (T)(0.5 * (X[i][j] + X[j][i]));
 }
 
+// The same for the blocks of degrees 5 and 6 (d2 = 21, 28), too large for one thread's
+// registers: one workgroup of 64 threads per face, the block factored in LDS (right-looking,
+// one row per thread), then one column of the inverse per thread.
+template <int D2, class T>
+__global__ void __launch_bounds__(64) k_bj_setup_wg(const double* __restrict__ H, const int* __restrict__ diag,
+                                                   int nfc, T* __restrict__ Minv) {
+  __shared__ double A[D2][D2 + 1];
+  __shared__ double X[D2][D2 + 1];
+  const int t = threadIdx.x;
+  for (int f = blockIdx.x; f < nfc; f += gridDim.x) {
+    const double* blk = H + (size_t)diag[f] * D2 * D2;
+    for (int i = t; i < D2 * D2; i += 64) A[i / D2][i % D2] = blk[i];
+    __syncthreads();
+    for (int j = 0; j < D2; ++j) {  // Cholesky, lower: column j from the updated trailing block
+      const double d = sqrt(A[j][j]);
+      __syncthreads();
+      if (t >= j && t < D2) A[t][j] = t == j ? d : A[t][j] / d;
+      __syncthreads();
+      if (t > j && t < D2)
+        for (int k = j + 1; k <= t; ++k) A[t][k] -= A[t][j] * A[k][j];
+      __syncthreads();
+    }
+    if (t < D2) {  // column t of the inverse, kept in LDS
+#pragma unroll 1
+      for (int r = 0; r < D2; ++r) {
+        double v = r == t ? 1.0 : 0.0;
+#pragma unroll 4
+        for (int k = 0; k < r; ++k) v -= A[r][k] * X[k][t];
+        X[r][t] = v / A[r][r];
+      }
+#pragma unroll 1
+      for (int r = D2 - 1; r >= 0; --r) {
+        double v = X[r][t];
+#pragma unroll 4
+        for (int k = r + 1; k < D2; ++k) v -= A[k][r] * X[k][t];
+        X[r][t] = v / A[r][r];
+      }
+    }
+    __syncthreads();
+    T* o = Minv + (size_t)f * D2 * D2;
+    for (int i = t; i < D2 * D2; i += 64) {
+      const int r = i / D2, c = i % D2;
+      o[i] = (T)(0.5 * (X[r][c] + X[c][r]));
+    }
+    __syncthreads();
+  }
+}
+
+// Minv[f] = (H_ff)^{-1} for every face, the form that suits the block size.
+template <int D2, class T>
+void launch_bj_setup(const double* H, const int* diag, int nfc, T* Minv, hipStream_t s) {
+  if constexpr (D2 > 15)
+    k_bj_setup_wg<D2, T><<<std::max(1, std::min(nfc, 8192)), 64, 0, s>>>(H, diag, nfc, Minv);
+  else
+    k_bj_setup<D2, T><<<(nfc + 63) / 64, 64, 0, s>>>(H, diag, nfc, Minv);
+}
+
 template <class T>
 __global__ void k_convert(const double* __restrict__ a, T* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -267,7 +324,7 @@ __global__ void __launch_bounds__(Lpre<D2>::THREADS) k_lpre_upper(const int* __r
 // lane order.  With PAP, part[wg] = the workgroup's share of p.Ap.
 template <int D2>
 struct SpmvC {
-  static_assert(D2 % 2 == 0, "pairs of columns");
+  static_assert(D2 % 2 == 0 && D2 * D2 / 2 <= 256, "pairs of columns, a face's lanes in one workgroup");
   static constexpr int LPR = D2 / 2, LPF = D2 * LPR, FACES = 256 / LPF, THREADS = FACES * LPF;
 };
 
@@ -373,7 +430,7 @@ constexpr int kMaxParts = 2048;
 template <int D2>
 void launch_spmv(const hdg_mesh* mesh, const double* H, const double* x, double* y, hipStream_t s) {
   const int nfc = (int)mesh->nfc;
-  if constexpr (D2 % 2 == 0 && D2 >= 6) {
+  if constexpr (D2 % 2 == 0 && D2 >= 6 && D2 * D2 / 2 <= 256) {
     const int groups = (nfc + SpmvC<D2>::FACES - 1) / SpmvC<D2>::FACES;
     k_spmv_c<D2, double, double, false><<<std::max(1, std::min(groups, kMaxParts)), 256, 0, s>>>(
         mesh->d_row_ptr, mesh->d_col_idx, H, x, y, nfc, nullptr);
@@ -386,7 +443,7 @@ void launch_spmv(const hdg_mesh* mesh, const double* H, const double* x, double*
 template <int D2, class TM, class TV>
 int launch_spmv_pap(const hdg_mesh* mesh, const TM* H, const TV* x, TV* y, double* part, hipStream_t s) {
   const int nfc = (int)mesh->nfc;
-  if constexpr (D2 % 2 == 0 && D2 >= 6 && sizeof(TM) == 8) {  // 16-byte pairs (FP64 H)
+  if constexpr (D2 % 2 == 0 && D2 >= 6 && D2 * D2 / 2 <= 256 && sizeof(TM) == 8) {  // 16-byte pairs (FP64 H)
     const int groups = (nfc + SpmvC<D2>::FACES - 1) / SpmvC<D2>::FACES;
     const int g = std::max(1, std::min(groups, kMaxParts));
     k_spmv_c<D2, TM, TV, true><<<g, 256, 0, s>>>(mesh->d_row_ptr, mesh->d_col_idx, H, x, y, nfc, part);
@@ -632,34 +689,37 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   const unsigned gr = (unsigned)((n + T - 1) / T);
   Solver<D2> S{mesh, s, n, gv, gr, part, scal};
   const int nfc = (int)mesh->nfc;
-  const bool learned = o->precond == 1;
+  constexpr bool kLearn = D2 <= 15;  // the learned factor exists for degrees 0..4
+  const bool learned = kLearn && o->precond == 1;
   const unsigned gf = (unsigned)((nfc + Lpre<D2>::FACES - 1) / Lpre<D2>::FACES);
   constexpr unsigned TL = Lpre<D2>::THREADS;
   auto pre64 = [&](const double* rr_, double* zz_) {
-    if (learned) {  // t -> zz_, s -> sw, then z -> zz_
-      k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
-      k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                 o->d_pre_B, zz_,
-                                                 sw, nfc);
-      k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                 o->d_pre_Linv, sw, zz_, nfc);
-    } else {
-      k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, rr_, zz_, nfc);
+    if constexpr (kLearn) {
+      if (learned) {  // t -> zz_, s -> sw, then z -> zz_
+        k_lpre_scale<D2, double><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
+        k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                   o->d_pre_B, zz_, sw, nfc);
+        k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                   o->d_pre_Linv, sw, zz_, nfc);
+        return;
+      }
     }
+    k_precond<D2, double, double><<<gr, T, 0, s>>>(Minv, rr_, zz_, nfc);
   };
   auto pre32 = [&](const float* rr_, float* zz_) {
-    if (learned) {
-      k_lpre_scale<D2, float><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
-      k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                o->d_pre_B, zz_,
-                                                sw32, nfc);
-      k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                o->d_pre_Linv, sw32, zz_, nfc);
-    } else {
-      k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, rr_, zz_, nfc);
+    if constexpr (kLearn) {
+      if (learned) {
+        k_lpre_scale<D2, float><<<gf, TL, 0, s>>>(o->d_pre_Linv, rr_, zz_, nfc);
+        k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                  o->d_pre_B, zz_, sw32, nfc);
+        k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                  o->d_pre_Linv, sw32, zz_, nfc);
+        return;
+      }
     }
+    k_precond<D2, float, float><<<gr, T, 0, s>>>(Minv32, rr_, zz_, nfc);
   };
-  k_bj_setup<D2, double><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv);
+  launch_bj_setup<D2, double>(H, mesh->d_diag, nfc, Minv, s);
   // ||b||
   S.dot(b, b, scal + 4);
   const double bb = S.read(scal + 4);
@@ -711,13 +771,15 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       const int od = old_slot(it), nw = 2 - od;
       const int np1 = launch_spmv_pap<D2>(mesh, H, p, Ap, part, s);
       k_sum_parts<<<1, kSumThreads, 0, s>>>(part, np1, scal + 1);
-      if (learned) {  // t -> z, s -> sw, then z
-        k_xr_lscale<D2, double><<<gfp, TL, 0, s>>>(x, r, p, Ap, o->d_pre_Linv, z, scal, od, nfc);
-        k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                   o->d_pre_B, z, sw, nfc);
-        k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                   o->d_pre_Linv, sw, z, nfc);
-        S.dot(r, z, scal + nw);
+      if (kLearn && learned) {  // t -> z, s -> sw, then z
+        if constexpr (kLearn) {
+          k_xr_lscale<D2, double><<<gfp, TL, 0, s>>>(x, r, p, Ap, o->d_pre_Linv, z, scal, od, nfc);
+          k_lpre_lower<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                     o->d_pre_B, z, sw, nfc);
+          k_lpre_upper<D2, double><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                     o->d_pre_Linv, sw, z, nfc);
+          S.dot(r, z, scal + nw);
+        }
       } else {
         k_xr_precond_rz<D2, double, double><<<gfp, TL, 0, s>>>(x, r, p, Ap, Minv, z, scal, od, nfc, part);
         k_sum_parts<<<1, kSumThreads, 0, s>>>(part, (int)gfp, scal + nw);
@@ -729,7 +791,7 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
   // ---- precision 1: FP64 refinement around an FP32-storage PCG
   const size_t nh = (size_t)mesh->nnzb * D2 * D2;
   k_convert<float><<<8192, T, 0, s>>>(H, H32, nh);
-  k_bj_setup<D2, float><<<(nfc + 63) / 64, 64, 0, s>>>(H, mesh->d_diag, nfc, Minv32);
+  launch_bj_setup<D2, float>(H, mesh->d_diag, nfc, Minv32, s);
   int total = 0;
   const double inner_rtol = 1e-4;
   for (int outer = 0; outer < 60; ++outer) {
@@ -762,13 +824,15 @@ hdg_status run_solve(const hdg_mesh* mesh, const double* H, const double* b, dou
       const int od = old_slot(it), nw = 2 - od;
       const int np1 = launch_spmv_pap<D2>(mesh, H32, p32, Ap32, part, s);
       k_sum_parts<<<1, kSumThreads, 0, s>>>(part, np1, scal + 1);
-      if (learned) {
-        k_xr_lscale<D2, float><<<gfp, TL, 0, s>>>(d32, r32, p32, Ap32, o->d_pre_Linv, z32, scal, od, nfc);
-        k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                  o->d_pre_B, z32, sw32, nfc);
-        k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
-                                                  o->d_pre_Linv, sw32, z32, nfc);
-        S.dot(r32, z32, scal + nw);
+      if (kLearn && learned) {
+        if constexpr (kLearn) {
+          k_xr_lscale<D2, float><<<gfp, TL, 0, s>>>(d32, r32, p32, Ap32, o->d_pre_Linv, z32, scal, od, nfc);
+          k_lpre_lower<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                    o->d_pre_B, z32, sw32, nfc);
+          k_lpre_upper<D2, float><<<gf, TL, 0, s>>>(mesh->d_row_ptr, mesh->d_diag, mesh->d_col_idx, o->d_pre_N,
+                                                    o->d_pre_Linv, sw32, z32, nfc);
+          S.dot(r32, z32, scal + nw);
+        }
       } else {
         k_xr_precond_rz<D2, float, float><<<gfp, TL, 0, s>>>(d32, r32, p32, Ap32, Minv32, z32, scal, od, nfc, part);
         k_sum_parts<<<1, kSumThreads, 0, s>>>(part, (int)gfp, scal + nw);
@@ -809,6 +873,8 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
     return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: bad options");
   if (opts->precond == 1 && (!opts->d_pre_N || !opts->d_pre_Linv))
     return set_error(HDG_ERR_INVALID_ARG, "hdg_solve: the learned preconditioner needs N and Linv");
+  if (opts->precond == 1 && disc->host.k > kMaxBatchDegree)
+    return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve: the learned preconditioner exists for degrees 0..4");
   if (!d_ws || ws_bytes < ws_size(mesh, disc->host.d2, opts->precision))
     return set_error(HDG_ERR_WORKSPACE, "hdg_solve: workspace too small");
   hipStream_t s = (hipStream_t)stream;
@@ -819,6 +885,8 @@ extern "C" hdg_status hdg_solve(const hdg_disc* disc, const hdg_mesh* mesh, cons
       case 2: return run_solve<dim2(2)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
       case 3: return run_solve<dim2(3)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
       case 4: return run_solve<dim2(4)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+      case 5: return run_solve<dim2(5)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
+      case 6: return run_solve<dim2(6)>(mesh, d_H, d_b, d_uhat, o, inf, d_ws, ws_bytes, s);
     }
     return set_error(HDG_ERR_UNSUPPORTED_DEGREE, "hdg_solve: unsupported degree");
   };

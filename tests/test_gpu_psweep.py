@@ -1,5 +1,5 @@
 """p-refinement on a fixed mesh through the GPU pipeline (Section 10, Table 4, eq 10.3):
-for k = 0..4 the errors of eq 10.1 computed from the library's q, u and uhat (condensation,
+for k = 0..6 the errors of eq 10.1 computed from the library's q, u and uhat (condensation,
 boundary data, PCG to 1e-13, reconstruction) equal the oracle's errors on the same mesh, so
 the library reproduces the oracle's p-convergence and its eq 10.3 ratios."""
 import math

@@ -36,11 +36,25 @@ def test_error_reporting_without_device(L):
     with pytest.raises(L.HdgError) as e:
         L.hdg_reference_table(2, "nope")
     assert e.value.name == "HDG_ERR_INVALID_ARG"
-    assert L.hdg_max_degree() >= 4
+    assert L.hdg_max_degree() == 6
+    with pytest.raises(L.HdgError) as e:
+        L.hdg_reference_table(7, "P")
+    assert e.value.name == "HDG_ERR_UNSUPPORTED_DEGREE"
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+def _dev(a, ref):
+    """max |a - ref| over the larger of 1 and max |ref|."""
+    return np.abs(a - ref).max() / max(1.0, np.abs(ref).max())
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5, 6])
 def test_tables_match_oracle(L, k):
+    """The library's long-double tables against the oracle's monomial-expansion basis.  The
+    oracle loses digits as the degree grows (its values at the points come from sums of
+    large monomial coefficients), so the bar is relative to the magnitude of the table, and ten
+    times wider at k = 5, 6, where the oracle's Gram defect |P^T W P - I| grows from 1.6e-14
+    (k = 4) to 2.4e-13 (k = 6) while the library's stays below 1.1e-14."""
+    sl = 10.0 if k >= 5 else 1.0
     n = k + 2
     vp, vw = OQ.tet_rule(n)
     tp, tw = OQ.tri_rule(n)
@@ -51,36 +65,36 @@ def test_tables_match_oracle(L, k):
     assert np.abs(T("tri_pts").reshape(-1, 2) - tp).max() < 1e-15
     assert np.abs(T("tri_w") - tw).max() < 1e-15
     P = OB.eval3(k, vp)
-    assert np.abs(T("P").reshape(-1, d3) - P).max() < 1e-12
+    assert _dev(T("P").reshape(-1, d3), P) < 1e-12 * sl
     G = OB.grad3(k, vp)
-    assert np.abs(T("Pgrad").reshape(3, -1, d3) - G).max() < 1e-11
+    assert _dev(T("Pgrad").reshape(3, -1, d3), G) < 1e-11 * sl
     D = OB.eval2(k, tp)
-    assert np.abs(T("D").reshape(-1, d2) - D).max() < 1e-13
+    assert _dev(T("D").reshape(-1, d2), D) < 1e-13 * sl
     # face traces (eq 4.4) at the points of eq 2.5
     s, t = tp[:, 0], tp[:, 1]
     fpts = [np.stack([s, t, 0 * s], 1), np.stack([s, 0 * s, t], 1), np.stack([0 * s, s, t], 1),
             np.stack([s, t, 1 - s - t], 1)]
     Pf = np.stack([OB.eval3(k, p) for p in fpts])
-    assert np.abs(T("Pface").reshape(4, -1, d3) - Pf).max() < 1e-12
+    assert _dev(T("Pface").reshape(4, -1, d3), Pf) < 1e-12 * sl
     # eq 3.7: Chat^h = (1/6) (w . P)^T P^h
     Ch = np.einsum("q,qi,hqj->hij", vw, P, G) / 6
-    assert np.abs(T("Chat").reshape(3, d3, d3) - Ch).max() < 1e-12
+    assert _dev(T("Chat").reshape(3, d3, d3), Ch) < 1e-12 * sl
     # eq 4.5: PP_l = (v . P^l)^T P^l
     PP = np.einsum("r,lri,lrj->lij", tw, Pf, Pf)
-    assert np.abs(T("PP").reshape(4, d3, d3) - PP).max() < 1e-12
+    assert _dev(T("PP").reshape(4, d3, d3), PP) < 1e-12 * sl
     # eq 4.10: DP_{mu,l} = (v . D^mu)^T P^l with D^mu_ri = D_i(F_mu(q_r)) (eq 2.2)
     Fm = [np.stack([s, t], 1), np.stack([t, s], 1), np.stack([t, 1 - s - t], 1), np.stack([s, 1 - s - t], 1),
           np.stack([1 - s - t, s], 1), np.stack([1 - s - t, t], 1)]
     Dmu = np.stack([OB.eval2(k, p) for p in Fm])
     DP = np.einsum("r,mri,lrj->mlij", tw, Dmu, Pf)
-    assert np.abs(T("DP").reshape(6, 4, d2, d3) - DP).max() < 1e-12
+    assert _dev(T("DP").reshape(6, 4, d2, d3), DP) < 1e-12 * sl
     # the HDG projection's inverses of the top-mode columns of each DP_{mu,l} (eq 9.13)
     Ainv = T("DPtopinv").reshape(6, 4, d2, d2)
     prod = np.einsum("mlij,mljk->mlik", Ainv, DP[:, :, :, d3 - d2:])
     assert np.abs(prod - np.eye(d2)).max() < 1e-10
     # postprocess tables
     G1 = OB.grad3(k + 1, vp)
-    assert np.abs(T("P1grad").reshape(3, -1, d3p) - G1).max() < 1e-10
+    assert _dev(T("P1grad").reshape(3, -1, d3p), G1) < 1e-12 * sl
     pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
     Sh = np.stack([np.einsum("q,qi,qj->ij", vw, G1[a], G1[b]) / 6 + (np.einsum("q,qi,qj->ij", vw, G1[b], G1[a]) / 6 if a != b else 0)
                    for a, b in pairs])

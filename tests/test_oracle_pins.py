@@ -34,7 +34,7 @@ def _const_problem(kappa=1.0, c=0.0, f=0.0, tau=1.0, uD=None):
 
 
 # ----------------------------------------------------------------------------- quadrature
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_tet_rule_moments(n):
     """eq 3.1 with weights summing to 1: 6 * int x^a y^b z^c = 6 a! b! c! / (a+b+c+3)!."""
     p, w = Q.tet_rule(n)
@@ -47,7 +47,7 @@ def test_tet_rule_moments(n):
                 assert abs(got - exact) < 1e-14
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_tri_rule_moments(n):
     """Section 4 face rule: 2 * int s^a t^b = 2 a! b! / (a+b+2)!."""
     p, w = Q.tri_rule(n)
@@ -65,17 +65,21 @@ def test_jacobi_coefficients_match_library(n, a):
     assert np.allclose(np.polynomial.polynomial.polyval(x, c), sps.eval_jacobi(n, a, 0.0, x), atol=1e-12, rtol=1e-12)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5, 6])
 def test_dubiner_orthonormal_hierarchical(k):
     """Orthonormal on the normalised measures (eq 3.1 weights), P_1 = D_1 = 1, and the first
-    C(j+3,3) (resp. C(j+2,2)) functions span P_j (hierarchical order, Section 3)."""
+    C(j+3,3) (resp. C(j+2,2)) functions span P_j (hierarchical order, Section 3).  The Gram
+    bar is 1e-13 up to k = 4 and 1e-12 at k = 5, 6: the values come from monomial expansions
+    whose coefficients grow with the degree (a wrong normalisation or a missing function
+    would still be off by O(1))."""
+    tol = 1e-13 if k <= 4 else 1e-12
     p, w = Q.tet_rule(k + 3)
     P = basis.eval3(k, p)
-    assert np.abs((P * w[:, None]).T @ P - np.eye(basis.dim3(k))).max() < 1e-13
+    assert np.abs((P * w[:, None]).T @ P - np.eye(basis.dim3(k))).max() < tol
     assert np.abs(P[:, 0] - 1).max() < 1e-15
     s, v = Q.tri_rule(k + 3)
     D = basis.eval2(k, s)
-    assert np.abs((D * v[:, None]).T @ D - np.eye(basis.dim2(k))).max() < 1e-13
+    assert np.abs((D * v[:, None]).T @ D - np.eye(basis.dim2(k))).max() < tol
     assert np.abs(D[:, 0] - 1).max() < 1e-15
     for j in range(k + 1):
         for polys, dim in ((basis.dubiner3(k), comb(j + 3, 3)), (basis.dubiner2(k), comb(j + 2, 2))):
@@ -298,13 +302,13 @@ def test_condensed_symmetric_and_global_spd(k):
 
 
 # ----------------------------------------------------------------------------- whole pipeline
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("n", [2, 3])
 def test_polynomial_reproduction(k, n):
     """Section 8, last paragraph: a polynomial solution of degree <= k with constant kappa
     is reproduced exactly (here with a variable c and mixed boundary conditions on a
     jittered mesh): u_h = u, q_h = q, uhat = u|_e, u* = u."""
-    if n == 3 and k == 4:
+    if n == 3 and k >= 4:
         pytest.skip("covered at n=2")
     m = kuhn_mesh(n, jitter=0.15, seed=10 + n, dirichlet_sides=("x0", "x1", "z0"), neumann_sides=("y0", "y1", "z1"))
     ex = _ex(m)
