@@ -656,8 +656,10 @@ typedef struct {
 
 /* Library-wide launch shape of the condensation of degree k, used by hdg_assemble_condense
  * and hdg_export_local and as the starting shape of new batches (defaults: k = 1..3
- * {4, 1, 1}, k = 4 {1, 1, 8}, k = 0 {2, 0, 1}).  Every shape gives the same results bit for
- * bit.  Not synchronised with calls running in other threads.  Errors: HDG_ERR_INVALID_ARG. */
+ * {4, 1, 1}, k = 4 {2, 1, 4}, k = 0 {2, 0, 1}, k = 5, 6 {1, 0, 4}; degrees 5 and 6 use
+ * workgroups_per_cu and xcd_remap only, and their workspace size follows workgroups_per_cu).
+ * Every shape gives the same results bit for bit.  Not synchronised with calls running in
+ * other threads.  Errors: HDG_ERR_INVALID_ARG. */
 hdg_status hdg_set_launch_config(int k, const hdg_tile_config* cfg);
 hdg_status hdg_get_launch_config(int k, hdg_tile_config* cfg);
 

@@ -57,7 +57,7 @@ hdg_status hdg_set_kernel_timer(const char* kernel, void* ev_start, void* ev_sto
 // Launch shapes of the single-mesh condensation, per degree (persistent grids; the tile
 // kernels of k = 1..3 run four elements per wavefront, so waves_per_element is 1).
 // Degrees 5 and 6 use workgroups_per_cu and xcd_remap only (four wavefronts per element).
-static hdg_tile_config g_launch[kMaxDegree + 1] = {{2, 0, 1}, {4, 1, 1}, {4, 1, 1}, {4, 1, 1}, {1, 1, 8},
+static hdg_tile_config g_launch[kMaxDegree + 1] = {{2, 0, 1}, {4, 1, 1}, {4, 1, 1}, {4, 1, 1}, {2, 1, 4},
                                                    {1, 0, 4}, {1, 0, 4}};
 
 hdg_status hdg_set_launch_config(int k, const hdg_tile_config* cfg) {

@@ -139,17 +139,22 @@ struct ElemLayout {
   static constexpr int PLD = LD, NQP = (NQD + 3) / 4 * 4;  // the padded basis table has rows of LD
   static constexpr int TT = LD / 4, TM = M / 4;             // tiles along D3 and along the M trace unknowns
   static constexpr int NCOL = 3 * D3 + M;                    // right-hand sides C^T | DP^T
-  static constexpr int BIG_SOLVE = (NCOL + M + 1) * LD;
-  static constexpr int BIG_STAGE = lds_stage_bytes<NQP * PLD>() / 8;
+  // W^T | Z^T; V^T = (Ls^{-1} [B | f])^T later overwrites the rows of W^T, dead by then
+  static constexpr int BIG_SOLVE = NCOL * LD;
+  // the basis table is staged in two halves of the points
+  static constexpr int NQH = NQP / 2;
+  static constexpr int BIG_STAGE = lds_stage_bytes<NQH * PLD>() / 8;
   static constexpr int BIG = BIG_SOLVE > BIG_STAGE ? BIG_SOLVE : BIG_STAGE;
-  static_assert(M % 4 == 0 && NQD % 4 == 0, "whole tiles of trace unknowns and of points");
+  static_assert(M % 4 == 0 && NQD % 8 == 0 && NQP == NQD, "whole tiles of trace unknowns and of points");
+  static_assert(M + 1 <= 3 * D3, "V^T fits in the rows of W^T");
 };
 
 template <int K>
 struct CondenseSmem {
   using Ly = ElemLayout<K>;
-  // the basis table at the points while the Gram matrices are summed, then one row per
-  // solved column: W_s^T (3 D3 rows), Z^T (M rows), V^T = (Ls^{-1} [B | f])^T (M + 1 rows)
+  // half of the basis table at the points while the Gram matrices are summed, then one row
+  // per solved column: W_s^T (3 D3 rows) and Z^T (M rows), then V^T = (Ls^{-1} [B | f])^T
+  // (M + 1 rows) in place of W^T
   double big[Ly::BIG];
   double wkc[2 * Ly::NQD];  // (|K| w_q / kappa_q, |K| w_q c_q)
   double wf[Ly::NQD];       // |K| w_q f_q
@@ -186,9 +191,10 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   if (E < 0 || E >= mesh.nelt) return;  // uniform across the block
   double* Wt = sm.big;
   double* Zt = sm.big + 3 * D3 * LD;
-  double* Vt = sm.big + NCOL * LD;
-  // ---- the basis table goes to LDS while the coefficients are formed
-  lds_stage_wg<Ly::NQP * PLD, NW>(tb.Pt, sm.big, wave, lane);
+  double* Vt = sm.big;  // over W^T, once B is formed
+  constexpr int NQH = Ly::NQH;
+  // ---- the first half of the basis table goes to LDS while the coefficients are formed
+  lds_stage_wg<NQH * PLD, NW>(tb.Pt, sm.big, wave, lane);
   {
   ElemGeom g;
   load_geometry(E, mesh, tau, g);
@@ -249,46 +255,55 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
   // ---- Gram matrices M = P^T diag(|K| w / kappa) P and Mc = P^T diag(|K| w c) P (eq 3.5,
   // eq 4.5) on the FP64 matrix cores: job j is upper tile j of both, one job per block,
   // four per wavefront instruction, four points per step; both weights come in one 16-byte
-  // read and the basis operands serve both products
-  for (int quad = wave; quad < (NUT + 3) / 4; quad += NW) {
-    const int job = min(4 * quad + blk, NUT - 1);
-    int ti, tj;
-    upper_pair(job, TT, ti, tj);
-    const double* px = sm.big + tr * PLD + 4 * ti + tc;
-    const double* py = sm.big + tr * PLD + 4 * tj + tc;
-    const double* pw = sm.wkc + 2 * tr;
-    double am[2] = {0, 0}, ac[2] = {0, 0};  // two chains per product
-#pragma unroll 6
-    for (int q0 = 0; q0 < NQD; q0 += 4) {
-      const int ch = (q0 / 4) & 1;
-      const double2 wq = *reinterpret_cast<const double2*>(pw + 2 * q0);
-      const double x = px[q0 * PLD], y = py[q0 * PLD];
-      am[ch] = mfma4(x, wq.x * y, am[ch]);
-      ac[ch] = mfma4(x, wq.y * y, ac[ch]);
+  // read and the basis operands serve both products.  The points come in two staged
+  // halves; the lane of a job adds the second half's sums to the first's in LDS.  The load
+  // vector f is summed beside them.
+  const int fi = (NW > 1 ? NT - 65 : NT - 1) - t;  // the thread of entry fi of f
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1) {
+      __syncthreads();  // every read of the first half is done
+      lds_stage_wg<NQH * PLD, NW>(tb.Pt + NQH * PLD, sm.big, wave, lane);
+      lds_stage_wait();
+      __syncthreads();
     }
-    if (4 * quad + blk < NUT) {
-      const int o = (4 * ti + tr) * LD + 4 * tj + tc;
-      sm.Lt[o] = am[0] + am[1];
-      sm.St[o] = ac[0] + ac[1];
+    for (int quad = wave; quad < (NUT + 3) / 4; quad += NW) {
+      const int job = min(4 * quad + blk, NUT - 1);
+      int ti, tj;
+      upper_pair(job, TT, ti, tj);
+      const double* px = sm.big + tr * PLD + 4 * ti + tc;
+      const double* py = sm.big + tr * PLD + 4 * tj + tc;
+      const double* pw = sm.wkc + 2 * (h * NQH + tr);
+      double am[2] = {0, 0}, ac[2] = {0, 0};  // two chains per product
+#pragma unroll 6
+      for (int q0 = 0; q0 < NQH; q0 += 4) {
+        const int ch = (q0 / 4) & 1;
+        const double2 wq = *reinterpret_cast<const double2*>(pw + 2 * q0);
+        const double x = px[q0 * PLD], y = py[q0 * PLD];
+        am[ch] = mfma4(x, wq.x * y, am[ch]);
+        ac[ch] = mfma4(x, wq.y * y, ac[ch]);
+      }
+      if (4 * quad + blk < NUT) {
+        const int o = (4 * ti + tr) * LD + 4 * tj + tc;
+        const double vm = am[0] + am[1], vc = ac[0] + ac[1];
+        sm.Lt[o] = h ? sm.Lt[o] + vm : vm;
+        sm.St[o] = h ? sm.St[o] + vc : vc;
+      }
+    }
+    if (fi >= 0 && fi < LD) {
+      double sf = 0;
+      if (fi < D3)
+        for (int q = 0; q < NQH; ++q) sf = fma(sm.wf[h * NQH + q], sm.big[q * PLD + fi], sf);
+      sm.fv[fi] = h ? sm.fv[fi] + sf : sf;
     }
   }
   __syncthreads();
   double* fa = factors ? factors + (size_t)E * (D3 * (D3 + 1) + D3) : nullptr;
-  // ---- L (one wavefront) while the columns arrive; the load vector f from the staged table
+  // ---- L (one wavefront); the load vector goes to the factor store
   if (wave == NW - 1) {
     const double* const parts[1] = {sm.Lt};
     wave_cholesky<D3, LD, 1>(parts, sm.Lt, sm.idl, lane);
   }
-  {
-    const int fi = (NW > 1 ? NT - 65 : NT - 1) - t;
-    if (fi >= 0 && fi < LD) {
-      double s = 0;
-      if (fi < D3)
-        for (int q = 0; q < NQD; ++q) s = fma(sm.wf[q], sm.big[q * PLD + fi], s);
-      sm.fv[fi] = s;
-      if (fa && fi < D3) fa[D3 * (D3 + 1) + fi] = s;
-    }
-  }
+  if (fa && fi >= 0 && fi < D3) fa[D3 * (D3 + 1) + fi] = sm.fv[fi];
   __syncthreads();
   // ---- W_s = L^{-1} C_s^T, Z = L^{-1} DP^T (eq 5.2), one column per thread
   for (int c = t; c < NCOL; c += NT) {
@@ -333,12 +348,17 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
     const double* const parts[1] = {sm.St};
     wave_cholesky<D3, LD, 1>(parts, sm.St, sm.ids, lane);
   }
+  // B^T by tiles on the matrix cores: B[i][c] = T_l DP_l[c][i] + sum_s sum_r W_s[r][i]
+  // (n_{l s} Z[r][c]), l the face of column c; the normal rides on the Z operand, whose
+  // element (r, tc) belongs to column 4 tcb + tc of the tile.  The tiles stay in registers
+  // until every wavefront is done with W^T, whose rows then receive them.
+  constexpr int NWB = NW == 1 ? 1 : NW - 1, NJ = TT * TM, NBQ = ((NJ + 3) / 4 + NWB - 1) / NWB;
+  double bres[NBQ];
   if (NW == 1 || wave < NW - 1) {
-    // B^T by tiles on the matrix cores: B[i][c] = T_l DP_l[c][i] + sum_s sum_r W_s[r][i]
-    // (n_{l s} Z[r][c]), l the face of column c; the normal rides on the Z operand, whose
-    // element (r, tc) belongs to column 4 tcb + tc of the tile
-    constexpr int NWB = NW == 1 ? 1 : NW - 1, NJ = TT * TM;
-    for (int quad = wave; quad < (NJ + 3) / 4; quad += NWB) {
+#pragma unroll
+    for (int u = 0; u < NBQ; ++u) {
+      const int quad = wave + u * NWB;
+      if (quad >= (NJ + 3) / 4) break;  // uniform across the wavefront
       const int job = min(4 * quad + blk, NJ - 1), ti = job % TT, tcb = job / TT;
       const int i = 4 * ti + tr, c = 4 * tcb + tc, l = c / D2;
       // the table term is added last, so its load overlaps the products
@@ -352,7 +372,18 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
 #pragma unroll
         for (int r0 = 0; r0 < LD; r0 += 4) acc[sd] = mfma4(px[r0], ns * py[r0], acc[sd]);
       }
-      if (4 * quad + blk < NJ && i < D3) Vt[c * LD + i] = fma(sm.gT[l], dp, (acc[0] + acc[1]) + acc[2]);
+      bres[u] = fma(sm.gT[l], dp, (acc[0] + acc[1]) + acc[2]);
+    }
+  }
+  __syncthreads();
+  if (NW == 1 || wave < NW - 1) {
+#pragma unroll
+    for (int u = 0; u < NBQ; ++u) {
+      const int quad = wave + u * NWB;
+      if (quad >= (NJ + 3) / 4) break;
+      const int job = 4 * quad + blk, ti = job % TT, tcb = job / TT;
+      const int i = 4 * ti + tr, c = 4 * tcb + tc;
+      if (job < NJ && i < D3) Vt[c * LD + i] = bres[u];
     }
   }
   __syncthreads();
@@ -435,7 +466,7 @@ __device__ __forceinline__ void condense_element(const hdg_mesh& mesh, const Tab
 // EXPORT selects the debugging form (listed elements, C^K and Cf^K written out instead of
 // scattered); the scatter form is compiled with those pointers known to be null.
 template <int K, int NT, bool EXPORT>
-__global__ void __launch_bounds__(NT) k_condense(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+__global__ void __launch_bounds__(NT, NT == 256 ? 2 : 1) k_condense(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                  const double* __restrict__ cco, const double* __restrict__ fco,
                                                  const double* __restrict__ tau, double* __restrict__ H,
                                                  double* __restrict__ F, double* __restrict__ factors,
@@ -556,7 +587,7 @@ __global__ void __launch_bounds__(256) k_batch_condense_k0(const BatchItem* __re
 
 // Persistent batched form: work unit u is element u - unit_begin of its mesh.
 template <int K, int NT>
-__global__ void __launch_bounds__(NT) k_batch_condense(const BatchItem* __restrict__ items, int nitems, int total_units,
+__global__ void __launch_bounds__(NT, NT == 256 ? 2 : 1) k_batch_condense(const BatchItem* __restrict__ items, int nitems, int total_units,
                                                        Tables tb, int xcd_remap) {
   for (int u = batch_block(xcd_remap); u < total_units; u += gridDim.x) {
     const BatchItem* it = items + batch_find(items, nitems, u);
@@ -601,7 +632,7 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
     }
     HDG_CHECK_LAUNCH("k_condense_k0");
     return HDG_OK;
-  }
+  } else {
   const hdg_tile_config lc = launch_config(K);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(n, (int64_t)lc.workgroups_per_cu * device_cu_count()));
   const int rm = lc.xcd_remap;
@@ -619,6 +650,7 @@ hdg_status run_condense(const hdg_disc* disc, const hdg_mesh* mesh, const double
   }
   HDG_CHECK_LAUNCH("k_condense");
   return HDG_OK;
+  }
 }
 
 }  // namespace
