@@ -23,14 +23,6 @@
 namespace hdg {
 namespace {
 
-// Value of lane l (uniform) of v, for the whole wavefront.
-__device__ __forceinline__ double lane_bcast(double v, int l) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __hiloint2double(hi, lo);
-}
-
 // Upper pair (i <= j) of an n x n matrix from its index p in the row-major order of the
 // upper triangle (counted from the end, kk = r (r + 1) / 2 + s with r = n - 1 - i).
 __device__ __forceinline__ void upper_pair(int p, int n, int& i, int& j) {
@@ -40,57 +32,6 @@ __device__ __forceinline__ void upper_pair(int p, int n, int& i, int& j) {
   while ((r + 1) * (r + 2) / 2 <= kk) ++r;
   i = n - 1 - r;
   j = n - 1 - (kk - r * (r + 1) / 2);
-}
-
-// Cholesky factor (eq 5.1, eq 5.4) of the N x N SPD matrix whose upper triangle is
-// A[0] + ... + A[NP-1] (row-major, leading dimension LD; entry (i, k) kept at
-// [min(i, k)][max(i, k)]), by one wavefront: lane i holds row i in registers; pass j
-// broadcasts column j lane by lane (v_readlane), updates the trailing rows with it while
-// still unscaled and then scales it; column j + 1 is updated first, so the next pivot's
-// reciprocal square root overlaps the rest of the pass.
-// Writes L^T to Lt (Lt[k][i] = L[i][k] for k <= i) and the reciprocal diagonal to idg.
-// Lt may alias A[0]: every lane has read its row before any lane writes.
-template <int N, int LD, int NP>
-__device__ __forceinline__ void wave_cholesky(const double* const (&A)[NP], double* Lt, double* idg, int lane) {
-  const int i = min(lane, N - 1);
-  double a[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int o = k < i ? k * LD + i : i * LD + k;
-    double s = A[0][o];
-#pragma unroll
-    for (int p = 1; p < NP; ++p) s += A[p][o];
-    a[k] = s;
-    if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
-  }
-  double myid = 0;
-  double piv = lane_bcast(a[0], 0), id = pivot_rsqrt(piv);
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const double t = a[j] * (id * id);
-    double pn = 1.0, idn = 1.0;
-    if (j + 1 < N) {  // column j + 1 first, so the next pivot's square root overlaps this pass
-      a[j + 1] = fma(-t, lane_bcast(a[j], j + 1), a[j + 1]);
-      pn = lane_bcast(a[j + 1], j + 1);
-      idn = pivot_rsqrt(pn);
-    }
-#pragma unroll
-    for (int k = j + 2; k < N; ++k) {
-      a[k] = fma(-t, lane_bcast(a[j], k), a[k]);
-      if ((k - j) % 8 == 0) __builtin_amdgcn_sched_barrier(0);  // bounds the broadcasts in flight
-    }
-    a[j] = lane == j ? piv * id : a[j] * id;
-    if (lane == j) myid = id;
-    piv = pn;
-    id = idn;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  if (lane < N) {
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-      if (k <= lane) Lt[k * LD + lane] = a[k];
-    idg[lane] = myid;
-  }
 }
 
 // x <- L^{-1} x for one right-hand side in registers, L given by Lt = L^T (leading

@@ -12,11 +12,17 @@
 // the two d3 x d3 factors, the point weights and a chunk of the basis table in LDS
 // (149 KB at k = 6, 74 KB at k = 5), and the solved blocks in its own slice of a caller
 // workspace (global memory, resident in the L2 and last-level caches while the element is
-// worked on).  The Gram sums stream the basis table through LDS in chunks of points; the
-// factorisations are right-looking on the upper triangle in LDS; every triangular solve
-// takes one right-hand side per thread in registers; the products S, B and C^K are 4 x 4
-// register tiles per thread reading the workspace in 16-byte pairs.
+// worked on).  Phases:
+//   Gram sums: the basis table streamed through LDS in chunks of points, one upper 4 x 4
+//     tile of M and Mc per thread;
+//   factorisations: the leading 64 rows by one wavefront with its rows in registers, the
+//     rest (k = 6) by a block step (U12 = L11^{-1} A12, A22 -= U12^T U12, factor A22);
+//   triangular solves: one right-hand side per thread in registers;
+//   products S, B and C^K: their operands (W_s; U_l = sum_s n_{l s} W_s with Z_l; the Z and
+//     V blocks of a face pair) staged in LDS over the factors once these are used up, 4 x 4
+//     (S, B) or 2 x 2 (C^K) register tiles per thread.
 #include "device_common.h"
+#include "tile.h"
 
 namespace hdg {
 namespace {
@@ -32,18 +38,25 @@ struct BigDims {
   static constexpr int SLICE = D3 * NCOL + D3 * NV;  // workspace doubles per workgroup
   static constexpr int QC = 32;            // points per staged chunk of the basis table
   static constexpr int NTRI = D3 * (D3 + 1) / 2;
-  static constexpr int NPAIR = (NTRI + kBigThreads - 1) / kBigThreads;  // Gram pairs per thread
   static_assert(D3 % 4 == 0 && M % 4 == 0, "whole 4 x 4 tiles");
   static_assert(NCOL % 2 == 0 && (3 * D3) % 2 == 0, "16-byte pairs of the solved blocks");
 };
 
+// LDS of one element.  R holds, in order: U (M, then U = L^T), a chunk of the basis table,
+// the point weights |K| w_q / kappa_q, |K| w_q c_q, |K| w_q f_q (NQDP each), and Us (Mc, then
+// S, then Us = Ls^T).  Once L is used up, the space before Us stages the operands of the
+// products S and B; once V is formed, the whole of R stages those of C^K.
 template <int K>
 struct BigSmem {
   using B = BigDims<K>;
-  double U[B::D3 * B::D3];   // M (upper triangle), then U = L^T
-  double Us[B::D3 * B::D3];  // Mc, then S, then Us = Ls^T
-  double Pc[B::QC * B::D3];  // a chunk of the basis table at the points
-  double wk[B::NQD], wc[B::NQD], wf[B::NQD];  // |K| w_q / kappa_q, |K| w_q c_q, |K| w_q f_q
+  static constexpr int NQDP = B::NQD + (B::NQD & 1);
+  static constexpr int OFF_PC = B::D3 * B::D3, OFF_W = OFF_PC + B::QC * B::D3, OFF_US = OFF_W + 3 * NQDP;
+  static constexpr int LEN = OFF_US + B::D3 * B::D3;
+  static constexpr int ZLD = (B::D2 + 3) / 4 * 4;  // face columns padded to whole tiles
+  static_assert(OFF_US % 2 == 0, "16-byte rows of Us");
+  static_assert(B::D3 * B::D3 + B::D3 * ZLD <= OFF_US, "U_l and Z_l fit before Us");
+  static_assert(4 * B::D3 * ZLD <= LEN, "Z_l, Z_m, V_l, V_m fit in R");
+  double R[LEN];
   double fv[B::D3], idl[B::D3], ids[B::D3];
   double nn[4][4];
   int slot[16], fbe[4];
@@ -59,16 +72,49 @@ __device__ __forceinline__ void lower_pair(int p, int& i, int& j) {
   j = p - r * (r + 1) / 2;
 }
 
-// In-place Cholesky factorisation A = U^T U of the N x N SPD matrix held in the upper
-// triangle of A (row-major, entries (i, j) with i <= j), by all threads of the workgroup;
-// idg receives 1 / U_kk.  Step k updates the trailing upper triangle with the unscaled row k
-// (divided by its pivot) and scales row k - 1, which no thread reads any more, so each step
-// needs one barrier.
+// x <- U^{-T} x (forward substitution with L = U^T, rows of U with leading dimension LD) for
+// one right-hand side in registers; every thread reads the same LDS words.
+template <int N, int LD = N>
+__device__ __forceinline__ void reg_forward(const double* U, const double* idg, double (&x)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double xk = x[k] * idg[k];
+    x[k] = xk;
+#pragma unroll
+    for (int r = k + 1; r < N; ++r) x[r] = fma(-U[k * LD + r], xk, x[r]);
+    __builtin_amdgcn_sched_barrier(0);  // one row of LDS reads in flight at a time
+  }
+}
+
+// Copy of n items by the workgroup, eight global loads in flight per thread before their
+// LDS stores: ld(i) reads item i, st(i, v) stores it.
+template <int NT, class Ld, class St>
+__device__ __forceinline__ void stage_batched(int n, int t, Ld ld, St st) {
+  for (int b = t; b < n; b += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = b + u * NT;
+      v[u] = i < n ? ld(i) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = b + u * NT;
+      if (i < n) st(i, v[u]);
+    }
+  }
+}
+
+// The same factorisation right-looking over the whole workgroup: step k updates the
+// trailing upper triangle (its entries spread over all threads) with the unscaled row k
+// divided by its pivot and scales row k - 1, which no thread reads any more, so each step
+// needs one barrier.  Used where it measured faster (the degree-6 stiffness matrix of the
+// degree-5 postprocess, which runs at two workgroups per CU).
 template <int N>
-__device__ inline void lds_chol_upper(double* A, double* idg) {
+__device__ inline void lds_chol_rows(double* A, double* idg) {
   const int t = threadIdx.x, nt = blockDim.x;
   for (int k = 0; k < N; ++k) {
-    __syncthreads();  // step k - 1's trailing update and idg[k - 1] are visible
+    __syncthreads();
     if (k > 0) {
       const int kp = k - 1;
       const double is = idg[kp];
@@ -88,17 +134,47 @@ __device__ inline void lds_chol_upper(double* A, double* idg) {
   __syncthreads();
 }
 
-// x <- U^{-T} x (forward substitution with L = U^T) for one right-hand side in registers;
-// every thread reads the same LDS words.
+// In-place Cholesky factorisation A = U^T U of the N x N SPD matrix held in the upper
+// triangle of A (row-major, entries (i, j) with i <= j), by the workgroup; idg receives
+// 1 / U_kk.  The leading block of up to 64 rows is factored by one wavefront with its rows in
+// registers (wave_cholesky); for N > 64 the trailing rows follow by blocks:
+// U12 = L11^{-1} A12 (one column per thread), A22 -= U12^T U12, and the one-wavefront
+// factorisation of A22.
 template <int N>
-__device__ __forceinline__ void reg_forward(const double* U, const double* idg, double (&x)[N]) {
+__device__ inline void lds_chol_upper(double* A, double* idg) {
+  constexpr int N1 = N <= 64 ? N : 64, N2 = N - N1;
+  static_assert(N2 <= 64, "two diagonal blocks");
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  __syncthreads();
+  if (wave == 0) {
+    const double* const parts[1] = {A};
+    wave_cholesky<N1, N, 1>(parts, A, idg, lane);
+  }
+  __syncthreads();
+  if constexpr (N2 > 0) {
+    if (t < N2) {
+      const int i = N1 + t;
+      double x[N1];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const double xk = x[k] * idg[k];
-    x[k] = xk;
+      for (int r = 0; r < N1; ++r) x[r] = A[r * N + i];
+      reg_forward<N1, N>(A, idg, x);
 #pragma unroll
-    for (int r = k + 1; r < N; ++r) x[r] = fma(-U[k * N + r], xk, x[r]);
-    __builtin_amdgcn_sched_barrier(0);  // one row of LDS reads in flight at a time
+      for (int r = 0; r < N1; ++r) A[r * N + i] = x[r];
+    }
+    __syncthreads();
+    for (int p = t; p < N2 * N2; p += blockDim.x) {
+      const int i = N1 + p / N2, j = N1 + p % N2;
+      if (j < i) continue;
+      double sacc = 0;
+      for (int r = 0; r < N1; ++r) sacc = fma(A[r * N + i], A[r * N + j], sacc);
+      A[i * N + j] -= sacc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const double* const parts[1] = {A + N1 * N + N1};
+      wave_cholesky<N2, N, 1>(parts, A + N1 * N + N1, idg + N1, lane);
+    }
+    __syncthreads();
   }
 }
 
@@ -113,21 +189,21 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
                                                               double* __restrict__ ws, int xcd_remap) {
   using B = BigDims<K>;
   constexpr int D3 = B::D3, D2 = B::D2, M = B::M, NQD = B::NQD, NCOL = B::NCOL, NV = B::NV, QC = B::QC;
-  constexpr int NTRI = B::NTRI, NPAIR = B::NPAIR, NT = kBigThreads;
-  constexpr int TT = D3 / 4, TM = M / 4;
+  constexpr int NTRI = B::NTRI, NT = kBigThreads;
+  constexpr int TT = D3 / 4, ZLD = BigSmem<K>::ZLD, NQDP = BigSmem<K>::NQDP;
+  static_assert(TT * (TT + 1) / 2 <= NT && TT * (ZLD / 4) <= NT && (ZLD / 2) * (ZLD / 2) <= NT,
+                "one product tile per thread");
   __shared__ __align__(16) BigSmem<K> sm;
   __shared__ ElemGeom sg;
+  double* R = sm.R;
+  double* U = R;
+  double* Pc = R + BigSmem<K>::OFF_PC;
+  double* wk = R + BigSmem<K>::OFF_W;
+  double* wc = wk + NQDP;
+  double* wf = wc + NQDP;
+  double* Us = R + BigSmem<K>::OFF_US;
   double* X = ws + (size_t)blockIdx.x * B::SLICE;  // [D3][NCOL]: W_0 | W_1 | W_2 | Z
   double* Vb = X + (size_t)D3 * NCOL;              // [D3][NV]:   B | f, then V
-  // this thread's Gram pairs (fixed for the whole launch)
-  int pi[NPAIR], pj[NPAIR];
-#pragma unroll
-  for (int u = 0; u < NPAIR; ++u) {
-    const int p = (int)threadIdx.x + u * NT;
-    pi[u] = 0;
-    pj[u] = 0;
-    if (p < NTRI) lower_pair(p, pi[u], pj[u]);
-  }
   for (int w = batch_block(xcd_remap); w < nwork; w += gridDim.x) {
     // the thread index passes through an opaque move, so the per-thread addresses derived
     // from it are formed where they are used, not hoisted out of the element loop (where
@@ -143,9 +219,9 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
     __syncthreads();
     for (int q = t; q < NQD; q += NT) {
       const double wq = sg.vol * tb.vol_w[q];
-      sm.wk[q] = wq / kappa[(size_t)E * NQD + q];
-      sm.wc[q] = wq * cco[(size_t)E * NQD + q];
-      sm.wf[q] = wq * fco[(size_t)E * NQD + q];
+      wk[q] = wq / kappa[(size_t)E * NQD + q];
+      wc[q] = wq * cco[(size_t)E * NQD + q];
+      wf[q] = wq * fco[(size_t)E * NQD + q];
     }
     if (t < 16) {
       const int l = t / 4, m = t % 4;
@@ -153,47 +229,62 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
     }
     // ---- M = P^T diag(|K| w / kappa) P, Mc = P^T diag(|K| w c) P, f = P^T (|K| w f) (eq 3.5,
     // eq 4.5), the basis table streamed through LDS in chunks of QC points
-    double am[NPAIR], ac[NPAIR], ff = 0;
-#pragma unroll
-    for (int u = 0; u < NPAIR; ++u) am[u] = ac[u] = 0;
+    // one upper 4 x 4 tile (gi <= gj) of both matrices per thread
+    const bool gjob = t < TT * (TT + 1) / 2;
+    int gi = 0, gj = 0;
+    if (gjob) lower_pair(t, gj, gi);
+    double am[4][4] = {}, ac[4][4] = {}, ff = 0;
     for (int q0 = 0; q0 < NQD; q0 += QC) {
       const int nq = min(QC, NQD - q0);
       __syncthreads();
-      for (int idx = t; idx < nq * D3; idx += NT) sm.Pc[idx] = tb.P[(size_t)q0 * D3 + idx];
+      const double* pchunk = tb.P + (size_t)q0 * D3;
+      stage_batched<NT>(nq * D3, t, [&](int i) { return pchunk[i]; }, [&](int i, double v) { Pc[i] = v; });
       __syncthreads();
+      if (gjob) {
+        for (int q = 0; q < nq; ++q) {
+          const double* pq = Pc + q * D3;
+          const double2 a01 = *reinterpret_cast<const double2*>(pq + 4 * gi);
+          const double2 a23 = *reinterpret_cast<const double2*>(pq + 4 * gi + 2);
+          const double2 b01 = *reinterpret_cast<const double2*>(pq + 4 * gj);
+          const double2 b23 = *reinterpret_cast<const double2*>(pq + 4 * gj + 2);
+          const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+          const double wkq = wk[q0 + q], wcq = wc[q0 + q];
 #pragma unroll
-      for (int u = 0; u < NPAIR; ++u) {
-        if (t + u * NT < NTRI) {
-          const double* pa = sm.Pc + pi[u];
-          const double* pb = sm.Pc + pj[u];
-          double sk = am[u], sc = ac[u];
-          for (int q = 0; q < nq; ++q) {
-            const double pp = pa[q * D3] * pb[q * D3];
-            sk = fma(sm.wk[q0 + q], pp, sk);
-            sc = fma(sm.wc[q0 + q], pp, sc);
+          for (int a = 0; a < 4; ++a) {
+            const double ka = wkq * av[a], ca = wcq * av[a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              am[a][b] = fma(ka, bv[b], am[a][b]);
+              ac[a][b] = fma(ca, bv[b], ac[a][b]);
+            }
           }
-          am[u] = sk;
-          ac[u] = sc;
         }
       }
       if (t < D3)
-        for (int q = 0; q < nq; ++q) ff = fma(sm.wf[q0 + q], sm.Pc[q * D3 + t], ff);
+        for (int q = 0; q < nq; ++q) ff = fma(wf[q0 + q], Pc[q * D3 + t], ff);
     }
-    // entry (i, j), i >= j, goes to the upper position (j, i)
+    if (gjob) {
 #pragma unroll
-    for (int u = 0; u < NPAIR; ++u)
-      if (t + u * NT < NTRI) {
-        sm.U[pj[u] * D3 + pi[u]] = am[u];
-        sm.Us[pj[u] * D3 + pi[u]] = ac[u];
-      }
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = 4 * gi + a, j = 4 * gj + b;
+          if (i <= j) {
+            U[i * D3 + j] = am[a][b];
+            Us[i * D3 + j] = ac[a][b];
+          }
+        }
+    }
     if (t < D3) sm.fv[t] = ff;
     // ---- L (eq 5.1), stored packed for the reconstruction
-    lds_chol_upper<D3>(sm.U, sm.idl);
+    lds_chol_upper<D3>(U, sm.idl);
     double* fa = (!EXPORT && factors) ? factors + (size_t)E * (D3 * (D3 + 1) + D3) : nullptr;
     if (fa) {
-#pragma unroll
-      for (int u = 0; u < NPAIR; ++u)
-        if (t + u * NT < NTRI) fa[t + u * NT] = sm.U[pj[u] * D3 + pi[u]];  // L[i][j] = U[j][i]
+      for (int p = t; p < NTRI; p += NT) {
+        int i, j;
+        lower_pair(p, i, j);
+        fa[p] = U[j * D3 + i];  // L[i][j] = U[j][i]
+      }
       if (t < D3) fa[D3 * (D3 + 1) + t] = sm.fv[t];
     }
     // ---- W_s = L^{-1} C_s^T and Z_l = L^{-1} DP_l^T (eq 5.2): column c < 3 D3 is (s, i),
@@ -213,86 +304,111 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
 #pragma unroll
         for (int r = 0; r < D3; ++r) x[r] = dp[r];
       }
-      reg_forward<D3>(sm.U, sm.idl, x);
+      reg_forward<D3>(U, sm.idl, x);
 #pragma unroll
       for (int r = 0; r < D3; ++r) X[(size_t)r * NCOL + c] = x[r];
     }
     __syncthreads();
-    // ---- S = Mc + sum_l T_l PP_l + sum_s W_s^T W_s (eq 5.3) on the upper 4 x 4 tiles
-    for (int job = t; job < TT * (TT + 1) / 2; job += NT) {
-      int ti, tj;  // ti <= tj
-      lower_pair(job, tj, ti);
+    // ---- S = Mc + sum_l T_l PP_l + sum_s W_s^T W_s (eq 5.3) on the upper 4 x 4 tiles (at
+    // most one per thread), each W_s staged in LDS over L, which is no longer needed
+    {
+      const bool job = t < TT * (TT + 1) / 2;
+      int ti = 0, tj = 0;  // ti <= tj
+      if (job) lower_pair(t, tj, ti);
       double acc[4][4] = {};
       for (int s = 0; s < 3; ++s) {
-        const double* xi = X + s * D3 + 4 * ti;
-        const double* xj = X + s * D3 + 4 * tj;
+        __syncthreads();
+        for (int idx = t; idx < D3 * D3 / 2; idx += NT) {
+          const int r = 2 * idx / D3, i = 2 * idx % D3;
+          *reinterpret_cast<double2*>(R + r * D3 + i) =
+              *reinterpret_cast<const double2*>(X + (size_t)r * NCOL + s * D3 + i);
+        }
+        __syncthreads();
+        if (job) {
+#pragma unroll 4
+          for (int r = 0; r < D3; ++r) {
+            const double2 a01 = *reinterpret_cast<const double2*>(R + r * D3 + 4 * ti);
+            const double2 a23 = *reinterpret_cast<const double2*>(R + r * D3 + 4 * ti + 2);
+            const double2 b01 = *reinterpret_cast<const double2*>(R + r * D3 + 4 * tj);
+            const double2 b23 = *reinterpret_cast<const double2*>(R + r * D3 + 4 * tj + 2);
+            const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+          }
+        }
+      }
+      if (job) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int i = 4 * ti + a, j = 4 * tj + b;
+            if (i > j) continue;
+            double v = Us[i * D3 + j] + acc[a][b];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) v = fma(sg.T[l], tb.PP[((size_t)l * D3 + i) * D3 + j], v);
+            Us[i * D3 + j] = v;
+          }
+      }
+    }
+    // ---- Ls (eq 5.4), stored packed after L, then f
+    lds_chol_upper<D3>(Us, sm.ids);
+    if (fa) {
+      for (int p = t; p < NTRI; p += NT) {
+        int i, j;
+        lower_pair(p, i, j);
+        fa[NTRI + p] = Us[j * D3 + i];
+      }
+    }
+    // ---- B_l = T_l DP_l^T + U_l^T Z_l with U_l = sum_s n_{l s} W_s (eq 5.2), face by face:
+    // U_l and Z_l (its columns padded to ZLD with zeros) staged in LDS, one 4 x 4 tile of
+    // (rows i of the u space, columns of face l) per thread; then the f column
+    for (int l = 0; l < 4; ++l) {
+      __syncthreads();
+      double* Ul = R;
+      double* Zl = R + D3 * D3;
+      const double n0 = sg.n[l][0], n1 = sg.n[l][1], n2 = sg.n[l][2];
+      for (int idx = t; idx < D3 * D3 / 2; idx += NT) {
+        const int r = 2 * idx / D3, i = 2 * idx % D3;
+        const double* xr = X + (size_t)r * NCOL + i;
+        const double2 w0 = *reinterpret_cast<const double2*>(xr);
+        const double2 w1 = *reinterpret_cast<const double2*>(xr + D3);
+        const double2 w2 = *reinterpret_cast<const double2*>(xr + 2 * D3);
+        *reinterpret_cast<double2*>(Ul + r * D3 + i) =
+            make_double2(n0 * w0.x + n1 * w1.x + n2 * w2.x, n0 * w0.y + n1 * w1.y + n2 * w2.y);
+      }
+      for (int idx = t; idx < D3 * ZLD; idx += NT) {
+        const int r = idx / ZLD, c = idx % ZLD;
+        Zl[idx] = c < D2 ? X[(size_t)r * NCOL + 3 * D3 + l * D2 + c] : 0.0;
+      }
+      __syncthreads();
+      if (t < TT * (ZLD / 4)) {
+        const int ti = t / (ZLD / 4), tc = t % (ZLD / 4);
+        double acc[4][4] = {};
 #pragma unroll 4
         for (int r = 0; r < D3; ++r) {
-          const double2 a01 = *reinterpret_cast<const double2*>(xi + (size_t)r * NCOL);
-          const double2 a23 = *reinterpret_cast<const double2*>(xi + (size_t)r * NCOL + 2);
-          const double2 b01 = *reinterpret_cast<const double2*>(xj + (size_t)r * NCOL);
-          const double2 b23 = *reinterpret_cast<const double2*>(xj + (size_t)r * NCOL + 2);
+          const double2 a01 = *reinterpret_cast<const double2*>(Ul + r * D3 + 4 * ti);
+          const double2 a23 = *reinterpret_cast<const double2*>(Ul + r * D3 + 4 * ti + 2);
+          const double2 b01 = *reinterpret_cast<const double2*>(Zl + r * ZLD + 4 * tc);
+          const double2 b23 = *reinterpret_cast<const double2*>(Zl + r * ZLD + 4 * tc + 2);
           const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
 #pragma unroll
           for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
         }
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int i = 4 * ti + a, j = 4 * tj + b;
-          if (i > j) continue;
-          double v = sm.Us[i * D3 + j] + acc[a][b];
+          const int ia = 4 * tc + b;
+          if (ia >= D2) continue;
+          const double* dp = tb.DP + ((size_t)(sg.mu[l] * 4 + l) * D2 + ia) * D3;
 #pragma unroll
-          for (int l = 0; l < 4; ++l) v = fma(sg.T[l], tb.PP[((size_t)l * D3 + i) * D3 + j], v);
-          sm.Us[i * D3 + j] = v;
-        }
-    }
-    // ---- Ls (eq 5.4), stored packed after L, then f
-    lds_chol_upper<D3>(sm.Us, sm.ids);
-    if (fa) {
-#pragma unroll
-      for (int u = 0; u < NPAIR; ++u)
-        if (t + u * NT < NTRI) fa[NTRI + t + u * NT] = sm.Us[pj[u] * D3 + pi[u]];
-    }
-    // ---- B_l = T_l DP_l^T + sum_s n_{l s} W_s^T Z_l (eq 5.2) as 4 x 4 tiles (rows i of the
-    // u space, columns (l, a) of the trace space; a tile may straddle two faces), and f
-    for (int job = t; job < TT * TM; job += NT) {
-      const int ti = job / TM, tc = job % TM;
-      double g[3][4][4] = {};
-      const double* zc = X + 3 * D3 + 4 * tc;
-#pragma unroll 2
-      for (int r = 0; r < D3; ++r) {
-        const double2 z01 = *reinterpret_cast<const double2*>(zc + (size_t)r * NCOL);
-        const double2 z23 = *reinterpret_cast<const double2*>(zc + (size_t)r * NCOL + 2);
-        const double zv[4] = {z01.x, z01.y, z23.x, z23.y};
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-          const double* wr = X + (size_t)r * NCOL + s * D3 + 4 * ti;
-          const double2 w01 = *reinterpret_cast<const double2*>(wr);
-          const double2 w23 = *reinterpret_cast<const double2*>(wr + 2);
-          const double wv[4] = {w01.x, w01.y, w23.x, w23.y};
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) g[s][a][b] = fma(wv[a], zv[b], g[s][a][b]);
-        }
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int col = 4 * tc + b, l = col / D2, ia = col % D2;
-        const double* dp = tb.DP + ((size_t)(sg.mu[l] * 4 + l) * D2 + ia) * D3;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const int i = 4 * ti + a;
-          double v = sg.T[l] * dp[i];
-          v = fma(sg.n[l][0], g[0][a][b], v);
-          v = fma(sg.n[l][1], g[1][a][b], v);
-          v = fma(sg.n[l][2], g[2][a][b], v);
-          Vb[(size_t)i * NV + col] = v;
+          for (int a = 0; a < 4; ++a) {
+            const int i = 4 * ti + a;
+            Vb[(size_t)i * NV + l * D2 + ia] = fma(sg.T[l], dp[i], acc[a][b]);
+          }
         }
       }
     }
@@ -303,67 +419,80 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
       double x[D3];
 #pragma unroll
       for (int r = 0; r < D3; ++r) x[r] = Vb[(size_t)r * NV + c];
-      reg_forward<D3>(sm.Us, sm.ids, x);
+      reg_forward<D3>(Us, sm.ids, x);
 #pragma unroll
       for (int r = 0; r < D3; ++r) Vb[(size_t)r * NV + c] = x[r];
     }
     __syncthreads();
-    // ---- C^K = tauDD + (n_l . n_m) Z_l^T Z_m - V^T V on the upper 4 x 4 tiles, scattered
-    // (eq 6.5: off-diagonal blocks have one writer, diagonal blocks two addends onto zeros)
-    // or exported; then Cf^K = V^T Ls^{-1} f
-    for (int job = t; job < TM * (TM + 1) / 2; job += NT) {
-      int ta, tb2;  // ta <= tb2
-      lower_pair(job, tb2, ta);
-      double az[4][4] = {}, av[4][4] = {};
-      const double* za = X + 3 * D3 + 4 * ta;
-      const double* zb = X + 3 * D3 + 4 * tb2;
-#pragma unroll 2
-      for (int r = 0; r < D3; ++r) {
-        const double2 x01 = *reinterpret_cast<const double2*>(za + (size_t)r * NCOL);
-        const double2 x23 = *reinterpret_cast<const double2*>(za + (size_t)r * NCOL + 2);
-        const double2 y01 = *reinterpret_cast<const double2*>(zb + (size_t)r * NCOL);
-        const double2 y23 = *reinterpret_cast<const double2*>(zb + (size_t)r * NCOL + 2);
-        const double zx[4] = {x01.x, x01.y, x23.x, x23.y}, zy[4] = {y01.x, y01.y, y23.x, y23.y};
-        const double* vr = Vb + (size_t)r * NV;
-        double vx[4], vy[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          vx[a] = vr[4 * ta + a];
-          vy[a] = vr[4 * tb2 + a];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            az[a][b] = fma(zx[a], zy[b], az[a][b]);
-            av[a][b] = fma(vx[a], vy[b], av[a][b]);
-          }
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int ra = 4 * ta + a, cb = 4 * tb2 + b;
-          if (ra > cb) continue;
-          const int la = ra / D2, lb = cb / D2, ia = ra % D2, ib = cb % D2;
-          double v = sm.nn[la][lb] * az[a][b] - av[a][b];
-          if (ra == cb) v += sg.T[la];
-          if (EXPORT) {
-            Cout[((size_t)w * M + ra) * M + cb] = v;
-            Cout[((size_t)w * M + cb) * M + ra] = v;
-          } else {
-            const size_t s1 = sm.slot[4 * la + lb];
-            if (la == lb) {
-              unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], v);
-              if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], v);
-            } else {
-              const size_t s2 = sm.slot[4 * lb + la];
-              H[(s1 * D2 + ia) * D2 + ib] = v;
-              H[(s2 * D2 + ib) * D2 + ia] = v;
+    // ---- C^K = tauDD + (n_l . n_m) Z_l^T Z_m - V^T V (eq 5.6) by face pairs l <= m: Z_l,
+    // Z_m, V_l, V_m staged in LDS (columns padded to ZLD with zeros; the factors are dead),
+    // one 2 x 2 tile per thread; scattered (eq 6.5: off-diagonal blocks have one writer,
+    // diagonal blocks two addends onto zeros) or exported.  Then Cf^K = V^T Ls^{-1} f.
+    for (int l = 0; l < 4; ++l)
+      for (int m = l; m < 4; ++m) {
+        __syncthreads();
+        double* Za = R;
+        double* Zb = R + D3 * ZLD;
+        double* Va = R + 2 * D3 * ZLD;
+        double* Vc = R + 3 * D3 * ZLD;
+        // item e of the four blocks: block e / (D3 ZLD), row, padded column
+        stage_batched<NT>(
+            4 * D3 * ZLD, t,
+            [&](int e) {
+              const int blk = e / (D3 * ZLD), rc = e % (D3 * ZLD), r = rc / ZLD, c = rc % ZLD;
+              const int col = (blk & 1 ? m : l) * D2 + c;
+              const double* src = blk < 2 ? X + (size_t)r * NCOL + 3 * D3 : Vb + (size_t)r * NV;
+              return c < D2 ? src[col] : 0.0;
+            },
+            [&](int e, double v) { R[e] = v; });
+        __syncthreads();
+        constexpr int T2 = ZLD / 2;
+        if (t < T2 * T2) {
+          const int ta = t / T2, tb2 = t % T2;
+          if (l < m || ta <= tb2) {
+            double az[2][2] = {}, av[2][2] = {};
+#pragma unroll 4
+            for (int r = 0; r < D3; ++r) {
+              const double2 za = *reinterpret_cast<const double2*>(Za + r * ZLD + 2 * ta);
+              const double2 zb = *reinterpret_cast<const double2*>(Zb + r * ZLD + 2 * tb2);
+              const double2 va = *reinterpret_cast<const double2*>(Va + r * ZLD + 2 * ta);
+              const double2 vb = *reinterpret_cast<const double2*>(Vc + r * ZLD + 2 * tb2);
+              az[0][0] = fma(za.x, zb.x, az[0][0]);
+              az[0][1] = fma(za.x, zb.y, az[0][1]);
+              az[1][0] = fma(za.y, zb.x, az[1][0]);
+              az[1][1] = fma(za.y, zb.y, az[1][1]);
+              av[0][0] = fma(va.x, vb.x, av[0][0]);
+              av[0][1] = fma(va.x, vb.y, av[0][1]);
+              av[1][0] = fma(va.y, vb.x, av[1][0]);
+              av[1][1] = fma(va.y, vb.y, av[1][1]);
             }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int b = 0; b < 2; ++b) {
+                const int ia = 2 * ta + a, ib = 2 * tb2 + b;
+                if (ia >= D2 || ib >= D2 || (l == m && ia > ib)) continue;
+                const int ra = l * D2 + ia, cb = m * D2 + ib;
+                double v = sm.nn[l][m] * az[a][b] - av[a][b];
+                if (ra == cb) v += sg.T[l];
+                if (EXPORT) {
+                  Cout[((size_t)w * M + ra) * M + cb] = v;
+                  Cout[((size_t)w * M + cb) * M + ra] = v;
+                } else {
+                  const size_t s1 = sm.slot[4 * l + m];
+                  if (l == m) {
+                    unsafeAtomicAdd(&H[(s1 * D2 + ia) * D2 + ib], v);
+                    if (ia != ib) unsafeAtomicAdd(&H[(s1 * D2 + ib) * D2 + ia], v);
+                  } else {
+                    const size_t s2 = sm.slot[4 * m + l];
+                    H[(s1 * D2 + ia) * D2 + ib] = v;
+                    H[(s2 * D2 + ib) * D2 + ia] = v;
+                  }
+                }
+              }
           }
         }
-    }
+      }
     for (int a = t; a < M; a += NT) {
       double v = 0;
       for (int r = 0; r < D3; ++r) v = fma(Vb[(size_t)r * NV + a], Vb[(size_t)r * NV + M], v);
@@ -465,7 +594,10 @@ __global__ void __launch_bounds__(kBigThreads) k_pp_big(hdg_mesh mesh, Tables tb
       rhs[i] = s;
     }
     // S* = U^T U, then U^T y = rhs and U x = y
-    lds_chol_upper<D3P>(S, idg);
+    if constexpr (K == 5)
+      lds_chol_rows<D3P>(S, idg);
+    else
+      lds_chol_upper<D3P>(S, idg);
     for (int k = 0; k < D3P; ++k) {
       const double xk = rhs[k] * idg[k];
       for (int r = k + 1 + t; r < D3P; r += NT) rhs[r] -= S[k * D3P + r] * xk;
