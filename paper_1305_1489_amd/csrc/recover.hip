@@ -1,6 +1,6 @@
 // Reconstruction of (q, u) from the face traces (eq 5.3, Section 6 "Reconstruction"),
-// one wavefront per element, every step spread over the wavefront's lanes.  The local
-// postprocess u* (eq 9.11) runs afterwards in its own kernel (postprocess.hip).
+// one wavefront per element (four at degrees 5 and 6), every step spread over its lanes.
+// The local postprocess u* (eq 9.11) runs afterwards in its own kernel (postprocess.hip).
 //
 // With the factors kept by the condensation (M = M_{1/kappa}, S the u-Schur complement,
 // and f):
@@ -92,8 +92,12 @@ __device__ inline void spd_apply(const double* F, double* X, double* tmp, int nc
     par_chol_solve<N>(F, N, X, ncols);
 }
 
+// Threads per element of the per-element reconstruction: one wavefront, four at degrees 5
+// and 6, whose two d3 x d3 factors in LDS (125 KB at k = 6) leave room for one element per CU.
+constexpr int recover_threads(int k) { return k >= 5 ? 256 : 64; }
+
 template <int K, bool TILE>
-__global__ void __launch_bounds__(64) k_recover(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+__global__ void __launch_bounds__(recover_threads(K)) k_recover(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                 const double* __restrict__ tau, const double* __restrict__ factors,
                                                 const double* __restrict__ uhat, double* __restrict__ qout,
                                                 double* __restrict__ uout) {
@@ -408,7 +412,7 @@ hdg_status run_recover(const hdg_disc* disc, const hdg_mesh* mesh, const double*
   } else {
     const int grid = (int)std::min<int64_t>(mesh->nelt, 1 << 20);
     timer_begin("k_recover", s);
-    k_recover<K, false><<<grid, 64, 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
+    k_recover<K, false><<<grid, recover_threads(K), 0, s>>>(*mesh, disc->dev, kappa, tau, factors, uhat, q, u);
     timer_end("k_recover", s);
   }
   HDG_CHECK_LAUNCH("k_recover");
