@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(kBigThreads) k_pp_big(hdg_mesh mesh, Tables tb
   using P = PPBig<K>;
   constexpr int D3 = P::D3, D3P = P::D3P, NQD = P::NQD, NT = kBigThreads;
   __shared__ double S[D3P * D3P];
-  __shared__ double V[3 * D3], Y[3 * NQD], rhs[D3P], idg[D3P];
+  __shared__ double V[3 * D3], Y[3 * NQD], rhs[D3P], idg[D3P], part[kBigThreads];
   __shared__ ElemGeom g;
   const int t = threadIdx.x;
   for (int E = blockIdx.x; E < mesh.nelt; E += gridDim.x) {
@@ -580,18 +580,29 @@ __global__ void __launch_bounds__(kBigThreads) k_pp_big(hdg_mesh mesh, Tables tb
       Y[2 * NQD + q] = wr * y2;
     }
     __syncthreads();
-    for (int i = t; i < D3P; i += NT) {
-      double s = 0;
-      if (i == 0) {
-        s = uin[(size_t)E * D3];
-      } else {
+    {  // the gradient contraction over the (direction, point) pairs: mode i by two threads
+       // (one half of the points each), four chains per thread
+      static_assert(NT == 256 && D3P <= 128, "two threads per mode");
+      const int i = t & 127, hf = t >> 7;
+      const int q0 = hf ? NQD / 2 : 0, q1 = hf ? NQD : NQD / 2;
+      double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      if (i > 0 && i < D3P) {
         for (int h = 0; h < 3; ++h) {
           const double* gp = tb.P1g + (size_t)h * NQD * D3P + i;
-          for (int q = 0; q < NQD; ++q) s = fma(gp[(size_t)q * D3P], Y[h * NQD + q], s);
+          const double* yh = Y + h * NQD;
+          int q = q0;
+          for (; q + 3 < q1; q += 4) {
+            s0 = fma(gp[(size_t)q * D3P], yh[q], s0);
+            s1 = fma(gp[(size_t)(q + 1) * D3P], yh[q + 1], s1);
+            s2 = fma(gp[(size_t)(q + 2) * D3P], yh[q + 2], s2);
+            s3 = fma(gp[(size_t)(q + 3) * D3P], yh[q + 3], s3);
+          }
+          for (; q < q1; ++q) s0 = fma(gp[(size_t)q * D3P], yh[q], s0);
         }
-        s = -s;
       }
-      rhs[i] = s;
+      part[t] = (s0 + s1) + (s2 + s3);
+      __syncthreads();
+      if (t < D3P) rhs[t] = t == 0 ? uin[(size_t)E * D3] : -(part[t] + part[128 + t]);
     }
     // S* = U^T U, then U^T y = rhs and U x = y
     if constexpr (K == 5)
