@@ -537,9 +537,10 @@ def psweep_metric(reps=10, n=16):
         torch.cuda.synchronize()
         ms = statistics.median(a.elapsed_time(b) for a, b in ts)
         fc, fr, fp = algorithmic_flops(k)
-        per_k[f"k{k}"] = {"ms": ms, "elements_per_s": m.nelt / (ms * 1e-3),
-                          "tflops": (fc + fr + fp) * m.nelt / (ms * 1e-3) / 1e12,
-                          "flops_per_element": fc + fr + fp, "trace_unknowns": S.mesh.nfc * S.disc.d2}
+        tf = (fc + fr + fp) * m.nelt / (ms * 1e-3) / 1e12
+        per_k[f"k{k}"] = {"ms": ms, "elements_per_s": m.nelt / (ms * 1e-3), "tflops": tf,
+                          "frac_fp64_peak": tf / 78.6, "flops_per_element": fc + fr + fp,
+                          "trace_unknowns": S.mesh.nfc * S.disc.d2}
         log(f"p-sweep k={k}: {ms:.3f} ms per step, {m.nelt / (ms * 1e-3) / 1e6:.1f} M elements/s")
     # p-convergence from the GPU pipeline on the small fixed mesh
     from oracle import globalsys as OG, mesh as OM
