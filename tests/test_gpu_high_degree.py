@@ -155,3 +155,34 @@ def test_high_degree_unsupported_forms():
     with pytest.raises(L.HdgError) as e:
         L.hdg_solve_gmres(S.disc, S.mesh, S.H, S.F, S.uhat)
     assert e.value.name == "HDG_ERR_UNSUPPORTED_DEGREE"
+
+
+def test_high_degree_workspace_follows_launch_shape():
+    """The degree-5 workspace is one slice per workgroup of the persistent grid: two workgroups
+    per CU double it, a workspace sized for one is refused before any launch, and every shape
+    gives the same bits."""
+    from paper_1305_1489_amd import _lib as L
+    k = 5
+    m = _mesh(4, 95, jitter=0.1)  # 384 elements: more than one workgroup per CU can hold
+    S = gpu_system(m, k, manufactured_sin_xyz("c1", "c1"))
+    saved = L.hdg_get_launch_config(k)
+    try:
+        L.hdg_set_launch_config(k, 1, 0, 4)
+        n1 = L.hdg_condense_workspace_size(S.disc, S.mesh)
+        ws1 = torch.empty(n1, dtype=torch.uint8, device="cuda")
+        L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors, ws=ws1)
+        torch.cuda.synchronize()
+        H1, F1, X1 = S.H.clone(), S.F.clone(), S.factors.clone()
+        L.hdg_set_launch_config(k, 2, 1, 4)
+        n2 = L.hdg_condense_workspace_size(S.disc, S.mesh)
+        assert n2 > n1  # min(384, 2 x CUs) slices against min(384, CUs)
+        with pytest.raises(L.HdgError) as e:
+            L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors, ws=ws1)
+        assert e.value.name == "HDG_ERR_WORKSPACE"
+        S.H.zero_()
+        S.F.zero_()
+        L.hdg_assemble_condense_ws(S.disc, S.mesh, S.kappa, S.c, S.f, S.tau, S.H, S.F, S.factors)
+        torch.cuda.synchronize()
+        assert torch.equal(S.H, H1) and torch.equal(S.F, F1) and torch.equal(S.factors, X1)
+    finally:
+        L.hdg_set_launch_config(k, saved["workgroups_per_cu"], saved["xcd_remap"], saved["waves_per_element"])
