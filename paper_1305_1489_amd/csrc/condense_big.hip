@@ -28,6 +28,10 @@ namespace hdg {
 namespace {
 
 constexpr int kBigThreads = 256;
+// Threads of the condensation workgroup: six wavefronts at k = 6, so that the 364
+// right-hand sides of the first triangular solve take one round (one per thread), four at
+// k = 5 (252 of them).
+constexpr int cond_threads(int k) { return k == 6 ? 384 : 256; }
 
 template <int K>
 struct BigDims {
@@ -179,7 +183,7 @@ __device__ inline void lds_chol_upper(double* A, double* idg) {
 }
 
 template <int K, bool EXPORT>
-__global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
+__global__ void __launch_bounds__(cond_threads(K)) k_condense_big(hdg_mesh mesh, Tables tb, const double* __restrict__ kappa,
                                                               const double* __restrict__ cco,
                                                               const double* __restrict__ fco,
                                                               const double* __restrict__ tau, double* __restrict__ H,
@@ -189,7 +193,7 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
                                                               double* __restrict__ ws, int xcd_remap) {
   using B = BigDims<K>;
   constexpr int D3 = B::D3, D2 = B::D2, M = B::M, NQD = B::NQD, NCOL = B::NCOL, NV = B::NV, QC = B::QC;
-  constexpr int NTRI = B::NTRI, NT = kBigThreads;
+  constexpr int NTRI = B::NTRI, NT = cond_threads(K);
   constexpr int TT = D3 / 4, ZLD = BigSmem<K>::ZLD, NQDP = BigSmem<K>::NQDP;
   static_assert(TT * (TT + 1) / 2 <= NT && TT * (ZLD / 4) <= NT && (ZLD / 2) * (ZLD / 2) <= NT,
                 "one product tile per thread");
@@ -228,8 +232,8 @@ __global__ void __launch_bounds__(kBigThreads) k_condense_big(hdg_mesh mesh, Tab
       sm.nn[l][m] = sg.n[l][0] * sg.n[m][0] + sg.n[l][1] * sg.n[m][1] + sg.n[l][2] * sg.n[m][2];
     }
     // ---- M = P^T diag(|K| w / kappa) P, Mc = P^T diag(|K| w c) P, f = P^T (|K| w f) (eq 3.5,
-    // eq 4.5), the basis table streamed through LDS in chunks of QC points
-    // one upper 4 x 4 tile (gi <= gj) of both matrices per thread
+    // eq 4.5), the basis table streamed through LDS in chunks of QC points, one upper 4 x 4
+    // tile (gi <= gj) of both matrices per thread
     const bool gjob = t < TT * (TT + 1) / 2;
     int gi = 0, gj = 0;
     if (gjob) lower_pair(t, gj, gi);
@@ -653,11 +657,11 @@ hdg_status run_condense_big(const hdg_disc* disc, const hdg_mesh* mesh, const do
   if (n == 0) return HDG_OK;
   const int rm = launch_config(K).xcd_remap;
   if (Cout) {
-    k_condense_big<K, true><<<grid, kBigThreads, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, nullptr, nullptr,
+    k_condense_big<K, true><<<grid, cond_threads(K), 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, nullptr, nullptr,
                                                           nullptr, elems, (int)n, Cout, Cfout, ws, rm);
   } else {
     timer_begin("k_condense", s);
-    k_condense_big<K, false><<<grid, kBigThreads, 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors,
+    k_condense_big<K, false><<<grid, cond_threads(K), 0, s>>>(*mesh, disc->dev, kappa, c, f, tau, H, F, factors,
                                                            nullptr, (int)n, nullptr, nullptr, ws, rm);
     timer_end("k_condense", s);
   }
