@@ -13,8 +13,8 @@
 // (149 KB at k = 6, 74 KB at k = 5), and the solved blocks in its own slice of a caller
 // workspace (global memory, resident in the L2 and last-level caches while the element is
 // worked on).  Phases:
-//   Gram sums: the basis table streamed through LDS in chunks of points, one upper 4 x 4
-//     tile of M and Mc per thread;
+//   Gram sums: the basis table streamed through LDS in chunks of points, one tile of M and
+//     Mc per thread over the upper triangle (2 x 4 at k = 5, 4 x 4 at k = 6);
 //   factorisations: the leading 64 rows by one wavefront with its rows in registers, the
 //     rest (k = 6) by a block step (U12 = L11^{-1} A12, A22 -= U12^T U12, factor A22);
 //   triangular solves: one right-hand side per thread in registers;
@@ -195,6 +195,9 @@ __global__ void __launch_bounds__(cond_threads(K)) k_condense_big(hdg_mesh mesh,
   constexpr int D3 = B::D3, D2 = B::D2, M = B::M, NQD = B::NQD, NCOL = B::NCOL, NV = B::NV, QC = B::QC;
   constexpr int NTRI = B::NTRI, NT = cond_threads(K);
   constexpr int TT = D3 / 4, ZLD = BigSmem<K>::ZLD, NQDP = BigSmem<K>::NQDP;
+  constexpr int GRAM_ROWS = K == 5 ? 2 : 4;
+  constexpr int GJOBS = GRAM_ROWS == 4 ? TT * (TT + 1) / 2 : TT * (TT + 1);
+  static_assert(GJOBS <= NT, "one Gram tile per thread");
   static_assert(TT * (TT + 1) / 2 <= NT && TT * (ZLD / 4) <= NT && (ZLD / 2) * (ZLD / 2) <= NT,
                 "one product tile per thread");
   __shared__ __align__(16) BigSmem<K> sm;
@@ -232,12 +235,23 @@ __global__ void __launch_bounds__(cond_threads(K)) k_condense_big(hdg_mesh mesh,
       sm.nn[l][m] = sg.n[l][0] * sg.n[m][0] + sg.n[l][1] * sg.n[m][1] + sg.n[l][2] * sg.n[m][2];
     }
     // ---- M = P^T diag(|K| w / kappa) P, Mc = P^T diag(|K| w c) P, f = P^T (|K| w f) (eq 3.5,
-    // eq 4.5), the basis table streamed through LDS in chunks of QC points, one upper 4 x 4
-    // tile (gi <= gj) of both matrices per thread
-    const bool gjob = t < TT * (TT + 1) / 2;
+    // eq 4.5), the basis table streamed through LDS in chunks of QC points, one GR x 4 tile
+    // of both matrices per thread over the upper triangle: rows GR gi .. GR gi + GR - 1,
+    // columns 4 gj .. 4 gj + 3 (GR = 2 at k = 5, so that 210 threads share the work, 4 at k = 6)
+    constexpr int GR = GRAM_ROWS;
+    const bool gjob = t < GJOBS;
     int gi = 0, gj = 0;
-    if (gjob) lower_pair(t, gj, gi);
-    double am[4][4] = {}, ac[4][4] = {}, ff = 0;
+    if (gjob) {
+      if constexpr (GR == 4) {
+        lower_pair(t, gj, gi);
+      } else {  // column tile gj holds 2 gj + 2 row pairs: job p = gj (gj + 1) + gi
+        gj = (int)((sqrtf(4.0f * t + 1.0f) - 1.0f) * 0.5f);
+        while (gj * (gj + 1) > t) --gj;
+        while ((gj + 1) * (gj + 2) <= t) ++gj;
+        gi = t - gj * (gj + 1);
+      }
+    }
+    double am[GR][4] = {}, ac[GR][4] = {}, ff = 0;
     for (int q0 = 0; q0 < NQD; q0 += QC) {
       const int nq = min(QC, NQD - q0);
       __syncthreads();
@@ -247,14 +261,19 @@ __global__ void __launch_bounds__(cond_threads(K)) k_condense_big(hdg_mesh mesh,
       if (gjob) {
         for (int q = 0; q < nq; ++q) {
           const double* pq = Pc + q * D3;
-          const double2 a01 = *reinterpret_cast<const double2*>(pq + 4 * gi);
-          const double2 a23 = *reinterpret_cast<const double2*>(pq + 4 * gi + 2);
+          double av[GR];
+#pragma unroll
+          for (int a = 0; a < GR; a += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(pq + GR * gi + a);
+            av[a] = v.x;
+            av[a + 1] = v.y;
+          }
           const double2 b01 = *reinterpret_cast<const double2*>(pq + 4 * gj);
           const double2 b23 = *reinterpret_cast<const double2*>(pq + 4 * gj + 2);
-          const double av[4] = {a01.x, a01.y, a23.x, a23.y}, bv[4] = {b01.x, b01.y, b23.x, b23.y};
+          const double bv[4] = {b01.x, b01.y, b23.x, b23.y};
           const double wkq = wk[q0 + q], wcq = wc[q0 + q];
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
+          for (int a = 0; a < GR; ++a) {
             const double ka = wkq * av[a], ca = wcq * av[a];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -269,10 +288,10 @@ __global__ void __launch_bounds__(cond_threads(K)) k_condense_big(hdg_mesh mesh,
     }
     if (gjob) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int a = 0; a < GR; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int i = 4 * gi + a, j = 4 * gj + b;
+          const int i = GR * gi + a, j = 4 * gj + b;
           if (i <= j) {
             U[i * D3 + j] = am[a][b];
             Us[i * D3 + j] = ac[a][b];
