@@ -56,7 +56,8 @@ hdg_status hdg_set_kernel_timer(const char* kernel, void* ev_start, void* ev_sto
 
 // Launch shapes of the single-mesh condensation, per degree (persistent grids; the tile
 // kernels of k = 1..3 run four elements per wavefront, so waves_per_element is 1).
-// Degrees 5 and 6 use workgroups_per_cu and xcd_remap only (four wavefronts per element).
+// Degrees 5 and 6 use workgroups_per_cu and xcd_remap only (four wavefronts per element at
+// k = 5, six at k = 6).
 static hdg_tile_config g_launch[kMaxDegree + 1] = {{2, 0, 1}, {4, 1, 1}, {4, 1, 1}, {4, 1, 1}, {2, 1, 4},
                                                    {1, 0, 4}, {1, 0, 4}};
 
